@@ -1,0 +1,241 @@
+/*
+ * ofm.h -- C ABI of the overlapping-fragments-method (OFM) library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method (Vukmirovic & Wang, "Overlapping fragments method for electronic
+ * structure calculation of large systems", Sec. II) represents the
+ * single-particle Hamiltonian H = -1/2 Laplacian + V (Eq. 1) in the basis of
+ * the lowest eigenstates of many mutually overlapping fragments.  The library
+ * computes, on one GPU:
+ *
+ *   1. ofm_build_fragments  -- fragment boxes, the pair list and the potential
+ *                              restricted to every box;
+ *   2. ofm_solve_fragments  -- the lowest s_j eigenpairs of every fragment
+ *                              Hamiltonian (one batched eigensolver for all
+ *                              fragments) and H|phi> with the whole-system H
+ *                              (Sec. II: "H of the whole system, not just the
+ *                              fragment");
+ *   3. ofm_matrix_elements  -- H_{ij,mn} = <phi_i^(j)|H|phi_m^(n)> and
+ *                              S_{ij,mn} = <phi_i^(j)|phi_m^(n)> for every
+ *                              overlapping pair (Sec. II);
+ *   4. ofm_solve_global     -- the generalised eigenproblem
+ *                              sum_mn (H - E S) C = 0 (Eq. 2).
+ *
+ * Discretisation (the paper's plane-wave basis is replaced by a real-space
+ * grid): uniform spacing h, x-fastest point order (index = x + nx*(y +
+ * ny*z)), 4th-order central second difference, Dirichlet walls one spacing
+ * outside every box (global grid and fragments alike) with odd-image second
+ * ghosts.  Inner products are plain l2 sums over grid points; every returned
+ * state has sum phi^2 = 1.  Units are Hartree atomic units.
+ *
+ * Conventions for every call:
+ *  - Return value is an ofm_status; nothing else crosses the ABI (no C++
+ *    exceptions, no abort).  On error, ofm_last_error(ctx) returns a message.
+ *  - Buffers named "host" are caller-owned host memory; the library copies
+ *    from / to them before returning.  Buffers named "host or device" may be
+ *    either; device pointers are borrowed only for the duration of the call.
+ *  - The library owns ofm_ctx / ofm_frags / ofm_mats handles; free them with
+ *    the matching *_destroy call.  Sizes for output buffers come from
+ *    ofm_frags_info / ofm_fragment_geometry (two-call pattern).
+ *  - All device work is enqueued on the context stream; every call that
+ *    returns results on the host synchronises that stream first.  A context
+ *    and the handles made with it must be used by one host thread at a time.
+ *  - The precision form is fixed when the context is created.
+ */
+#ifndef OFM_H
+#define OFM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OFM_OK = 0,
+  OFM_E_INVALID = -1,   /* bad argument: NaN/Inf in V, box outside the grid,
+                           s_j > n_j, NULL where a buffer is required, ...   */
+  OFM_E_NOMEM = -2,     /* device or host allocation failed                  */
+  OFM_E_DEVICE = -3,    /* a HIP / rocSOLVER / rocBLAS call failed           */
+  OFM_E_NOCONV = -4,    /* eigensolver hit max_iter; results are returned and
+                           the per-fragment converged flags say which        */
+  OFM_E_SINGULAR = -5,  /* every eigenvalue of S is below the threshold      */
+  OFM_E_STATE = -6      /* call out of order (e.g. elements before states)   */
+} ofm_status;
+
+typedef enum {
+  OFM_FP64 = 0,          /* all vector arithmetic and products in FP64       */
+  OFM_MIXED_BF16X3 = 1   /* vectors and stencil in FP32; subspace and element
+                            contractions as 3-term split-BF16 MFMA products
+                            with FP32 accumulation and FP64 cross-tile sums;
+                            Cholesky, small eigensolves and the global solve
+                            in FP64                                          */
+} ofm_precision;
+
+/* Global grid: point (ix,iy,iz) at origin + (ix,iy,iz)*h (bohr). */
+typedef struct {
+  int nx, ny, nz;
+  double h;
+  double origin[3];
+} ofm_grid;
+
+/* One fragment: a cuboid box of grid points [lo, lo+dims) in global indices
+   (x, y, z order) and the number of its lowest states kept in the basis. */
+typedef struct {
+  int lo[3];
+  int dims[3];
+  int n_states;
+} ofm_fragment_desc;
+
+/* Eigensolver options.  Fields set to 0 take the default in brackets. */
+typedef struct {
+  double tol;            /* residual bound ||H_j phi - eps phi||_2 per wanted
+                            state [1e-10 FP64, 2e-5 mixed]                   */
+  int max_iter;          /* outer (filter + Rayleigh-Ritz) iterations [60]   */
+  int guard;             /* extra block vectors beyond s_j [8]               */
+  int degree;            /* Chebyshev filter degree per iteration [32]       */
+  unsigned long long seed; /* start-vector seed [0]                          */
+  int use_graph;         /* 1: replay each iteration as a HIP graph [1]      */
+  int autotune;          /* 1: time tile variants once per shape class [0]   */
+} ofm_solve_opts;
+
+typedef struct ofm_ctx ofm_ctx;
+typedef struct ofm_frags ofm_frags;
+typedef struct ofm_mats ofm_mats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+   enqueue on (borrowed, must outlive the context) or NULL for a stream owned
+   by the context. */
+ofm_status ofm_create(ofm_ctx** ctx, int device, void* hip_stream,
+                      ofm_precision precision);
+ofm_status ofm_destroy(ofm_ctx* ctx);
+/* Message for the last failed call on ctx (owned by ctx; "" if none).
+   ctx may be NULL for errors of ofm_create itself. */
+const char* ofm_last_error(const ofm_ctx* ctx);
+/* Library version string (static storage). */
+const char* ofm_version(void);
+
+/* ---- fragments (Sec. II: fragments are boxes; Sec. III-C: pair set) ---- */
+
+/* Set up fragments on the grid.
+   V        : potential, nx*ny*nz doubles, x fastest (host or device).
+   frags    : n_frag descriptors (host).
+   atom_xyz, frag_atom_ptr, frag_atom_idx: optional atom positions (3*n_atoms
+              doubles, bohr) and CSR lists of each fragment's atoms (host);
+              only used when d_cut > 0.
+   d_cut    : <= 0 selects the exact pair set of the stencil: {j,n} is a pair
+              iff box_j grown by the stencil reach (2 points) meets box_n, and
+              every dropped block is exactly zero.  > 0 additionally drops
+              pairs whose closest atoms are >= d_cut apart (Sec. III-C).
+   Errors: OFM_E_INVALID for a box outside the grid, dims < 1, n_states < 1
+   or > box points, non-finite V or h <= 0. */
+ofm_status ofm_build_fragments(ofm_ctx* ctx, const ofm_grid* grid,
+                               const double* V, int n_frag,
+                               const ofm_fragment_desc* frags,
+                               const double* atom_xyz,
+                               const long long* frag_atom_ptr,
+                               const int* frag_atom_idx, double d_cut,
+                               ofm_frags** out);
+ofm_status ofm_frags_destroy(ofm_frags* f);
+/* Sizes: basis size sum_j s_j, number of stored blocks (pairs j<=n,
+   diagonal included) and sum_j n_j.  Any pointer may be NULL. */
+ofm_status ofm_frags_info(const ofm_frags* f, long long* n_basis,
+                          long long* n_pairs, long long* total_points);
+/* Geometry of fragment j: its box, its dilated box (box grown by 2 points per
+   side, clipped to the grid: the support of H|phi>), and s_j.  Any output
+   pointer may be NULL. */
+ofm_status ofm_fragment_geometry(const ofm_frags* f, int j, int lo[3],
+                                 int dims[3], int dlo[3], int ddims[3],
+                                 int* n_states);
+/* The pair list (j <= n) in storage order, and the offset of each block in
+   the packed block arrays (block p is s_j x s_n row-major at block_off[p]).
+   Arrays sized n_pairs (host). */
+ofm_status ofm_pairs(const ofm_frags* f, int* pair_j, int* pair_n,
+                     long long* block_off);
+
+/* ---- fragment eigenstates (Sec. II, Sec. III-B) ------------------------- */
+
+/* Lowest s_j eigenpairs of every fragment Hamiltonian H_j (V restricted to
+   box j, walls at the box faces), all fragments in one batched solver, then
+   H|phi> with the whole-system H on every dilated box.
+   eps       : sum_j s_j doubles, fragment by fragment (host, may be NULL).
+   iters     : n_frag ints, outer iterations used (host, may be NULL).
+   converged : n_frag bytes, 1 if every wanted residual <= tol (host, may be
+               NULL).
+   Returns OFM_E_NOCONV (results still valid) if any fragment missed tol. */
+ofm_status ofm_solve_fragments(ofm_ctx* ctx, ofm_frags* f,
+                               const ofm_solve_opts* opts, double* eps,
+                               int* iters, unsigned char* converged);
+/* States of fragment j: phi is s_j*n_j doubles, state-major (state i at
+   phi + i*n_j, points x fastest); eps is s_j doubles.  Host.  Sign gauge:
+   the largest-|.| component of every state is positive (first on ties). */
+ofm_status ofm_get_states(const ofm_frags* f, int j, double* phi, double* eps);
+/* Import states for fragment j (same layout; host), e.g. to evaluate matrix
+   elements for externally computed states or to resume.  The whole-system
+   H|phi> is recomputed for j.  Rows are used as given (no orthonormalisation).
+ */
+ofm_status ofm_set_states(ofm_frags* f, int j, const double* phi,
+                          const double* eps);
+/* H|phi> of fragment j with the whole-system H on its dilated box: s_j *
+   (ddims product) doubles, state-major, x fastest (host). */
+ofm_status ofm_get_hphi(const ofm_frags* f, int j, double* hphi);
+/* Apply the fragment Hamiltonian H_j to nvec vectors of box j (state-major,
+   host in and out): the stencil of the eigensolver, exposed for checking. */
+ofm_status ofm_apply_fragment_h(ofm_ctx* ctx, ofm_frags* f, int j, int nvec,
+                                const double* x, double* y);
+
+/* ---- matrix elements (Sec. II) ------------------------------------------ */
+
+/* H and S blocks for every pair j <= n: S_jn = Phi_j^T Phi_n over box_j ^
+   box_n, H_jn = Phi_j^T (H Phi_n) over box_j ^ dil(box_n); diagonal blocks
+   are symmetrised.  One grouped launch for all pairs.  Requires states
+   (ofm_solve_fragments or ofm_set_states for every fragment). */
+ofm_status ofm_matrix_elements(ofm_ctx* ctx, ofm_frags* f, ofm_mats** out);
+/* Number of stored doubles per matrix (sum over pairs of s_j*s_n). */
+ofm_status ofm_mats_info(const ofm_mats* m, long long* n_values);
+/* Copy the packed blocks (layout of ofm_pairs) to host buffers of
+   n_values doubles each; either pointer may be NULL. */
+ofm_status ofm_mats_copy(const ofm_mats* m, double* H_blocks,
+                         double* S_blocks);
+ofm_status ofm_mats_destroy(ofm_mats* m);
+
+/* ---- generalised eigenproblem (Eq. 2) ----------------------------------- */
+
+/* Solve sum_mn (H - E S) C = 0 in the fragment basis, FP64 on the GPU:
+   S = U diag(s) U^T; directions with s < s_thresh are dropped; X =
+   U_K diag(s_K^-1/2); eigenpairs of X^T H X.  Eigenvalues in [e_lo, e_hi]
+   are returned ascending.
+   n_kept : |K| (host, may be NULL).   n_eig : number written to E (host).
+   E      : capacity n_basis doubles (host).
+   C      : optional, n_basis * n_eig doubles, column k (stride n_basis) the
+            coefficients of eigenvalue k (host, may be NULL).
+   s_min  : smallest kept eigenvalue of S (host, may be NULL).
+   Returns OFM_E_SINGULAR if no eigenvalue of S reaches s_thresh. */
+ofm_status ofm_solve_global(ofm_ctx* ctx, const ofm_mats* m, double s_thresh,
+                            double e_lo, double e_hi, int* n_kept, int* n_eig,
+                            double* E, double* C, double* s_min);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Turn per-launch HIP-event timing of the library's kernels on or off.  When
+   on, the library records an event pair around each launch of the timed
+   kernels on the context stream. */
+ofm_status ofm_set_profiling(ofm_ctx* ctx, int on);
+/* Accumulated timing of one kernel family since the last reset: "stencil"
+   (fragment-Hamiltonian filter steps), "gram" (subspace contractions),
+   "elements" (pair contractions), "rotate", "small".  total_ms is the sum of
+   launch durations, alg_bytes the algorithmic HBM bytes of those launches
+   (inputs read once, outputs written once), flops their useful flops. */
+ofm_status ofm_kernel_stats(ofm_ctx* ctx, const char* family,
+                            long long* launches, double* total_ms,
+                            double* alg_bytes, double* flops);
+ofm_status ofm_reset_stats(ofm_ctx* ctx);
+/* Wall time (ms, host clock around the call) of the last solve_fragments,
+   matrix_elements and solve_global calls. */
+ofm_status ofm_stage_times(const ofm_ctx* ctx, double* solve_ms,
+                           double* elements_ms, double* global_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OFM_H */
