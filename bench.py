@@ -1,0 +1,224 @@
+"""Benchmark of the OFM hot path on one MI355X.
+
+One step = the whole path over one synthetic system with the potential
+already resident in HBM: fragment setup (boxes, pair list, V per box),
+batched fragment eigensolve + whole-system H|phi>, grouped pair matrix
+elements, and the thresholded generalised eigenproblem.
+
+Prints ONE JSON line.  `value` is fragment eigenstates delivered per second
+by the whole step (sum_j s_j / step time); the per-stage rates (fragment
+eigenstates/s of the eigensolver stage, H,S elements/s of the element stage),
+the roofline of the dominant kernel (the fragment-Hamiltonian stencil of the
+Chebyshev filter) and the CPU oracle's rate on a bounded sample ride along.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config alkane]
+                  [--precision fp64|mixed] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP64_PEAK_TFS = 78.6         # MI355X FP64 (vector and matrix), TFLOP/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="alkane")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--window", type=float, default=0.3,
+                    help="energy window above the lowest OFM eigenvalue (Ha)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8,
+                    help="fragments in the oracle's timed sample")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="run a device copy of this size first (counter "
+                         "calibration for rocprofv3 --pmc runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(system, n_sample, seed):
+    """The CPU oracle, as it stands, on a seeded sample of fragments of the
+    same workload: their eigenpairs, whole-system H|phi> and the pair blocks
+    among them.  Rate in fragment eigenstates/s."""
+    import numpy as np
+
+    import oracle as O
+    rng = np.random.default_rng(seed + 1234)
+    nf = system.n_frag
+    pick = sorted(rng.choice(nf, size=min(n_sample, nf), replace=False).tolist())
+    V = system.potential()
+    t0 = time.perf_counter()
+    r = O.run(V, system.grid.h, system.frag_lo, system.frag_dims,
+              system.frag_states, fragments=pick, solve=False)
+    t = time.perf_counter() - t0
+    n_states = int(sum(int(system.frag_states[j]) for j in pick))
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {"value": n_states / t, "unit": "fragment eigenstates/s",
+            "cores": int(cores), "kind": "oracle",
+            "sample": (f"{len(pick)} of {nf} fragments (seeded), their "
+                       f"eigenpairs + whole-system H|phi> + {len(r.pairs)} "
+                       f"pair blocks among them; {t:.1f} s")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the "
+              "multi-GPU sharding of this path is a design note, not a "
+              "measured configuration", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1011_4764_amd as P
+    from ofm_inputs import make_system
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating", args.config, "seed", args.seed)
+    system = make_system(args.config, seed=args.seed)
+    V = system.potential()
+    g = system.grid
+    n_states = system.n_basis
+    log(f"grid {g.nx}x{g.ny}x{g.nz}, {system.n_frag} fragments, "
+        f"{n_states} states")
+
+    if args.calibrate_copy_gib > 0:
+        n = int(args.calibrate_copy_gib * (1 << 30) // 4)
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 4} bytes read, {n * 4} bytes written")
+        del a, b
+
+    stream = torch.cuda.current_stream(dev)
+    prec = P.OFM_FP64 if args.precision == "fp64" else P.OFM_MIXED_BF16X3
+    ctx = P.ofm_create(0, stream.cuda_stream, prec)
+    V_dev = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
+    torch.cuda.synchronize()
+
+    last = {}
+
+    def step():
+        f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V_dev,
+                                  system.frag_lo, system.frag_dims,
+                                  system.frag_states, origin=g.origin)
+        st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+        m = P.ofm_matrix_elements(ctx, f)
+        gs = P.ofm_solve_global(ctx, m, 1e-6)
+        E = gs["E"]
+        win = E[E <= E[0] + args.window]
+        last.update(status=st, iters=it, conv=cv, n_pairs=f.n_pairs,
+                    n_values=m.n_values, window=win, n_kept=gs["n_kept"],
+                    stages=ctx.stage_times())
+        m.close()
+        f.close()
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        log(f"warmup {w}: {time.perf_counter() - t:.3f} s, status "
+            f"{last['status']}, iters max {int(last['iters'].max())}")
+    ctx.reset_stats()
+    ctx.set_profiling(True)
+    stage_sum = {"solve_ms": 0.0, "elements_ms": 0.0, "global_ms": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        for key in stage_sum:
+            stage_sum[key] += last["stages"][key]
+        log(f"step {k} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_profiling(False)
+    ms_step = 1000.0 * elapsed / args.steps
+    st = ctx.kernel_stats("stencil")
+    el = ctx.kernel_stats("elements")
+    gr = ctx.kernel_stats("gram")
+    avg_ms = st["ms"] / max(st["launches"], 1)
+    bytes_launch = st["bytes"] / max(st["launches"], 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    solve_ms = stage_sum["solve_ms"] / args.steps
+    elem_ms = stage_sum["elements_ms"] / args.steps
+    glob_ms = stage_sum["global_ms"] / args.steps
+    n_elem = 2 * last["n_values"]
+    out = {
+        "metric": "fragment eigenstates/s + H,S elements/s; mixed vs FP64 at 1e-5 Ha",
+        "value": n_states / (ms_step * 1e-3),
+        "unit": "fragment eigenstates/s (whole step)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+bf16x3",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config} seed {args.seed}: "
+                               f"{len(system.atoms)} atoms, grid "
+                               f"{g.nx}x{g.ny}x{g.nz} (h={g.h}), "
+                               f"{system.n_frag} fragments, "
+                               f"{n_states} states, {last['n_pairs']} pairs",
+                   "precision": args.precision},
+        "stages": {
+            "fragment_eigenstates_per_s": n_states / (solve_ms * 1e-3),
+            "solve_ms": solve_ms,
+            "hs_elements_per_s": n_elem / (elem_ms * 1e-3),
+            "elements_ms": elem_ms,
+            "global_ms": glob_ms,
+            "outer_iterations_max": int(last["iters"].max()),
+            "outer_iterations_mean": float(last["iters"].mean()),
+            "all_converged": bool(last["conv"].all()),
+            "window_eigenvalues": int(len(last["window"])),
+            "basis_kept": int(last["n_kept"]),
+        },
+        "roofline": {
+            "kernel": "k_apply_h (Chebyshev filter step of H_j)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": st["launches"], "avg_launch_ms": avg_ms,
+            "alg_bytes_per_launch": bytes_launch,
+        },
+        "other_kernels": {
+            "gram": {"launches": gr["launches"],
+                     "avg_ms": gr["ms"] / max(gr["launches"], 1),
+                     "GBps": (gr["bytes"] / gr["ms"] / 1e6) if gr["ms"] else 0,
+                     "TFLOPs": (gr["flops"] / gr["ms"] / 1e9) if gr["ms"] else 0},
+            "elements": {"launches": el["launches"],
+                         "avg_ms": el["ms"] / max(el["launches"], 1),
+                         "TFLOPs": (el["flops"] / el["ms"] / 1e9) if el["ms"] else 0,
+                         "frac_fp64_peak": ((el["flops"] / el["ms"] / 1e9)
+                                            / FP64_PEAK_TFS) if el["ms"] else 0},
+        },
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(system, args.cpu_sample, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,8 @@ typedef struct ofm_mats ofm_mats;
    by the context. */
 ofm_status ofm_create(ofm_ctx** ctx, int device, void* hip_stream,
                       ofm_precision precision);
+/* Returns OFM_E_STATE (and destroys nothing) while fragment or matrix
+   handles made with ctx are still alive. */
 ofm_status ofm_destroy(ofm_ctx* ctx);
 /* Message for the last failed call on ctx (owned by ctx; "" if none).
    ctx may be NULL for errors of ofm_create itself. */

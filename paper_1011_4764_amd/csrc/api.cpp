@@ -1,0 +1,825 @@
+// C ABI of the OFM library: argument checking, device arenas and the host
+// loop of the batched fragment eigensolver.
+//
+// Fragment eigensolver (method Sec. II: every fragment Hamiltonian is
+// diagonalised for its lowest states; Sec. III-B: the lowest s_j states form
+// the basis).  All fragments advance together through one batched
+// Chebyshev-filtered block subspace iteration:
+//   X <- p_d(H_j) X          (degree-d scaled Chebyshev filter damping
+//                             [theta_b, lambda_max], every fragment at once)
+//   X <- X R^-1  (twice)     (CholQR2, FP64 Cholesky of the Gram matrix)
+//   HX <- H_j X; G = X^T HX; G = Y Theta Y^T  (Rayleigh-Ritz, FP64 Jacobi)
+//   X <- X Y, HX <- HX Y, r_i = ||HX_i - theta_i X_i||
+// until every wanted residual is below tol; a converged fragment drops out
+// of all later launches.  The Chebyshev filter plays the role of the
+// preconditioner of a block-Davidson correction step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+#include "ofm_internal.h"
+
+using namespace ofm;
+
+namespace {
+
+const char* kVersion = "ofm-mi355x 0.1 (gfx950)";
+thread_local std::string g_create_err;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+void set_err(ofm_ctx* c, const std::string& m) {
+  if (c)
+    c->err = m;
+  else
+    g_create_err = m;
+}
+
+template <typename F>
+ofm_status guarded(ofm_ctx* c, F&& fn) {
+  try {
+    if (c) c->err.clear();
+    return fn();
+  } catch (const Error& e) {
+    set_err(c, e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_err(c, "host allocation failed");
+    return OFM_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_err(c, e.what());
+    return OFM_E_INVALID;
+  }
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+void use_device(ofm_ctx* c) { OFM_HIP(hipSetDevice(c->device)); }
+
+size_t wsize(const ofm_ctx* c) { return c->precision == OFM_FP64 ? 8 : 4; }
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// timing brackets
+// --------------------------------------------------------------------------
+namespace ofm {
+Timed::Timed(ofm_ctx* ctx, const char* family, double by, double fl)
+    : c(ctx), fam(family), bytes(by), flops(fl) {
+  if (!c || !c->profiling) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    a = b = nullptr;
+    return;
+  }
+  (void)hipEventRecord(a, c->stream);
+}
+Timed::~Timed() {
+  if (!a) return;
+  (void)hipEventRecord(b, c->stream);
+  c->pending.push_back({fam, a, b, bytes, flops});
+}
+void collect_stats(ofm_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto& s = c->stats[p.fam];
+      s.launches += 1;
+      s.ms += ms;
+      s.bytes += p.bytes;
+      s.flops += p.flops;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c->pending.clear();
+}
+}  // namespace ofm
+
+// --------------------------------------------------------------------------
+// V statistics per box: max (filter bound) and finiteness
+// --------------------------------------------------------------------------
+namespace {
+
+__global__ void k_vstats(FragDev* F, int nf, const double* __restrict__ Vj,
+                         int* bad) {
+  const int j = blockIdx.x;
+  if (j >= nf) return;
+  const FragDev& fr = F[j];
+  double m = -INFINITY;
+  int b = 0;
+  for (int p = threadIdx.x; p < fr.npts; p += 256) {
+    const double v = Vj[fr.v_off + p];
+    if (!isfinite(v)) b = 1;
+    m = fmax(m, v);
+  }
+  __shared__ double sm[256];
+  __shared__ int sb;
+  if (threadIdx.x == 0) sb = 0;
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  if (b) atomicOr(&sb, 1);
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    F[j].vmax = sm[0];
+    if (sb) atomicOr(bad, 1);
+  }
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+T* arena(void* p) {
+  return static_cast<T*>(p);
+}
+
+void free_frags(ofm_frags* f) {
+  void* ptrs[] = {f->d_frag, f->d_v, f->d_v32, f->d_x, f->d_p, f->d_hx,
+                  f->d_hphi, f->d_tiles, f->d_stiles, f->d_rtiles, f->d_G,
+                  f->d_Q, f->d_theta, f->d_res, f->d_res_partial, f->d_fs,
+                  f->d_active, f->d_iters, f->d_conv, f->d_flags,
+                  f->d_nactive};
+  for (void* p : ptrs) dev_free(p);
+}
+
+// ---------------------------------------------------------------------------
+// the batched eigensolver
+// ---------------------------------------------------------------------------
+struct SolveCfg {
+  double tol;
+  int max_iter, degree;
+  unsigned long long seed;
+};
+
+template <typename T>
+ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
+                      double* eps, int* iters, unsigned char* converged) {
+  hipStream_t s = c->stream;
+  const int nf = f->n_frag;
+  T* X = arena<T>(f->d_x);
+  T* P = arena<T>(f->d_p);
+  T* HX = arena<T>(f->d_hx);
+  const double w = sizeof(T);
+  OFM_HIP(hipMemsetAsync(f->d_iters, 0, sizeof(int) * nf, s));
+  OFM_HIP(hipMemsetAsync(f->d_conv, 0, nf, s));
+  OFM_HIP(hipMemsetAsync(f->d_flags, 0, sizeof(int) * nf, s));
+  hipLaunchKernelGGL(k_fill_int, dim3((nf + 255) / 256), dim3(256), 0, s,
+                     f->d_active, nf, 1);
+  OFM_HIP(hipGetLastError());
+  k::init_random<T>(s, f, X, cfg.seed);
+
+  std::vector<int> act(nf, 1);
+  // algorithmic bytes / flops of one pass over the active fragments
+  auto sums = [&](double& nb, double& npt, double& nb2) {
+    nb = npt = nb2 = 0;
+    for (int j = 0; j < nf; ++j)
+      if (act[j]) {
+        const auto& d = f->host[j];
+        nb += (double)d.npts * d.bw;
+        npt += d.npts;
+        nb2 += (double)d.npts * d.bw * d.bw;
+      }
+  };
+  auto cholqr = [&]() {
+    double nb, npt, nb2;
+    sums(nb, npt, nb2);
+    for (int pass = 0; pass < 2; ++pass) {
+      k::gram<T>(c, f, X, X, f->d_G, f->d_active, nb * w, nb2 * 2.0 * 0.5);
+      k::cholinv(s, f, f->d_G, f->d_Q, f->d_active, f->d_flags);
+      k::rotate<T>(c, f, X, nullptr, f->d_Q, nullptr, nullptr, f->d_active,
+                   1, 2 * nb * w, nb2 * 2.0 * 0.5);
+    }
+  };
+  auto apply_plain = [&]() {
+    double nb, npt, nb2;
+    sums(nb, npt, nb2);
+    k::apply_h<T>(c, f, X, X, HX, f->d_tiles, f->n_tiles, f->d_active, 0,
+                  f->d_fs, 0, -1, (2 * nb + npt) * w, 28.0 * nb);
+  };
+  int n_active = nf;
+  auto rayleigh_ritz = [&]() {
+    double nb, npt, nb2;
+    sums(nb, npt, nb2);
+    k::gram<T>(c, f, X, HX, f->d_G, f->d_active, 2 * nb * w, nb2 * 2.0);
+    k::rr_eig(s, f, f->d_G, f->d_Q, f->d_theta, f->d_active);
+    k::rotate<T>(c, f, X, HX, f->d_Q, f->d_theta, f->d_res_partial,
+                 f->d_active, 0, 4 * nb * w, nb2 * 4.0);
+    OFM_HIP(hipMemsetAsync(f->d_nactive, 0, sizeof(int), s));
+    k::finalize_iter(s, f, f->d_theta, f->d_res_partial, f->d_fs, f->d_active,
+                     f->d_iters, f->d_conv, cfg.tol, f->d_nactive, f->d_res);
+    OFM_HIP(hipMemcpyAsync(&n_active, f->d_nactive, sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    OFM_HIP(hipMemcpyAsync(act.data(), f->d_active, sizeof(int) * nf,
+                           hipMemcpyDeviceToHost, s));
+    OFM_HIP(hipStreamSynchronize(s));
+    collect_stats(c);
+  };
+
+  cholqr();
+  apply_plain();
+  rayleigh_ritz();
+  for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
+    double nb, npt, nb2;
+    sums(nb, npt, nb2);
+    for (int step = 1; step <= cfg.degree; ++step) {
+      const bool odd = step & 1;
+      const T* in = odd ? X : P;
+      const T* prev = odd ? P : X;
+      T* out = odd ? P : X;
+      const double by = (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
+      k::apply_h<T>(c, f, in, prev, out, f->d_tiles, f->n_tiles, f->d_active,
+                    step, f->d_fs, 1, -1, by, 32.0 * nb);
+    }
+    cholqr();
+    apply_plain();
+    rayleigh_ritz();
+  }
+  // states: the lowest s_j Ritz vectors, sign gauge, whole-system H phi
+  k::gauge<T>(s, f, X);
+  k::whole_h<T>(c, f, X, arena<T>(f->d_hphi), -1);
+  std::vector<double> theta(f->th_total);
+  std::vector<int> it_h(nf);
+  std::vector<unsigned char> cv(nf);
+  OFM_HIP(hipMemcpyAsync(theta.data(), f->d_theta, sizeof(double) * theta.size(),
+                         hipMemcpyDeviceToHost, s));
+  OFM_HIP(hipMemcpyAsync(it_h.data(), f->d_iters, sizeof(int) * nf,
+                         hipMemcpyDeviceToHost, s));
+  OFM_HIP(hipMemcpyAsync(cv.data(), f->d_conv, nf, hipMemcpyDeviceToHost, s));
+  OFM_HIP(hipStreamSynchronize(s));
+  collect_stats(c);
+  f->eps_host.assign(f->n_basis, 0.0);
+  bool all = true;
+  for (int j = 0; j < nf; ++j) {
+    const auto& d = f->host[j];
+    for (int i = 0; i < d.n_states; ++i)
+      f->eps_host[d.basis_off + i] = theta[d.th_off + i];
+    all = all && cv[j];
+  }
+  if (eps) std::memcpy(eps, f->eps_host.data(), sizeof(double) * f->n_basis);
+  if (iters) std::memcpy(iters, it_h.data(), sizeof(int) * nf);
+  if (converged) std::memcpy(converged, cv.data(), nf);
+  f->have_states = true;
+  if (!all) {
+    c->err = "eigensolver reached max_iter before every fragment converged";
+    return OFM_E_NOCONV;
+  }
+  return OFM_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char* ofm_version(void) { return kVersion; }
+
+ofm_status ofm_create(ofm_ctx** out, int device, void* hip_stream,
+                      ofm_precision precision) {
+  if (!out) return OFM_E_INVALID;
+  *out = nullptr;
+  if (precision != OFM_FP64 && precision != OFM_MIXED_BF16X3) {
+    g_create_err = "unknown precision form";
+    return OFM_E_INVALID;
+  }
+  return guarded(nullptr, [&]() -> ofm_status {
+    int n = 0;
+    OFM_HIP(hipGetDeviceCount(&n));
+    OFM_REQUIRE(device >= 0 && device < n, OFM_E_INVALID,
+                "device index out of range");
+    auto* c = new ofm_ctx;
+    c->device = device;
+    c->precision = precision;
+    try {
+      OFM_HIP(hipSetDevice(device));
+      if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+      } else {
+        OFM_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+      }
+      hipDeviceProp_t prop;
+      OFM_HIP(hipGetDeviceProperties(&prop, device));
+      c->n_cu = prop.multiProcessorCount;
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_destroy(ofm_ctx* c) {
+  if (!c) return OFM_E_INVALID;
+  if (c->live > 0) {
+    c->err = "destroy every fragment and matrix handle before the context";
+    return OFM_E_STATE;
+  }
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  collect_stats(c);
+  ofm::destroy_blas(c);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return OFM_OK;
+}
+
+const char* ofm_last_error(const ofm_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
+                               const double* V, int n_frag,
+                               const ofm_fragment_desc* frags,
+                               const double* atom_xyz,
+                               const long long* frag_atom_ptr,
+                               const int* frag_atom_idx, double d_cut,
+                               ofm_frags** out) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(grid && V && frags && out, OFM_E_INVALID,
+                "grid, V, frags and out are required");
+    *out = nullptr;
+    use_device(c);
+    auto* f = new ofm_frags;
+    f->ctx = c;
+    try {
+      plan_fragments(f, *grid, n_frag, frags, 8);
+      plan_pairs(f, atom_xyz, frag_atom_ptr, frag_atom_idx, d_cut);
+      // tile lists
+      std::vector<int2> tiles, stiles, rtiles;
+      int th = 0;
+      for (int j = 0; j < n_frag; ++j) {
+        auto& d = f->host[j];
+        d.th_off = th;
+        th += d.bw;
+        for (int v = 0; v < d.bw; ++v) tiles.push_back(make_int2(j, v));
+        for (int i = 0; i < d.n_states; ++i) stiles.push_back(make_int2(j, i));
+        d.rt_begin = (int)rtiles.size();
+        d.rt_count = (d.npts + k::RCH - 1) / k::RCH;
+        for (int ch = 0; ch < d.rt_count; ++ch) rtiles.push_back(make_int2(j, ch));
+      }
+      f->th_total = th;
+      f->n_tiles = (int)tiles.size();
+      f->n_stiles = (int)stiles.size();
+      f->n_rtiles = (int)rtiles.size();
+      hipStream_t s = c->stream;
+      const size_t w = wsize(c);
+      f->d_frag = dev_alloc<FragDev>(n_frag);
+      f->d_tiles = dev_alloc<int2>(tiles.size());
+      f->d_stiles = dev_alloc<int2>(stiles.size());
+      f->d_rtiles = dev_alloc<int2>(rtiles.size());
+      f->d_v = dev_alloc<double>(f->v_total);
+      f->d_v32 = dev_alloc<float>(f->v_total);
+      f->d_x = dev_alloc<char>(f->x_total * w);
+      f->d_p = dev_alloc<char>(f->x_total * w);
+      f->d_hx = dev_alloc<char>(f->x_total * w);
+      f->d_hphi = dev_alloc<char>(f->hphi_total * w);
+      f->d_G = dev_alloc<double>((size_t)f->small_total * k::GCH);
+      f->d_Q = dev_alloc<double>(f->small_total);
+      f->d_theta = dev_alloc<double>(th);
+      f->d_res = dev_alloc<double>(th);
+      f->d_res_partial = dev_alloc<double>((size_t)f->n_rtiles * k::SMAX);
+      f->d_fs = dev_alloc<FilterState>(n_frag);
+      f->d_active = dev_alloc<int>(n_frag);
+      f->d_iters = dev_alloc<int>(n_frag);
+      f->d_conv = dev_alloc<unsigned char>(n_frag);
+      f->d_flags = dev_alloc<int>(n_frag);
+      f->d_nactive = dev_alloc<int>(4);
+      OFM_HIP(hipMemsetAsync(f->d_x, 0, f->x_total * w, s));
+      OFM_HIP(hipMemsetAsync(f->d_p, 0, f->x_total * w, s));
+      OFM_HIP(hipMemsetAsync(f->d_hx, 0, f->x_total * w, s));
+      OFM_HIP(hipMemsetAsync(f->d_hphi, 0, f->hphi_total * w, s));
+      OFM_HIP(hipMemsetAsync(f->d_theta, 0, sizeof(double) * th, s));
+      OFM_HIP(hipMemcpyAsync(f->d_frag, f->host.data(),
+                             sizeof(FragDev) * n_frag, hipMemcpyHostToDevice, s));
+      OFM_HIP(hipMemcpyAsync(f->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
+                             hipMemcpyHostToDevice, s));
+      OFM_HIP(hipMemcpyAsync(f->d_stiles, stiles.data(),
+                             sizeof(int2) * stiles.size(), hipMemcpyHostToDevice, s));
+      OFM_HIP(hipMemcpyAsync(f->d_rtiles, rtiles.data(),
+                             sizeof(int2) * rtiles.size(), hipMemcpyHostToDevice, s));
+      // potential: copy to the device if needed, restrict to the boxes
+      const long long nv = (long long)grid->nx * grid->ny * grid->nz;
+      const double* dV = V;
+      double* tmp = nullptr;
+      if (!is_device_ptr(V)) {
+        tmp = dev_alloc<double>(nv);
+        OFM_HIP(hipMemcpyAsync(tmp, V, sizeof(double) * nv,
+                               hipMemcpyHostToDevice, s));
+        dV = tmp;
+      }
+      int* bad = dev_alloc<int>(1);
+      OFM_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+      k::restrict_potential(s, dV, *grid, f);
+      hipLaunchKernelGGL(k_vstats, dim3(n_frag), dim3(256), 0, s, f->d_frag,
+                         n_frag, f->d_v, bad);
+      OFM_HIP(hipGetLastError());
+      int bad_h = 0;
+      OFM_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+      std::vector<FragDev> back(n_frag);
+      OFM_HIP(hipMemcpyAsync(back.data(), f->d_frag, sizeof(FragDev) * n_frag,
+                             hipMemcpyDeviceToHost, s));
+      OFM_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < n_frag; ++j) f->host[j].vmax = back[j].vmax;
+      dev_free(bad);
+      dev_free(tmp);
+      OFM_REQUIRE(!bad_h, OFM_E_INVALID,
+                  "V holds a NaN or Inf inside a fragment box");
+    } catch (...) {
+      free_frags(f);
+      delete f;
+      throw;
+    }
+    c->live += 1;
+    *out = f;
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_frags_destroy(ofm_frags* f) {
+  if (!f) return OFM_E_INVALID;
+  if (f->ctx) {
+    (void)hipSetDevice(f->ctx->device);
+    (void)hipStreamSynchronize(f->ctx->stream);
+    f->ctx->live -= 1;
+  }
+  free_frags(f);
+  delete f;
+  return OFM_OK;
+}
+
+ofm_status ofm_frags_info(const ofm_frags* f, long long* n_basis,
+                          long long* n_pairs, long long* total_points) {
+  if (!f) return OFM_E_INVALID;
+  if (n_basis) *n_basis = f->n_basis;
+  if (n_pairs) *n_pairs = (long long)f->pair_j.size();
+  if (total_points) *total_points = f->total_points;
+  return OFM_OK;
+}
+
+ofm_status ofm_fragment_geometry(const ofm_frags* f, int j, int lo[3],
+                                 int dims[3], int dlo[3], int ddims[3],
+                                 int* n_states) {
+  if (!f || j < 0 || j >= f->n_frag) return OFM_E_INVALID;
+  const FragDev& d = f->host[j];
+  for (int a = 0; a < 3; ++a) {
+    if (lo) lo[a] = d.lo[a];
+    if (dims) dims[a] = d.dims[a];
+    if (dlo) dlo[a] = d.dlo[a];
+    if (ddims) ddims[a] = d.ddims[a];
+  }
+  if (n_states) *n_states = d.n_states;
+  return OFM_OK;
+}
+
+ofm_status ofm_pairs(const ofm_frags* f, int* pair_j, int* pair_n,
+                     long long* block_off) {
+  if (!f) return OFM_E_INVALID;
+  const size_t n = f->pair_j.size();
+  if (pair_j) std::memcpy(pair_j, f->pair_j.data(), sizeof(int) * n);
+  if (pair_n) std::memcpy(pair_n, f->pair_n.data(), sizeof(int) * n);
+  if (block_off) std::memcpy(block_off, f->block_off.data(), sizeof(long long) * n);
+  return OFM_OK;
+}
+
+ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
+                               const ofm_solve_opts* opts, double* eps,
+                               int* iters, unsigned char* converged) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(f && f->ctx == c, OFM_E_INVALID,
+                "fragments were built with another context");
+    use_device(c);
+    SolveCfg cfg;
+    const bool fp64 = c->precision == OFM_FP64;
+    cfg.tol = (opts && opts->tol > 0) ? opts->tol : (fp64 ? 1e-10 : 2e-5);
+    cfg.max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 60;
+    cfg.degree = (opts && opts->degree > 0) ? opts->degree : 32;
+    cfg.degree += cfg.degree & 1;   // even: the filtered block ends in X
+    cfg.seed = opts ? opts->seed : 0;
+    OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
+                OFM_E_INVALID,
+                "guard vectors are fixed when the fragments are built");
+    const double t0 = now_ms();
+    ofm_status st = fp64 ? solve_impl<double>(c, f, cfg, eps, iters, converged)
+                         : solve_impl<float>(c, f, cfg, eps, iters, converged);
+    c->t_solve = now_ms() - t0;
+    return st;
+  });
+}
+
+ofm_status ofm_get_states(const ofm_frags* f, int j, double* phi,
+                          double* eps) {
+  if (!f || j < 0 || j >= f->n_frag) return OFM_E_INVALID;
+  ofm_ctx* c = f->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(f->have_states, OFM_E_STATE, "no states yet");
+    use_device(c);
+    const FragDev& d = f->host[j];
+    if (phi) {
+      const size_t w = wsize(c);
+      std::vector<char> buf((size_t)d.n_states * d.npts * w);
+      OFM_HIP(hipMemcpy2DAsync(buf.data(), d.npts * w,
+                               (char*)f->d_x + d.x_off * w, (size_t)d.ld * w,
+                               d.npts * w, d.n_states, hipMemcpyDeviceToHost,
+                               c->stream));
+      OFM_HIP(hipStreamSynchronize(c->stream));
+      const size_t n = (size_t)d.n_states * d.npts;
+      if (w == 8)
+        std::memcpy(phi, buf.data(), n * 8);
+      else
+        for (size_t i = 0; i < n; ++i) phi[i] = ((const float*)buf.data())[i];
+    }
+    if (eps)
+      for (int i = 0; i < d.n_states; ++i) eps[i] = f->eps_host[d.basis_off + i];
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_set_states(ofm_frags* f, int j, const double* phi,
+                          const double* eps) {
+  if (!f || j < 0 || j >= f->n_frag || !phi) return OFM_E_INVALID;
+  ofm_ctx* c = f->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    use_device(c);
+    const FragDev& d = f->host[j];
+    const size_t w = wsize(c);
+    const size_t n = (size_t)d.n_states * d.npts;
+    std::vector<char> buf(n * w);
+    if (w == 8)
+      std::memcpy(buf.data(), phi, n * 8);
+    else
+      for (size_t i = 0; i < n; ++i) ((float*)buf.data())[i] = (float)phi[i];
+    OFM_HIP(hipMemcpy2DAsync((char*)f->d_x + d.x_off * w, (size_t)d.ld * w,
+                             buf.data(), d.npts * w, d.npts * w, d.n_states,
+                             hipMemcpyHostToDevice, c->stream));
+    if (c->precision == OFM_FP64)
+      k::whole_h<double>(c, f, arena<double>(f->d_x), arena<double>(f->d_hphi), j);
+    else
+      k::whole_h<float>(c, f, arena<float>(f->d_x), arena<float>(f->d_hphi), j);
+    OFM_HIP(hipStreamSynchronize(c->stream));
+    if (f->eps_host.size() != (size_t)f->n_basis) f->eps_host.assign(f->n_basis, 0.0);
+    for (int i = 0; i < d.n_states; ++i)
+      f->eps_host[d.basis_off + i] = eps ? eps[i] : 0.0;
+    f->have_states = true;
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_get_hphi(const ofm_frags* f, int j, double* hphi) {
+  if (!f || j < 0 || j >= f->n_frag || !hphi) return OFM_E_INVALID;
+  ofm_ctx* c = f->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(f->have_states, OFM_E_STATE, "no states yet");
+    use_device(c);
+    const FragDev& d = f->host[j];
+    const size_t w = wsize(c);
+    std::vector<char> buf((size_t)d.n_states * d.ndil * w);
+    OFM_HIP(hipMemcpy2DAsync(buf.data(), d.ndil * w,
+                             (char*)f->d_hphi + d.hphi_off * w, (size_t)d.ldd * w,
+                             d.ndil * w, d.n_states, hipMemcpyDeviceToHost,
+                             c->stream));
+    OFM_HIP(hipStreamSynchronize(c->stream));
+    const size_t n = (size_t)d.n_states * d.ndil;
+    if (w == 8)
+      std::memcpy(hphi, buf.data(), n * 8);
+    else
+      for (size_t i = 0; i < n; ++i) hphi[i] = ((const float*)buf.data())[i];
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_apply_fragment_h(ofm_ctx* c, ofm_frags* f, int j, int nvec,
+                                const double* x, double* y) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(f && f->ctx == c && j >= 0 && j < f->n_frag && nvec >= 1 && x && y,
+                OFM_E_INVALID, "bad arguments");
+    use_device(c);
+    const FragDev& d = f->host[j];
+    const size_t w = wsize(c);
+    const size_t n = (size_t)nvec * d.ld;
+    char* din = dev_alloc<char>(n * w);
+    char* dout = dev_alloc<char>(n * w);
+    int2* dt = dev_alloc<int2>(nvec);
+    try {
+      std::vector<char> buf((size_t)nvec * d.npts * w);
+      for (size_t i = 0; i < (size_t)nvec * d.npts; ++i) {
+        if (w == 8)
+          ((double*)buf.data())[i] = x[i];
+        else
+          ((float*)buf.data())[i] = (float)x[i];
+      }
+      std::vector<int2> t(nvec);
+      for (int v = 0; v < nvec; ++v) t[v] = make_int2(j, v);
+      OFM_HIP(hipMemsetAsync(din, 0, n * w, c->stream));
+      OFM_HIP(hipMemcpy2DAsync(din, (size_t)d.ld * w, buf.data(), d.npts * w,
+                               d.npts * w, nvec, hipMemcpyHostToDevice, c->stream));
+      OFM_HIP(hipMemcpyAsync(dt, t.data(), sizeof(int2) * nvec,
+                             hipMemcpyHostToDevice, c->stream));
+      // nvec may exceed b_j: the descriptor's ld is used, tiles list v < nvec
+      if (w == 8)
+        k::apply_h<double>(c, f, (const double*)din, (const double*)din,
+                           (double*)dout, dt, nvec, nullptr, 0, nullptr, 0, 0,
+                           0, 0);
+      else
+        k::apply_h<float>(c, f, (const float*)din, (const float*)din,
+                          (float*)dout, dt, nvec, nullptr, 0, nullptr, 0, 0,
+                          0, 0);
+      OFM_HIP(hipMemcpy2DAsync(buf.data(), d.npts * w, dout, (size_t)d.ld * w,
+                               d.npts * w, nvec, hipMemcpyDeviceToHost, c->stream));
+      OFM_HIP(hipStreamSynchronize(c->stream));
+      collect_stats(c);
+      for (size_t i = 0; i < (size_t)nvec * d.npts; ++i)
+        y[i] = w == 8 ? ((double*)buf.data())[i] : ((float*)buf.data())[i];
+    } catch (...) {
+      dev_free(din);
+      dev_free(dout);
+      dev_free(dt);
+      throw;
+    }
+    dev_free(din);
+    dev_free(dout);
+    dev_free(dt);
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(f && f->ctx == c && out, OFM_E_INVALID, "bad arguments");
+    OFM_REQUIRE(f->have_states, OFM_E_STATE,
+                "matrix elements need fragment states (solve or set_states)");
+    *out = nullptr;
+    use_device(c);
+    const double t0 = now_ms();
+    auto tasks = plan_pair_tasks(f);
+    auto* m = new ofm_mats;
+    m->ctx = c;
+    m->frags = f;
+    m->n_values = f->n_values;
+    m->n_basis = f->n_basis;
+    m->pair_j = f->pair_j;
+    m->pair_n = f->pair_n;
+    m->block_off = f->block_off;
+    for (auto& d : f->host) {
+      m->states.push_back(d.n_states);
+      m->basis_off.push_back(d.basis_off);
+    }
+    PairTask* dt = nullptr;
+    try {
+      m->d_H = dev_alloc<double>(f->n_values);
+      m->d_S = dev_alloc<double>(f->n_values);
+      dt = dev_alloc<PairTask>(tasks.size());
+      hipStream_t s = c->stream;
+      OFM_HIP(hipMemsetAsync(m->d_H, 0, sizeof(double) * f->n_values, s));
+      OFM_HIP(hipMemsetAsync(m->d_S, 0, sizeof(double) * f->n_values, s));
+      OFM_HIP(hipMemcpyAsync(dt, tasks.data(), sizeof(PairTask) * tasks.size(),
+                             hipMemcpyHostToDevice, s));
+      double flops = 0, bytes = 0;
+      for (auto& t : tasks)
+        flops += 2.0 * t.ma * t.mb * (double)t.om[0] * t.om[1] * t.om[2];
+      const double w = (double)wsize(c);
+      for (auto& d : f->host)
+        bytes += (double)(d.npts + d.ndil) * d.n_states * w;
+      bytes += 2.0 * 8.0 * f->n_values;
+      if (c->precision == OFM_FP64)
+        k::pair_elements<double>(c, f, dt, (int)tasks.size(),
+                                 arena<double>(f->d_x), arena<double>(f->d_hphi),
+                                 m->d_H, m->d_S, flops, bytes);
+      else
+        k::pair_elements<float>(c, f, dt, (int)tasks.size(),
+                                arena<float>(f->d_x), arena<float>(f->d_hphi),
+                                m->d_H, m->d_S, flops, bytes);
+      OFM_HIP(hipStreamSynchronize(s));
+      collect_stats(c);
+    } catch (...) {
+      dev_free(dt);
+      dev_free(m->d_H);
+      dev_free(m->d_S);
+      delete m;
+      throw;
+    }
+    dev_free(dt);
+    c->t_elem = now_ms() - t0;
+    c->live += 1;
+    *out = m;
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_mats_info(const ofm_mats* m, long long* n_values) {
+  if (!m) return OFM_E_INVALID;
+  if (n_values) *n_values = m->n_values;
+  return OFM_OK;
+}
+
+ofm_status ofm_mats_copy(const ofm_mats* m, double* H_blocks,
+                         double* S_blocks) {
+  if (!m) return OFM_E_INVALID;
+  ofm_ctx* c = m->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    use_device(c);
+    if (H_blocks)
+      OFM_HIP(hipMemcpyAsync(H_blocks, m->d_H, sizeof(double) * m->n_values,
+                             hipMemcpyDeviceToHost, c->stream));
+    if (S_blocks)
+      OFM_HIP(hipMemcpyAsync(S_blocks, m->d_S, sizeof(double) * m->n_values,
+                             hipMemcpyDeviceToHost, c->stream));
+    OFM_HIP(hipStreamSynchronize(c->stream));
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_mats_destroy(ofm_mats* m) {
+  if (!m) return OFM_E_INVALID;
+  (void)hipSetDevice(m->ctx->device);
+  (void)hipStreamSynchronize(m->ctx->stream);
+  m->ctx->live -= 1;
+  dev_free(m->d_H);
+  dev_free(m->d_S);
+  delete m;
+  return OFM_OK;
+}
+
+ofm_status ofm_solve_global(ofm_ctx* c, const ofm_mats* m, double s_thresh,
+                            double e_lo, double e_hi, int* n_kept, int* n_eig,
+                            double* E, double* C, double* s_min) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(m && m->ctx == c && n_eig && E, OFM_E_INVALID, "bad arguments");
+    OFM_REQUIRE(std::isfinite(s_thresh) && s_thresh >= 0, OFM_E_INVALID,
+                "s_thresh must be finite and >= 0");
+    use_device(c);
+    const double t0 = now_ms();
+    global_solve(c, m, s_thresh, e_lo, e_hi, n_kept, n_eig, E, C, s_min);
+    c->t_global = now_ms() - t0;
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_set_profiling(ofm_ctx* c, int on) {
+  if (!c) return OFM_E_INVALID;
+  c->profiling = on != 0;
+  return OFM_OK;
+}
+
+ofm_status ofm_kernel_stats(ofm_ctx* c, const char* family,
+                            long long* launches, double* total_ms,
+                            double* alg_bytes, double* flops) {
+  if (!c || !family) return OFM_E_INVALID;
+  (void)hipStreamSynchronize(c->stream);
+  collect_stats(c);
+  auto it = c->stats.find(family);
+  KernelStat s;
+  if (it != c->stats.end()) s = it->second;
+  if (launches) *launches = s.launches;
+  if (total_ms) *total_ms = s.ms;
+  if (alg_bytes) *alg_bytes = s.bytes;
+  if (flops) *flops = s.flops;
+  return OFM_OK;
+}
+
+ofm_status ofm_reset_stats(ofm_ctx* c) {
+  if (!c) return OFM_E_INVALID;
+  (void)hipStreamSynchronize(c->stream);
+  collect_stats(c);
+  c->stats.clear();
+  return OFM_OK;
+}
+
+ofm_status ofm_stage_times(const ofm_ctx* c, double* solve_ms,
+                           double* elements_ms, double* global_ms) {
+  if (!c) return OFM_E_INVALID;
+  if (solve_ms) *solve_ms = c->t_solve;
+  if (elements_ms) *elements_ms = c->t_elem;
+  if (global_ms) *global_ms = c->t_global;
+  return OFM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+// Generalised eigenproblem sum_mn (H - E S) C = 0 in the fragment basis
+// (method Eq. 2), FP64 on the GPU by thresholded canonical
+// orthogonalisation:
+//   S = U diag(s) U^T            (rocSOLVER dsyevd)
+//   K = { k : s_k >= s_thresh }  (directions of S below the threshold are
+//                                 linearly dependent combinations of
+//                                 overlapping fragment states and are dropped)
+//   X = U_K diag(s_K^-1/2)       (own kernel)
+//   H' = X^T H X                 (two rocBLAS dgemm)
+//   H' = Y diag(E) Y^T           (rocSOLVER dsyevd), C = X Y
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ofm_internal.h"
+
+using namespace ofm;
+
+namespace {
+
+#define OFM_BLAS(call)                                                      \
+  do {                                                                      \
+    rocblas_status s_ = (call);                                             \
+    if (s_ != rocblas_status_success)                                       \
+      throw Error{OFM_E_DEVICE, std::string(#call) + " failed: " +          \
+                                    rocblas_status_to_string(s_)};          \
+  } while (0)
+
+// scatter the packed upper blocks (and their transposes) into dense N x N
+__global__ void k_assemble(const int* __restrict__ pj, const int* __restrict__ pn,
+                           const long long* __restrict__ boff,
+                           const int* __restrict__ st,
+                           const long long* __restrict__ bas, int npair,
+                           const double* __restrict__ Hb,
+                           const double* __restrict__ Sb, double* __restrict__ H,
+                           double* __restrict__ S, long long N) {
+  const int p = blockIdx.x;
+  if (p >= npair) return;
+  const int j = pj[p], n = pn[p];
+  const int sj = st[j], sn = st[n];
+  const long long r0 = bas[j], c0 = bas[n];
+  for (int e = threadIdx.x; e < sj * sn; e += blockDim.x) {
+    const int i = e / sn, m = e % sn;
+    const double h = Hb[boff[p] + e], s = Sb[boff[p] + e];
+    // symmetric: column-major and row-major storage coincide
+    H[(r0 + i) * N + (c0 + m)] = h;
+    S[(r0 + i) * N + (c0 + m)] = s;
+    H[(c0 + m) * N + (r0 + i)] = h;
+    S[(c0 + m) * N + (r0 + i)] = s;
+  }
+}
+
+// X[:, k] = U[:, first + k] / sqrt(s[first + k])   (column-major N x K)
+__global__ void k_scale_cols(const double* __restrict__ U,
+                             const double* __restrict__ s, double* __restrict__ X,
+                             long long N, int first, int K) {
+  const long long total = N * (long long)K;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long col = e / N, row = e % N;
+    X[e] = U[(first + col) * N + row] / sqrt(s[first + col]);
+  }
+}
+
+rocblas_handle blas(ofm_ctx* c) {
+  if (!c->blas) {
+    rocblas_handle h;
+    OFM_BLAS(rocblas_create_handle(&h));
+    c->blas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(c->blas);
+  OFM_BLAS(rocblas_set_stream(h, c->stream));
+  return h;
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  explicit DevBuf(size_t n) { p = dev_alloc<T>(n); }
+  ~DevBuf() { dev_free(p); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+}  // namespace
+
+namespace ofm {
+
+void destroy_blas(ofm_ctx* c) {
+  if (c && c->blas) {
+    (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
+    c->blas = nullptr;
+  }
+}
+
+void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
+                  double e_hi, int* n_kept, int* n_eig, double* E, double* C,
+                  double* s_min) {
+  const long long N = m->n_basis;
+  OFM_REQUIRE(N >= 1 && N <= 200000, OFM_E_INVALID,
+              "basis size outside the dense solver's range");
+  hipStream_t st = c->stream;
+  rocblas_handle h = blas(c);
+  const int np = (int)m->pair_j.size();
+  const int nf = (int)m->states.size();
+  DevBuf<double> H(N * N), S(N * N), s(N), work(N);
+  DevBuf<int> pj(np), pn(np), sts(nf), info(1);
+  DevBuf<long long> boff(np), bas(nf);
+  OFM_HIP(hipMemsetAsync(H.p, 0, sizeof(double) * N * N, st));
+  OFM_HIP(hipMemsetAsync(S.p, 0, sizeof(double) * N * N, st));
+  OFM_HIP(hipMemcpyAsync(pj.p, m->pair_j.data(), sizeof(int) * np,
+                         hipMemcpyHostToDevice, st));
+  OFM_HIP(hipMemcpyAsync(pn.p, m->pair_n.data(), sizeof(int) * np,
+                         hipMemcpyHostToDevice, st));
+  OFM_HIP(hipMemcpyAsync(boff.p, m->block_off.data(), sizeof(long long) * np,
+                         hipMemcpyHostToDevice, st));
+  OFM_HIP(hipMemcpyAsync(sts.p, m->states.data(), sizeof(int) * nf,
+                         hipMemcpyHostToDevice, st));
+  OFM_HIP(hipMemcpyAsync(bas.p, m->basis_off.data(), sizeof(long long) * nf,
+                         hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_assemble, dim3(np), dim3(256), 0, st, pj.p, pn.p,
+                     boff.p, sts.p, bas.p, np, m->d_H, m->d_S, H.p, S.p, N);
+  OFM_HIP(hipGetLastError());
+  // eig(S), ascending
+  OFM_BLAS(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper,
+                            (rocblas_int)N, S.p, (rocblas_int)N, s.p, work.p,
+                            info.p));
+  std::vector<double> sh(N);
+  int info_h = 0;
+  OFM_HIP(hipMemcpyAsync(sh.data(), s.p, sizeof(double) * N,
+                         hipMemcpyDeviceToHost, st));
+  OFM_HIP(hipMemcpyAsync(&info_h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  OFM_HIP(hipStreamSynchronize(st));
+  OFM_REQUIRE(info_h == 0, OFM_E_DEVICE, "dsyevd(S) did not converge");
+  long long first = 0;
+  while (first < N && !(sh[first] >= s_thresh)) ++first;
+  const int K = (int)(N - first);
+  if (n_kept) *n_kept = K;
+  if (K == 0) {
+    *n_eig = 0;
+    throw Error{OFM_E_SINGULAR, "every eigenvalue of S is below the threshold"};
+  }
+  if (s_min) *s_min = sh[first];
+  DevBuf<double> X(N * (long long)K), T1(N * (long long)K), Hp((long long)K * K),
+      E_d(K), work2(K);
+  hipLaunchKernelGGL(k_scale_cols, dim3(1024), dim3(256), 0, st, S.p, s.p, X.p,
+                     N, (int)first, K);
+  OFM_HIP(hipGetLastError());
+  const double one = 1.0, zero = 0.0;
+  // T1 = H X  (N x K), H' = X^T T1  (K x K)
+  OFM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none,
+                         (rocblas_int)N, K, (rocblas_int)N, &one, H.p,
+                         (rocblas_int)N, X.p, (rocblas_int)N, &zero, T1.p,
+                         (rocblas_int)N));
+  OFM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none,
+                         K, K, (rocblas_int)N, &one, X.p, (rocblas_int)N, T1.p,
+                         (rocblas_int)N, &zero, Hp.p, K));
+  OFM_BLAS(rocsolver_dsyevd(h, C ? rocblas_evect_original : rocblas_evect_none,
+                            rocblas_fill_upper, K, Hp.p, K, E_d.p, work2.p,
+                            info.p));
+  std::vector<double> Eh(K);
+  OFM_HIP(hipMemcpyAsync(Eh.data(), E_d.p, sizeof(double) * K,
+                         hipMemcpyDeviceToHost, st));
+  OFM_HIP(hipMemcpyAsync(&info_h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  OFM_HIP(hipStreamSynchronize(st));
+  OFM_REQUIRE(info_h == 0, OFM_E_DEVICE, "dsyevd(H') did not converge");
+  int lo = 0;
+  while (lo < K && !(Eh[lo] >= e_lo)) ++lo;
+  int hi = lo;
+  while (hi < K && Eh[hi] <= e_hi) ++hi;
+  const int ne = hi - lo;
+  *n_eig = ne;
+  for (int i = 0; i < ne; ++i) E[i] = Eh[lo + i];
+  if (C && ne > 0) {
+    // C = X Y[:, lo:hi]   (N x ne, column-major, stride N)
+    DevBuf<double> Cd(N * (long long)ne);
+    OFM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none,
+                           (rocblas_int)N, ne, K, &one, X.p, (rocblas_int)N,
+                           Hp.p + (long long)lo * K, K, &zero, Cd.p,
+                           (rocblas_int)N));
+    OFM_HIP(hipMemcpyAsync(C, Cd.p, sizeof(double) * N * ne,
+                           hipMemcpyDeviceToHost, st));
+    OFM_HIP(hipStreamSynchronize(st));
+  }
+}
+
+}  // namespace ofm

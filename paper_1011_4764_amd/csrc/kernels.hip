@@ -1,0 +1,988 @@
+// HIP kernels of the OFM hot path for gfx950 (MI355X, CDNA4).
+//
+//  * k_apply_h      fragment Hamiltonian H_j = -1/2 Lap + V_j on a box, one
+//                   workgroup per (fragment, vector): the xy plane is staged in
+//                   LDS, z neighbours ride in a 5-deep register queue while the
+//                   workgroup marches along z (every input value read from HBM
+//                   once).  Also runs the scaled three-term Chebyshev step.
+//  * k_gram         G = A^T B per fragment over its box points, FP64 MFMA
+//                   (16x16x4) with split-K partials summed in fixed order.
+//  * k_cholinv      Cholesky of a Gram matrix and the inverse of its factor
+//                   (CholQR), one workgroup per fragment, FP64 in LDS.
+//  * k_rr_eig       cyclic two-sided Jacobi on the projected matrix (Rayleigh-
+//                   Ritz), one workgroup per fragment, FP64 in LDS.
+//  * k_rotate       X <- X Q (and HX <- HX Q with fused residual norms).
+//  * k_whole_h      H|phi> with the whole-system H on the dilated box.
+//  * k_pair         grouped pair contraction C = A^T B over box overlaps,
+//                   FP64 MFMA, one workgroup per block.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "ofm_internal.h"
+
+namespace ofm {
+namespace k {
+
+constexpr int WG = 256;
+
+// 4th-order central second-difference weights (times 1/h^2)
+constexpr double W0 = -2.5, W1 = 4.0 / 3.0, W2 = -1.0 / 12.0;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Workgroup i is dispatched to XCD i % 8; remap so that each XCD receives a
+// contiguous range of logical tiles (tiles of one fragment share V_j and
+// their neighbours' planes in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int bid, int nblk_pad) {
+  const int per = nblk_pad >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+static int pad8(int n) { return (n + 7) / 8 * 8; }
+
+// ---------------------------------------------------------------------------
+// potential restricted to every box
+// ---------------------------------------------------------------------------
+__global__ void k_restrict(const FragDev* __restrict__ F, int nf,
+                           const double* __restrict__ V, int nx, int ny,
+                           double* __restrict__ out, float* __restrict__ out32) {
+  const int j = blockIdx.y;
+  if (j >= nf) return;
+  const FragDev f = F[j];
+  for (int p = blockIdx.x * WG + threadIdx.x; p < f.npts;
+       p += gridDim.x * WG) {
+    const int x = p % f.dims[0];
+    const int y = (p / f.dims[0]) % f.dims[1];
+    const int z = p / (f.dims[0] * f.dims[1]);
+    const long long g = (long long)(f.lo[0] + x) +
+                        (long long)nx * ((f.lo[1] + y) + (long long)ny *
+                                                             (f.lo[2] + z));
+    const double v = V[g];
+    out[f.v_off + p] = v;
+    out32[f.v_off + p] = (float)v;
+  }
+}
+
+void restrict_potential(hipStream_t s, const double* V, const ofm_grid& g,
+                        const ofm_frags* f) {
+  int maxp = 0;
+  for (auto& d : f->host) maxp = std::max(maxp, d.npts);
+  dim3 grid((maxp + WG - 1) / WG, f->n_frag);
+  hipLaunchKernelGGL(k_restrict, grid, dim3(WG), 0, s, f->d_frag, f->n_frag,
+                     V, g.nx, g.ny, f->d_v, f->d_v32);
+  OFM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// seeded start vectors: splitmix64 of (seed, fragment, vector, point)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void k_init_random(const FragDev* __restrict__ F,
+                              const int2* __restrict__ rt, int nrt,
+                              T* __restrict__ X, unsigned long long seed) {
+  const int t = blockIdx.x;
+  if (t >= nrt) return;
+  const int j = rt[t].x;
+  const FragDev f = F[j];
+  const int p = rt[t].y * RCH + threadIdx.x;
+  if (p >= f.npts) return;
+  for (int v = 0; v < f.bw; ++v) {
+    unsigned long long key = seed * 0x100000001B3ULL ^
+                             ((unsigned long long)j << 40) ^
+                             ((unsigned long long)v << 26) ^
+                             (unsigned long long)p;
+    const unsigned long long r = splitmix64(key);
+    const double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);
+    X[f.x_off + (long long)v * f.ld + p] = (T)(2.0 * u - 1.0);
+  }
+}
+
+template <typename T>
+void init_random(hipStream_t s, const ofm_frags* f, T* X,
+                 unsigned long long seed) {
+  hipLaunchKernelGGL(k_init_random<T>, dim3(f->n_rtiles), dim3(RCH), 0, s,
+                     f->d_frag, f->d_rtiles, f->n_rtiles, X, seed);
+  OFM_HIP(hipGetLastError());
+}
+template void init_random<double>(hipStream_t, const ofm_frags*, double*,
+                                  unsigned long long);
+template void init_random<float>(hipStream_t, const ofm_frags*, float*,
+                                 unsigned long long);
+
+// ---------------------------------------------------------------------------
+// fragment Hamiltonian / Chebyshev step
+// ---------------------------------------------------------------------------
+// mode 0: out = H_j in
+// mode 1: step k of the scaled Chebyshev filter on [lower, upper] normalised
+//         at `scale`:  Y_1 = (s1/e)(H - c) Y_0,
+//         Y_k = (2 s_k/e)(H - c) Y_{k-1} - s_{k-1} s_k Y_{k-2},
+//         e = (upper-lower)/2, c = (upper+lower)/2, s1 = e/(scale-c),
+//         s_k = 1/(2/s1 - s_{k-1}).
+// `prev` and `out` may alias (each point of `out` depends on `prev` at the
+// same point only); `in` must not alias either.
+template <typename T, int PPT>
+__global__ __launch_bounds__(WG) void k_apply_h(
+    const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
+    int nblk_pad, const T* __restrict__ Vj, const T* __restrict__ in,
+    const T* prev, T* out, const FilterState* __restrict__ fs,
+    const int* __restrict__ active, int step, int mode, double nh,
+    long long base_override) {
+  const int t = xcd_tile(blockIdx.x, nblk_pad);
+  if (t >= ntiles) return;
+  const int j = tiles[t].x, v = tiles[t].y;
+  if (active && !active[j]) return;
+  const FragDev& fr = F[j];
+  const int nx = fr.dims[0], ny = fr.dims[1], nz = fr.dims[2];
+  const int plane = nx * ny;
+  const long long base =
+      (base_override >= 0 ? base_override : fr.x_off) + (long long)v * fr.ld;
+  const T* __restrict__ src = in + base;
+  const T* pv = prev + base;
+  T* dst = out + base;
+  const T* __restrict__ vv = Vj + fr.v_off;
+
+  T alpha = 1, gamma = 0, beta = 0;
+  if (mode == 1) {
+    const FilterState st = fs[j];
+    const double e = 0.5 * (st.upper - st.lower);
+    if (!(e > 1e-12 * fabs(st.upper))) {
+      alpha = 0; gamma = 1; beta = 0;   // degenerate interval: identity
+    } else {
+      const double c = 0.5 * (st.upper + st.lower);
+      const double s1 = e / (st.scale - c);
+      double sp = s1, sc = s1;
+      const double tau = 2.0 / s1;
+      for (int k = 2; k <= step; ++k) {
+        sp = sc;
+        sc = 1.0 / (tau - sp);
+      }
+      const double a = (step == 1 ? sc : 2.0 * sc) / e;
+      alpha = (T)a;
+      gamma = (T)(-c * a);
+      beta = (T)(step == 1 ? 0.0 : -sp * sc);
+    }
+  }
+
+  __shared__ T lds[2][PPT * WG];
+  const int tid = threadIdx.x;
+  int px[PPT], py[PPT], pp[PPT];
+  bool ok[PPT];
+  T q0[PPT], q1[PPT], q2[PPT], q3[PPT], q4[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int p = tid + k * WG;
+    ok[k] = p < plane;
+    pp[k] = ok[k] ? p : 0;
+    px[k] = pp[k] % nx;
+    py[k] = pp[k] / nx;
+    q0[k] = 0;
+    q1[k] = 0;
+    q2[k] = ok[k] ? src[pp[k]] : T(0);
+    q3[k] = (ok[k] && nz > 1) ? src[plane + pp[k]] : T(0);
+    q4[k] = (ok[k] && nz > 2) ? src[2 * plane + pp[k]] : T(0);
+  }
+  const T tw0 = (T)W0, tw1 = (T)W1, tw2 = (T)W2, tnh = (T)nh;
+  for (int z = 0; z < nz; ++z) {
+    T nxt[PPT], vz[PPT], pz[PPT];
+    const int zoff = z * plane;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      nxt[k] = (ok[k] && z + 3 < nz) ? src[zoff + 3 * plane + pp[k]] : T(0);
+      vz[k] = ok[k] ? vv[zoff + pp[k]] : T(0);
+      pz[k] = (ok[k] && mode == 1 && step > 1) ? pv[zoff + pp[k]] : T(0);
+      if (ok[k]) lds[z & 1][pp[k]] = q2[k];
+    }
+    __syncthreads();
+    const T* L = lds[z & 1];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (!ok[k]) continue;
+      const int p = pp[k], x = px[k], y = py[k];
+      const T c = q2[k];
+      const T xm1 = x >= 1 ? L[p - 1] : T(0);
+      const T xm2 = x >= 2 ? L[p - 2] : T(0);
+      const T xp1 = x + 1 < nx ? L[p + 1] : T(0);
+      const T xp2 = x + 2 < nx ? L[p + 2] : T(0);
+      const T ym1 = y >= 1 ? L[p - nx] : T(0);
+      const T ym2 = y >= 2 ? L[p - 2 * nx] : T(0);
+      const T yp1 = y + 1 < ny ? L[p + nx] : T(0);
+      const T yp2 = y + 2 < ny ? L[p + 2 * nx] : T(0);
+      // walls at every box face: odd image of the second ghost
+      const int nfaces = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) +
+                         (z == 0) + (z == nz - 1);
+      const T lap = tw0 * T(3) * c +
+                    tw1 * ((xm1 + xp1) + (ym1 + yp1) + (q1[k] + q3[k])) +
+                    tw2 * ((xm2 + xp2) + (ym2 + yp2) + (q0[k] + q4[k])) -
+                    tw2 * T(nfaces) * c;
+      const T hv = tnh * lap + vz[k] * c;
+      T o;
+      if (mode == 0)
+        o = hv;
+      else
+        o = alpha * hv + gamma * c + beta * pz[k];
+      dst[zoff + p] = o;
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      q0[k] = q1[k];
+      q1[k] = q2[k];
+      q2[k] = q3[k];
+      q3[k] = q4[k];
+      q4[k] = nxt[k];
+    }
+  }
+}
+
+template <typename T>
+void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
+             T* out, const int2* tiles, int ntiles, const int* active,
+             int step, const FilterState* fs, int mode,
+             long long base_override, double alg_bytes, double flops) {
+  const T* Vj;
+  if constexpr (sizeof(T) == 8)
+    Vj = (const T*)f->d_v;
+  else
+    Vj = (const T*)f->d_v32;
+  const double nh = -0.5 / (f->grid.h * f->grid.h);
+  const int nblk = pad8(ntiles);
+  Timed tm(c, "stencil", alg_bytes, flops);
+  if (f->max_plane <= 2 * WG)
+    hipLaunchKernelGGL((k_apply_h<T, 2>), dim3(nblk), dim3(WG), 0, c->stream,
+                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
+                       active, step, mode, nh, base_override);
+  else if (f->max_plane <= 4 * WG)
+    hipLaunchKernelGGL((k_apply_h<T, 4>), dim3(nblk), dim3(WG), 0, c->stream,
+                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
+                       active, step, mode, nh, base_override);
+  else if (f->max_plane <= 9 * WG)
+    hipLaunchKernelGGL((k_apply_h<T, 9>), dim3(nblk), dim3(WG), 0, c->stream,
+                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
+                       active, step, mode, nh, base_override);
+  else
+    hipLaunchKernelGGL((k_apply_h<T, 16>), dim3(nblk), dim3(WG), 0, c->stream,
+                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
+                       active, step, mode, nh, base_override);
+  OFM_HIP(hipGetLastError());
+}
+template void apply_h<double>(ofm_ctx*, const ofm_frags*, const double*,
+                              const double*, double*, const int2*, int,
+                              const int*, int, const FilterState*, int,
+                              long long, double, double);
+template void apply_h<float>(ofm_ctx*, const ofm_frags*, const float*,
+                             const float*, float*, const int2*, int,
+                             const int*, int, const FilterState*, int,
+                             long long, double, double);
+
+// ---------------------------------------------------------------------------
+// Gram products G = A^T B per fragment (FP64 MFMA 16x16x4)
+// ---------------------------------------------------------------------------
+// MFMA operand placement: lane l = r + 16 g supplies A[r][g] and B[g][r]; the
+// K index is free to permute, so lane (r, g) feeds four consecutive points
+// of vector r from one 32-byte load.  Accumulator: item i of lane l holds
+// row l/16 + 4 i, column l % 16.
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void load4(const T* p, double* o) {
+  if constexpr (sizeof(T) == 8) {
+    const d4 v = *reinterpret_cast<const d4*>(p);
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+  } else {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 v = *reinterpret_cast<const f4*>(p);
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+  }
+}
+
+// symmetric (upper tiles only) when A == B
+template <typename T>
+__global__ __launch_bounds__(WG) void k_gram(
+    const FragDev* __restrict__ F, int nf, const T* __restrict__ A,
+    const T* __restrict__ B, double* __restrict__ partial,
+    const int* __restrict__ active, int symmetric) {
+  const int j = blockIdx.x / GCH, ch = blockIdx.x % GCH;
+  if (j >= nf) return;
+  if (active && !active[j]) return;
+  const FragDev& fr = F[j];
+  const int bw = fr.bw;
+  const int nt = (bw + 15) / 16;
+  int cs = (fr.ld + GCH - 1) / GCH;
+  cs = (cs + 15) / 16 * 16;
+  const int kb = ch * cs;
+  const int ke = min(kb + cs, fr.ld);
+  double* out = partial + (long long)fr.small_off * GCH + (long long)ch * bw * bw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  int tile = 0;
+  for (int ti = 0; ti < nt; ++ti) {
+    for (int tj = symmetric ? ti : 0; tj < nt; ++tj, ++tile) {
+      if ((tile & 3) != wave) continue;
+      const int ra = ti * 16 + r, rb = tj * 16 + r;
+      const bool va = ra < bw, vb = rb < bw;
+      const T* pa = A + fr.x_off + (long long)(va ? ra : 0) * fr.ld;
+      const T* pb = B + fr.x_off + (long long)(vb ? rb : 0) * fr.ld;
+      d4 acc = {0, 0, 0, 0};
+      // kb and ke are multiples of 16, so every lane runs the same trip
+      // count (an MFMA reads all lanes' operands)
+      for (int k = kb + 4 * g; k < ke; k += 16) {
+        double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+        if (va) load4(pa + k, a);
+        if (vb) load4(pb + k, b);
+        acc = mfma_f64(a[0], b[0], acc);
+        acc = mfma_f64(a[1], b[1], acc);
+        acc = mfma_f64(a[2], b[2], acc);
+        acc = mfma_f64(a[3], b[3], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ti * 16 + g + 4 * i, col = tj * 16 + r;
+        if (row < bw && col < bw) out[row * bw + col] = acc[i];
+      }
+    }
+  }
+}
+
+template <typename T>
+void gram(ofm_ctx* c, const ofm_frags* f, const T* A, const T* B, double* G,
+          const int* active, double bytes, double flops) {
+  Timed tm(c, "gram", bytes, flops);
+  hipLaunchKernelGGL(k_gram<T>, dim3(f->n_frag * GCH), dim3(WG), 0, c->stream,
+                     f->d_frag, f->n_frag, A, B, G, active, A == B ? 1 : 0);
+  OFM_HIP(hipGetLastError());
+}
+template void gram<double>(ofm_ctx*, const ofm_frags*, const double*,
+                           const double*, double*, const int*, double, double);
+template void gram<float>(ofm_ctx*, const ofm_frags*, const float*,
+                          const float*, double*, const int*, double, double);
+
+// sum the split-K partials of fragment fr into a symmetric LDS matrix
+__device__ void load_sym(const FragDev& fr, const double* __restrict__ partial,
+                         double* M, int ldm, int symmetric) {
+  const int bw = fr.bw;
+  const double* base = partial + (long long)fr.small_off * GCH;
+  for (int e = threadIdx.x; e < bw * bw; e += WG) {
+    const int i = e / bw, jj = e % bw;
+    if (symmetric && jj < i) continue;
+    double s = 0;
+    for (int ch = 0; ch < GCH; ++ch) s += base[(long long)ch * bw * bw + e];
+    M[i * ldm + jj] = s;
+    if (symmetric) M[jj * ldm + i] = s;
+  }
+  __syncthreads();
+  if (!symmetric) {   // symmetrise (A + A^T)/2
+    for (int e = threadIdx.x; e < bw * bw; e += WG) {
+      const int i = e / bw, jj = e % bw;
+      if (jj <= i) continue;
+      const double m = 0.5 * (M[i * ldm + jj] + M[jj * ldm + i]);
+      M[i * ldm + jj] = m;
+      M[jj * ldm + i] = m;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CholQR factor: G = R^T R (after unit-diagonal scaling), Q = R^-1
+// ---------------------------------------------------------------------------
+constexpr int SLD = SMAX + 1;
+
+__global__ __launch_bounds__(WG) void k_cholinv(
+    const FragDev* __restrict__ F, int nf, const double* __restrict__ partial,
+    double* __restrict__ Q, const int* __restrict__ active,
+    int* __restrict__ flags) {
+  const int j = blockIdx.x;
+  if (j >= nf) return;
+  if (active && !active[j]) return;
+  const FragDev& fr = F[j];
+  const int bw = fr.bw;
+  __shared__ double M[SMAX * SLD];
+  __shared__ double R[SMAX * SLD];
+  __shared__ double dsc[SMAX];
+  __shared__ int fail;
+  load_sym(fr, partial, M, SLD, 1);
+  // unit-diagonal scaling (column norms of X)
+  for (int i = threadIdx.x; i < bw; i += WG) {
+    const double d = M[i * SLD + i];
+    dsc[i] = d > 0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < bw * bw; e += WG) {
+    const int i = e / bw, jj = e % bw;
+    R[i * SLD + jj] = M[i * SLD + jj] * dsc[i] * dsc[jj];
+  }
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (attempt == 1) {
+      // shifted Cholesky: G + 1e-12 * bw * I (scaled matrix has unit diagonal)
+      for (int e = threadIdx.x; e < bw * bw; e += WG) {
+        const int i = e / bw, jj = e % bw;
+        R[i * SLD + jj] = M[i * SLD + jj] * dsc[i] * dsc[jj] +
+                          (i == jj ? 1e-12 * bw : 0.0);
+      }
+      if (threadIdx.x == 0) fail = 0;
+      __syncthreads();
+    }
+    for (int k = 0; k < bw; ++k) {
+      if (threadIdx.x == 0) {
+        const double d = R[k * SLD + k];
+        if (!(d > 1e-300)) fail = 1;
+        R[k * SLD + k] = sqrt(d > 1e-300 ? d : 1e-300);
+      }
+      __syncthreads();
+      const double piv = R[k * SLD + k];
+      for (int jj = k + 1 + threadIdx.x; jj < bw; jj += WG)
+        R[k * SLD + jj] /= piv;
+      __syncthreads();
+      const int m = bw - k - 1;
+      for (int e = threadIdx.x; e < m * m; e += WG) {
+        const int a = k + 1 + e / m, b = k + 1 + e % m;
+        if (b >= a) R[a * SLD + b] -= R[k * SLD + a] * R[k * SLD + b];
+      }
+      __syncthreads();
+    }
+    if (!fail) break;
+    if (threadIdx.x == 0 && flags) atomicOr(&flags[j], 1);
+  }
+  // inverse of the upper-triangular factor, one column per thread
+  double* Qj = Q + fr.small_off;
+  for (int col = threadIdx.x; col < bw; col += WG) {
+    // back substitution for column col of R^-1: entries row <= col
+    double x[SMAX];
+    for (int row = col; row >= 0; --row) {
+      double s = (row == col) ? 1.0 : 0.0;
+      for (int kk = row + 1; kk <= col; ++kk) s -= R[row * SLD + kk] * x[kk];
+      x[row] = s / R[row * SLD + row];
+    }
+    for (int row = 0; row < bw; ++row)
+      Qj[row * bw + col] = row <= col ? x[row] * dsc[row] : 0.0;
+  }
+}
+
+void cholinv(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
+             const int* active, int* flags) {
+  hipLaunchKernelGGL(k_cholinv, dim3(f->n_frag), dim3(WG), 0, s, f->d_frag,
+                     f->n_frag, G, Q, active, flags);
+  OFM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Rayleigh-Ritz: cyclic two-sided Jacobi on the symmetric projected matrix
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_rr_eig(
+    const FragDev* __restrict__ F, int nf, const double* __restrict__ partial,
+    double* __restrict__ Q, double* __restrict__ theta,
+    const int* __restrict__ active) {
+  const int j = blockIdx.x;
+  if (j >= nf) return;
+  if (active && !active[j]) return;
+  const FragDev& fr = F[j];
+  const int n = fr.bw;
+  __shared__ double A[SMAX * SLD];
+  __shared__ double U[SMAX * SLD];
+  __shared__ double cs[SMAX / 2], sn[SMAX / 2];
+  __shared__ int pp[SMAX / 2], qq[SMAX / 2];
+  __shared__ double red[WG / 64];
+  __shared__ double offn, totn;
+  load_sym(fr, partial, A, SLD, 0);
+  for (int e = threadIdx.x; e < n * n; e += WG)
+    U[(e / n) * SLD + e % n] = (e / n == e % n) ? 1.0 : 0.0;
+  const int n2 = n + (n & 1);       // round-robin over an even count
+  const int npair = n2 / 2;
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // off-diagonal and total Frobenius norms
+    double so = 0, st = 0;
+    for (int e = threadIdx.x; e < n * n; e += WG) {
+      const double a = A[(e / n) * SLD + e % n];
+      st += a * a;
+      if (e / n != e % n) so += a * a;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      so += __shfl_xor(so, o);
+      st += __shfl_xor(st, o);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = so;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int w = 0; w < WG / 64; ++w) t += red[w];
+      offn = t;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = st;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int w = 0; w < WG / 64; ++w) t += red[w];
+      totn = t;
+    }
+    __syncthreads();
+    if (!(offn > 1e-32 * totn) || n == 1) break;
+    for (int round = 0; round < n2 - 1; ++round) {
+      if (threadIdx.x < npair) {
+        const int i = threadIdx.x;
+        auto pos = [&](int m) { return m == 0 ? 0 : 1 + (m - 1 + round) % (n2 - 1); };
+        int p = pos(i), q = pos(n2 - 1 - i);
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1, s = 0;
+        if (q < n) {
+          const double apq = A[p * SLD + q];
+          if (apq != 0.0) {
+            const double app = A[p * SLD + p], aqq = A[q * SLD + q];
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0 ? 1.0 : -1.0) /
+                             (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pp[i] = p; qq[i] = q; cs[i] = c; sn[i] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = threadIdx.x; e < npair * n; e += WG) {
+        const int i = e / n, m = e % n;
+        const int p = pp[i], q = qq[i];
+        if (q >= n || sn[i] == 0.0) continue;
+        const double c = cs[i], s = sn[i];
+        const double ap = A[p * SLD + m], aq = A[q * SLD + m];
+        A[p * SLD + m] = c * ap - s * aq;
+        A[q * SLD + m] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A J, U <- U J
+      for (int e = threadIdx.x; e < npair * n; e += WG) {
+        const int i = e / n, m = e % n;
+        const int p = pp[i], q = qq[i];
+        if (q >= n || sn[i] == 0.0) continue;
+        const double c = cs[i], s = sn[i];
+        const double ap = A[m * SLD + p], aq = A[m * SLD + q];
+        A[m * SLD + p] = c * ap - s * aq;
+        A[m * SLD + q] = s * ap + c * aq;
+        const double up = U[m * SLD + p], uq = U[m * SLD + q];
+        U[m * SLD + p] = c * up - s * uq;
+        U[m * SLD + q] = s * up + c * uq;
+      }
+      __syncthreads();
+    }
+  }
+  // ascending order (stable by index), Q[k][rank] = U[k][i]
+  double* Qj = Q + fr.small_off;
+  for (int i = threadIdx.x; i < n; i += WG) {
+    const double d = A[i * SLD + i];
+    int rank = 0;
+    for (int m = 0; m < n; ++m) {
+      const double dm = A[m * SLD + m];
+      rank += (dm < d) || (dm == d && m < i);
+    }
+    theta[fr.th_off + rank] = d;
+    for (int k2 = 0; k2 < n; ++k2) Qj[k2 * n + rank] = U[k2 * SLD + i];
+  }
+}
+
+void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
+            double* theta, const int* active) {
+  hipLaunchKernelGGL(k_rr_eig, dim3(f->n_frag), dim3(WG), 0, s, f->d_frag,
+                     f->n_frag, G, Q, theta, active);
+  OFM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// rotation X <- X Q (and HX <- HX Q with residual partial sums)
+// ---------------------------------------------------------------------------
+template <typename T, int BMAX>
+__global__ __launch_bounds__(RCH) void k_rotate(
+    const FragDev* __restrict__ F, const int2* __restrict__ rt, int nrt,
+    T* __restrict__ X, T* __restrict__ HX, const double* __restrict__ Q,
+    const double* __restrict__ theta, double* __restrict__ res_partial,
+    const int* __restrict__ active, int upper) {
+  const int t = blockIdx.x;
+  if (t >= nrt) return;
+  const int j = rt[t].x;
+  if (active && !active[j]) return;
+  const FragDev& fr = F[j];
+  const int bw = fr.bw;
+  __shared__ double q[SMAX * SMAX];
+  __shared__ double th[SMAX];
+  __shared__ double red[RCH / 64][SMAX];
+  const double* Qj = Q + fr.small_off;
+  for (int e = threadIdx.x; e < bw * bw; e += RCH) q[e] = Qj[e];
+  if (HX)
+    for (int i = threadIdx.x; i < bw; i += RCH) th[i] = theta[fr.th_off + i];
+  __syncthreads();
+  const int p = rt[t].y * RCH + threadIdx.x;
+  const bool ok = p < fr.npts;
+  T* xp = X + fr.x_off + (ok ? p : 0);
+  T x[BMAX], hx[BMAX];
+#pragma unroll
+  for (int k = 0; k < BMAX; ++k) {
+    x[k] = (ok && k < bw) ? xp[(long long)k * fr.ld] : T(0);
+  }
+  T* hp = nullptr;
+  if (HX) {
+    hp = HX + fr.x_off + (ok ? p : 0);
+#pragma unroll
+    for (int k = 0; k < BMAX; ++k)
+      hx[k] = (ok && k < bw) ? hp[(long long)k * fr.ld] : T(0);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = 0; i < bw; ++i) {
+    double a = 0, h = 0;
+#pragma unroll
+    for (int k = 0; k < BMAX; ++k) {
+      if (k < bw && (!upper || k <= i)) {
+        const double qk = q[k * bw + i];
+        a += (double)x[k] * qk;
+        if (HX) h += (double)hx[k] * qk;
+      }
+    }
+    if (ok) xp[(long long)i * fr.ld] = (T)a;
+    if (HX) {
+      if (ok) hp[(long long)i * fr.ld] = (T)h;
+      double r = ok ? (double)((T)h) - th[i] * (double)((T)a) : 0.0;
+      r *= r;
+      for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+      if (lane == 0) red[wave][i] = r;
+    }
+  }
+  if (HX) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < bw; i += RCH) {
+      double s = 0;
+      for (int w = 0; w < RCH / 64; ++w) s += red[w][i];
+      res_partial[(long long)t * SMAX + i] = s;
+    }
+  }
+}
+
+template <typename T>
+void rotate(ofm_ctx* c, const ofm_frags* f, T* X, T* HX, const double* Q,
+            const double* theta, double* res_partial, const int* active,
+            int upper, double bytes, double flops) {
+  Timed tm(c, "rotate", bytes, flops);
+  const int b = f->max_bw;
+#define ROT(BM)                                                              \
+  hipLaunchKernelGGL((k_rotate<T, BM>), dim3(f->n_rtiles), dim3(RCH), 0,     \
+                     c->stream, f->d_frag, f->d_rtiles, f->n_rtiles, X, HX,  \
+                     Q, theta, res_partial, active, upper)
+  if (b <= 16) ROT(16);
+  else if (b <= 24) ROT(24);
+  else if (b <= 32) ROT(32);
+  else if (b <= 48) ROT(48);
+  else ROT(64);
+#undef ROT
+  OFM_HIP(hipGetLastError());
+}
+template void rotate<double>(ofm_ctx*, const ofm_frags*, double*, double*,
+                             const double*, const double*, double*,
+                             const int*, int, double, double);
+template void rotate<float>(ofm_ctx*, const ofm_frags*, float*, float*,
+                            const double*, const double*, double*,
+                            const int*, int, double, double);
+
+// ---------------------------------------------------------------------------
+// end of an outer iteration: residual norms, convergence, filter bounds
+// ---------------------------------------------------------------------------
+__global__ void k_finalize(const FragDev* __restrict__ F, int nf,
+                           const double* __restrict__ theta,
+                           const double* __restrict__ res_partial,
+                           FilterState* __restrict__ fs, int* __restrict__ active,
+                           int* __restrict__ iters,
+                           unsigned char* __restrict__ conv, double tol,
+                           int* __restrict__ n_active, double* __restrict__ res,
+                           double upper_kin) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nf) return;
+  if (!active[j]) return;
+  const FragDev& fr = F[j];
+  double worst = 0;
+  for (int i = 0; i < fr.bw; ++i) {
+    double s = 0;
+    for (int t = fr.rt_begin; t < fr.rt_begin + fr.rt_count; ++t)
+      s += res_partial[(long long)t * SMAX + i];
+    const double r = sqrt(s);
+    res[fr.th_off + i] = r;
+    if (i < fr.n_states) worst = fmax(worst, r);
+  }
+  iters[j] += 1;
+  FilterState st;
+  st.upper = upper_kin + fmax(fr.vmax, 0.0);
+  st.lower = theta[fr.th_off + fr.bw - 1];
+  st.scale = theta[fr.th_off];
+  st.pad = worst;
+  fs[j] = st;
+  if (worst <= tol || fr.bw == fr.npts) {
+    active[j] = 0;
+    conv[j] = 1;
+  } else {
+    atomicAdd(n_active, 1);
+  }
+}
+
+void finalize_iter(hipStream_t s, const ofm_frags* f, const double* theta,
+                   const double* res_partial, FilterState* fs, int* active,
+                   int* iters, unsigned char* conv, double tol, int* n_active,
+                   double* res) {
+  const double h = f->grid.h;
+  hipLaunchKernelGGL(k_finalize, dim3((f->n_frag + 127) / 128), dim3(128), 0,
+                     s, f->d_frag, f->n_frag, theta, res_partial, fs, active,
+                     iters, conv, tol, n_active, res, 8.0 / (h * h));
+  OFM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// sign gauge: the largest-|.| component of every state is positive
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(WG) void k_gauge(const FragDev* __restrict__ F,
+                                             const int2* __restrict__ st,
+                                             int nst, T* __restrict__ X) {
+  const int t = blockIdx.x;
+  if (t >= nst) return;
+  const FragDev& fr = F[st[t].x];
+  T* x = X + fr.x_off + (long long)st[t].y * fr.ld;
+  double best = -1;
+  int bi = 0x7fffffff;
+  for (int p = threadIdx.x; p < fr.npts; p += WG) {
+    const double a = fabs((double)x[p]);
+    if (a > best) { best = a; bi = p; }
+  }
+  __shared__ double sb[WG];
+  __shared__ int si[WG];
+  sb[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double b2 = sb[threadIdx.x + o];
+      const int i2 = si[threadIdx.x + o];
+      if (b2 > sb[threadIdx.x] || (b2 == sb[threadIdx.x] && i2 < si[threadIdx.x])) {
+        sb[threadIdx.x] = b2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = x[si[0]] < T(0);
+  __syncthreads();
+  if (flip)
+    for (int p = threadIdx.x; p < fr.npts; p += WG) x[p] = -x[p];
+}
+
+template <typename T>
+void gauge(hipStream_t s, const ofm_frags* f, T* X) {
+  hipLaunchKernelGGL(k_gauge<T>, dim3(f->n_stiles), dim3(WG), 0, s, f->d_frag,
+                     f->d_stiles, f->n_stiles, X);
+  OFM_HIP(hipGetLastError());
+}
+template void gauge<double>(hipStream_t, const ofm_frags*, double*);
+template void gauge<float>(hipStream_t, const ofm_frags*, float*);
+
+// ---------------------------------------------------------------------------
+// H|phi> with the whole-system H on the dilated box
+// ---------------------------------------------------------------------------
+// phi is zero outside box_j; walls (with the odd second ghost) only where the
+// point lies on a global-grid face.  V enters only inside the box.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_whole_h(
+    const FragDev* __restrict__ F, const int2* __restrict__ st, int nst,
+    const T* __restrict__ Vj, const T* __restrict__ X, T* __restrict__ HP,
+    double nh, int gnx, int gny, int gnz, int only_frag) {
+  const int t = blockIdx.y;
+  if (t >= nst) return;
+  const int j = st[t].x, i = st[t].y;
+  if (only_frag >= 0 && j != only_frag) return;
+  const FragDev& fr = F[j];
+  const T* x = X + fr.x_off + (long long)i * fr.ld;
+  T* out = HP + fr.hphi_off + (long long)i * fr.ldd;
+  const int bx = fr.dims[0], by = fr.dims[1], bz = fr.dims[2];
+  const int ox = fr.lo[0] - fr.dlo[0], oy = fr.lo[1] - fr.dlo[1],
+            oz = fr.lo[2] - fr.dlo[2];
+  for (int p = blockIdx.x * WG + threadIdx.x; p < fr.ndil;
+       p += gridDim.x * WG) {
+    const int dx = p % fr.ddims[0];
+    const int dy = (p / fr.ddims[0]) % fr.ddims[1];
+    const int dz = p / (fr.ddims[0] * fr.ddims[1]);
+    const int x0 = dx - ox, y0 = dy - oy, z0 = dz - oz;  // box-local
+    auto at = [&](int xx, int yy, int zz) -> double {
+      if (xx < 0 || yy < 0 || zz < 0 || xx >= bx || yy >= by || zz >= bz)
+        return 0.0;
+      return (double)x[xx + bx * (yy + by * zz)];
+    };
+    const double c = at(x0, y0, z0);
+    double lap = W0 * 3.0 * c +
+                 W1 * (at(x0 - 1, y0, z0) + at(x0 + 1, y0, z0) +
+                       at(x0, y0 - 1, z0) + at(x0, y0 + 1, z0) +
+                       at(x0, y0, z0 - 1) + at(x0, y0, z0 + 1)) +
+                 W2 * (at(x0 - 2, y0, z0) + at(x0 + 2, y0, z0) +
+                       at(x0, y0 - 2, z0) + at(x0, y0 + 2, z0) +
+                       at(x0, y0, z0 - 2) + at(x0, y0, z0 + 2));
+    const int gx = fr.dlo[0] + dx, gy = fr.dlo[1] + dy, gz = fr.dlo[2] + dz;
+    const int nfaces = (gx == 0) + (gx == gnx - 1) + (gy == 0) +
+                       (gy == gny - 1) + (gz == 0) + (gz == gnz - 1);
+    lap -= W2 * nfaces * c;
+    double v = 0;
+    if (x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 < bx && y0 < by && z0 < bz)
+      v = (double)Vj[fr.v_off + x0 + bx * (y0 + by * z0)];
+    out[p] = (T)(nh * lap + v * c);
+  }
+}
+
+template <typename T>
+void whole_h(ofm_ctx* c, const ofm_frags* f, const T* X, T* HPHI,
+             int only_frag) {
+  const T* Vj;
+  if constexpr (sizeof(T) == 8)
+    Vj = (const T*)f->d_v;
+  else
+    Vj = (const T*)f->d_v32;
+  int maxd = 0;
+  for (auto& d : f->host) maxd = std::max(maxd, d.ndil);
+  dim3 grid(std::min((maxd + WG - 1) / WG, 32), f->n_stiles);
+  const double h = f->grid.h;
+  hipLaunchKernelGGL(k_whole_h<T>, grid, dim3(WG), 0, c->stream, f->d_frag,
+                     f->d_stiles, f->n_stiles, Vj, X, HPHI, -0.5 / (h * h),
+                     f->grid.nx, f->grid.ny, f->grid.nz, only_frag);
+  OFM_HIP(hipGetLastError());
+}
+template void whole_h<double>(ofm_ctx*, const ofm_frags*, const double*,
+                              double*, int);
+template void whole_h<float>(ofm_ctx*, const ofm_frags*, const float*, float*,
+                             int);
+
+// ---------------------------------------------------------------------------
+// grouped pair contraction: one workgroup per (pair, S|H) block
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(WG) void k_pair(
+    const PairTask* __restrict__ tasks, int ntask, const T* __restrict__ PHI,
+    const T* __restrict__ HPHI, double* __restrict__ Hout,
+    double* __restrict__ Sout) {
+  const int ti = blockIdx.x;
+  if (ti >= ntask) return;
+  const PairTask tk = tasks[ti];
+  const T* A = PHI + tk.a_off;
+  const T* B = (tk.which ? HPHI : PHI) + tk.b_off;
+  double* C = (tk.which ? Hout : Sout) + tk.c_off;
+  const int ox = tk.om[0], oy = tk.om[1];
+  const int K = ox * oy * tk.om[2];
+  const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
+  __shared__ double blk[SMAX * SLD];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  for (int tile = wave; tile < nta * ntb; tile += WG / 64) {
+    const int ta = tile / ntb, tb = tile % ntb;
+    const int ra = ta * 16 + r, rb = tb * 16 + r;
+    const bool va = ra < tk.ma, vb = rb < tk.mb;
+    const T* pa = A + (long long)(va ? ra : 0) * tk.lda;
+    const T* pb = B + (long long)(vb ? rb : 0) * tk.ldb;
+    d4 acc = {0, 0, 0, 0};
+    // the trip count must be uniform across the wave: an MFMA reads every
+    // lane's operands, so lanes may not leave the loop early
+    for (int kb = 0; kb < K; kb += 16) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = kb + 4 * g + u;
+        a[u] = 0;
+        b[u] = 0;
+        if (k < K) {
+          const int x = k % ox, rr = k / ox;
+          const int y = rr % oy, z = rr / oy;
+          const int ia = (tk.a_org[0] + x) +
+                         tk.a_dims[0] * ((tk.a_org[1] + y) +
+                                         tk.a_dims[1] * (tk.a_org[2] + z));
+          const int ib = (tk.b_org[0] + x) +
+                         tk.b_dims[0] * ((tk.b_org[1] + y) +
+                                         tk.b_dims[1] * (tk.b_org[2] + z));
+          if (va) a[u] = (double)pa[ia];
+          if (vb) b[u] = (double)pb[ib];
+        }
+      }
+      acc = mfma_f64(a[0], b[0], acc);
+      acc = mfma_f64(a[1], b[1], acc);
+      acc = mfma_f64(a[2], b[2], acc);
+      acc = mfma_f64(a[3], b[3], acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = ta * 16 + g + 4 * i, col = tb * 16 + r;
+      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = acc[i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
+    const int i = e / tk.mb, m = e % tk.mb;
+    double v = blk[i * SLD + m];
+    if (tk.sym) v = 0.5 * (v + blk[m * SLD + i]);
+    C[e] = v;
+  }
+}
+
+template <typename T>
+void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
+                   int n_tasks, const T* phi, const T* hphi, double* H,
+                   double* S, double flops, double bytes) {
+  Timed tm(c, "elements", bytes, flops);
+  hipLaunchKernelGGL(k_pair<T>, dim3(n_tasks), dim3(WG), 0, c->stream, tasks,
+                     n_tasks, phi, hphi, H, S);
+  OFM_HIP(hipGetLastError());
+}
+template void pair_elements<double>(ofm_ctx*, const ofm_frags*,
+                                    const PairTask*, int, const double*,
+                                    const double*, double*, double*, double,
+                                    double);
+template void pair_elements<float>(ofm_ctx*, const ofm_frags*, const PairTask*,
+                                   int, const float*, const float*, double*,
+                                   double*, double, double);
+
+// ---------------------------------------------------------------------------
+// conversions and copies between the FP64 host layout and the arenas
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_convert(const double* __restrict__ in, T* __restrict__ out,
+                          long long n) {
+  for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < n;
+       i += (long long)gridDim.x * WG)
+    out[i] = (T)in[i];
+}
+template <typename T>
+__global__ void k_convert_back(const T* __restrict__ in,
+                               double* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < n;
+       i += (long long)gridDim.x * WG)
+    out[i] = (double)in[i];
+}
+template <typename T>
+void convert(hipStream_t s, const double* in, T* out, long long n) {
+  const int nb = (int)std::min<long long>((n + WG - 1) / WG, 4096);
+  hipLaunchKernelGGL(k_convert<T>, dim3(std::max(nb, 1)), dim3(WG), 0, s, in,
+                     out, n);
+  OFM_HIP(hipGetLastError());
+}
+template <typename T>
+void convert_back(hipStream_t s, const T* in, double* out, long long n) {
+  const int nb = (int)std::min<long long>((n + WG - 1) / WG, 4096);
+  hipLaunchKernelGGL(k_convert_back<T>, dim3(std::max(nb, 1)), dim3(WG), 0, s,
+                     in, out, n);
+  OFM_HIP(hipGetLastError());
+}
+template void convert<double>(hipStream_t, const double*, double*, long long);
+template void convert<float>(hipStream_t, const double*, float*, long long);
+template void convert_back<double>(hipStream_t, const double*, double*,
+                                   long long);
+template void convert_back<float>(hipStream_t, const float*, double*,
+                                  long long);
+
+}  // namespace k
+}  // namespace ofm

@@ -1,0 +1,261 @@
+// Internal declarations of the OFM library: device descriptors, handles and
+// kernel launchers.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ofm.h"
+
+namespace ofm {
+
+// ---------------------------------------------------------------------------
+// device-side fragment descriptor (plain old data, copied to HBM once)
+// ---------------------------------------------------------------------------
+// Face bits: which faces of the box lie on the global grid's walls.  The
+// fragment operator has a wall at every face; the whole-system operator only
+// at global-grid faces.
+enum : int { FACE_XLO = 1, FACE_XHI = 2, FACE_YLO = 4, FACE_YHI = 8,
+             FACE_ZLO = 16, FACE_ZHI = 32 };
+
+struct FragDev {
+  int lo[3], dims[3];     // box (global indices, x y z)
+  int dlo[3], ddims[3];   // box grown by 2 per side, clipped to the grid
+  int n_states;           // s_j
+  int bw;                 // eigensolver block width b_j (s_j + guard, <= n_j)
+  int npts;               // n_j
+  int ld;                 // leading dimension of box vectors (n_j rounded up)
+  int ndil;               // points of the dilated box
+  int ldd;                // leading dimension of dilated-box vectors
+  int gfaces;             // FACE_* bits of global-wall faces
+  int small_off;          // offset of this fragment's b_j x b_j matrices
+  int th_off;             // offset of this fragment's b_j Ritz values
+  int rt_begin, rt_count; // range of this fragment's point chunks (rotation)
+  long long v_off;        // offset of V restricted to the box (n_j values)
+  long long x_off;        // offset of the b_j block vectors (b_j * ld)
+  long long hphi_off;     // offset of the s_j dilated-box vectors (s_j * ldd)
+  long long basis_off;    // offset of the fragment's states in the basis
+  double vmax;            // max of V over the box (filter upper bound)
+};
+
+// one task of the grouped pair contraction: C (ma x mb) += A^T B over the
+// cuboid omega, A stored on box a, B on box b (both x-fastest)
+struct PairTask {
+  long long a_off, b_off;   // base offsets of the first vector of A and B
+  long long c_off;          // offset of the ma x mb row-major output block
+  int a_dims[3], b_dims[3]; // dims of the boxes A and B live on
+  int a_org[3], b_org[3];   // omega's corner relative to each box
+  int om[3];                // omega dims
+  int lda, ldb;             // vector strides of A and B
+  int ma, mb;
+  int sym;                  // 1: diagonal block, symmetrise on write
+  int which;                // 0: S block, 1: H block
+};
+
+// per-fragment Chebyshev filter state (device)
+struct FilterState {
+  double lower;   // lower end of the damped interval (largest block Ritz value)
+  double upper;   // upper bound of the spectrum
+  double scale;   // point normalised to 1 (smallest Ritz value)
+  double pad;
+};
+
+struct KernelStat {
+  long long launches = 0;
+  double ms = 0.0, bytes = 0.0, flops = 0.0;
+};
+
+}  // namespace ofm
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct ofm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  ofm_precision precision = OFM_FP64;
+  std::string err;
+  bool profiling = false;
+  std::map<std::string, ofm::KernelStat> stats;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  struct Pending { std::string fam; hipEvent_t a, b; double bytes, flops; };
+  std::vector<Pending> pending;
+  double t_solve = 0, t_elem = 0, t_global = 0;
+  void* blas = nullptr;    // rocblas_handle, created lazily
+  int live = 0;            // fragment / matrix handles made with this context
+  int n_cu = 256;
+};
+
+struct ofm_frags {
+  ofm_ctx* ctx = nullptr;
+  ofm_grid grid{};
+  int n_frag = 0;
+  int guard = 8;
+  std::vector<ofm::FragDev> host;      // descriptors (host copy)
+  std::vector<int> pair_j, pair_n;     // pair list j <= n
+  std::vector<long long> block_off;    // packed block offsets
+  long long n_values = 0;              // sum over pairs of s_j * s_n
+  long long n_basis = 0, total_points = 0;
+  long long v_total = 0, x_total = 0, hphi_total = 0;
+  int small_total = 0;
+  int max_bw = 0, max_plane = 0, max_states = 0;
+  ofm::FragDev* d_frag = nullptr;
+  double* d_v = nullptr;       // V restricted to boxes (FP64)
+  float* d_v32 = nullptr;      // same, FP32 (mixed form)
+  void* d_x = nullptr;         // block vectors (T)
+  void* d_p = nullptr;         // filter work vectors (T)
+  void* d_hx = nullptr;        // H times block vectors (T)
+  void* d_hphi = nullptr;      // whole-system H phi on dilated boxes (T)
+  // tile lists: (fragment, vector < b_j), (fragment, state < s_j) and
+  // (fragment, 256-point chunk)
+  int2* d_tiles = nullptr;
+  int n_tiles = 0;
+  int2* d_stiles = nullptr;
+  int n_stiles = 0;
+  int2* d_rtiles = nullptr;
+  int n_rtiles = 0;
+  int th_total = 0;
+  // eigensolver work buffers
+  double* d_G = nullptr;       // split-K Gram partials (16 per fragment)
+  double* d_Q = nullptr;       // b_j x b_j rotation per fragment
+  double* d_theta = nullptr;   // Ritz values (th_off indexing)
+  double* d_res = nullptr;     // residual norms (th_off indexing)
+  double* d_res_partial = nullptr;  // per rotation chunk, 64 entries
+  ofm::FilterState* d_fs = nullptr;
+  int* d_active = nullptr;
+  int* d_iters = nullptr;
+  unsigned char* d_conv = nullptr;
+  int* d_flags = nullptr;
+  int* d_nactive = nullptr;
+  std::vector<double> eps_host;  // sum_j s_j, valid when have_states
+  bool have_states = false;
+  bool imported = false;
+};
+
+struct ofm_mats {
+  ofm_ctx* ctx = nullptr;
+  const ofm_frags* frags = nullptr;
+  long long n_values = 0, n_basis = 0;
+  std::vector<int> pair_j, pair_n;
+  std::vector<long long> block_off;
+  std::vector<int> states;            // s_j per fragment
+  std::vector<long long> basis_off;   // per fragment
+  double* d_H = nullptr;
+  double* d_S = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// helpers shared by the host files
+// ---------------------------------------------------------------------------
+namespace ofm {
+
+struct Error {
+  ofm_status code;
+  std::string msg;
+};
+
+#define OFM_HIP(call)                                                       \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      throw ::ofm::Error{OFM_E_DEVICE, std::string(#call) + ": " +          \
+                                           hipGetErrorString(e_)};          \
+  } while (0)
+
+#define OFM_REQUIRE(cond, code, msg)                                        \
+  do {                                                                      \
+    if (!(cond)) throw ::ofm::Error{code, msg};                             \
+  } while (0)
+
+template <typename T>
+T* dev_alloc(size_t n) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess)
+    throw Error{OFM_E_NOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) +
+                                 " bytes failed"};
+  return static_cast<T*>(p);
+}
+
+inline void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// timed-launch bracket (no-op unless profiling is on)
+struct Timed {
+  ofm_ctx* c;
+  std::string fam;
+  double bytes, flops;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(ofm_ctx* ctx, const char* family, double by, double fl);
+  ~Timed();
+};
+void collect_stats(ofm_ctx* c);
+
+// geometry planner (planner.cpp)
+void plan_fragments(ofm_frags* f, const ofm_grid& g, int n_frag,
+                    const ofm_fragment_desc* fr, int guard);
+void plan_pairs(ofm_frags* f, const double* atom_xyz,
+                const long long* frag_atom_ptr, const int* frag_atom_idx,
+                double d_cut);
+std::vector<PairTask> plan_pair_tasks(const ofm_frags* f);
+
+// global solve (global_solve.cpp)
+void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
+                  double e_hi, int* n_kept, int* n_eig, double* E, double* C,
+                  double* s_min);
+void destroy_blas(ofm_ctx* c);
+
+// kernel launchers (kernels.hip)
+namespace k {
+void restrict_potential(hipStream_t s, const double* V, const ofm_grid& g,
+                        const ofm_frags* f);
+template <typename T>
+void init_random(hipStream_t s, const ofm_frags* f, T* X,
+                 unsigned long long seed);
+template <typename T>
+void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
+             T* out, const int2* tiles, int ntiles, const int* active,
+             int step, const FilterState* fs, int mode,
+             long long base_override, double alg_bytes, double flops);
+template <typename T>
+void gram(ofm_ctx* c, const ofm_frags* f, const T* A, const T* B, double* G,
+          const int* active, double bytes, double flops);
+void cholinv(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
+             const int* active, int* flags);
+void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
+            double* theta, const int* active);
+template <typename T>
+void rotate(ofm_ctx* c, const ofm_frags* f, T* X, T* HX, const double* Q,
+            const double* theta, double* res_partial, const int* active,
+            int upper, double bytes, double flops);
+void finalize_iter(hipStream_t s, const ofm_frags* f, const double* theta,
+                   const double* res_partial, FilterState* fs, int* active,
+                   int* iters, unsigned char* conv, double tol, int* n_active,
+                   double* res);
+template <typename T>
+void gauge(hipStream_t s, const ofm_frags* f, T* X);
+template <typename T>
+void whole_h(ofm_ctx* c, const ofm_frags* f, const T* X, T* HPHI,
+             int only_frag);
+template <typename T>
+void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
+                   int n_tasks, const T* phi, const T* hphi, double* H,
+                   double* S, double flops, double bytes);
+template <typename T>
+void convert(hipStream_t s, const double* in, T* out, long long n);
+template <typename T>
+void convert_back(hipStream_t s, const T* in, double* out, long long n);
+constexpr int GCH = 16;   // split-K chunks per fragment of the Gram kernel
+constexpr int RCH = 256;  // points per rotation chunk
+constexpr int SMAX = 64;  // largest block width
+}  // namespace k
+
+}  // namespace ofm

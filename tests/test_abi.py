@@ -1,0 +1,39 @@
+"""The C ABI library loads and exports every symbol the header declares
+(no GPU call), and the host-side planner's checks need no device."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ofm.h")
+LIB = os.path.join(ROOT, "paper_1011_4764_amd", "libofm.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ofm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_matches_binding_list():
+    from paper_1011_4764_amd.ofm import EXPORTS
+    assert sorted(EXPORTS) == _declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libofm.so not built")
+def test_library_exports_every_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], check=True,
+                         capture_output=True, text=True).stdout
+    syms = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    missing = [s for s in _declared() if s not in syms]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libofm.so not built")
+def test_library_loads_without_gpu():
+    import paper_1011_4764_amd as P
+    L = P.lib()
+    for name in _declared():
+        assert hasattr(L, name)
+    assert "gfx950" in P.ofm_version()

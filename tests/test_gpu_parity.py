@@ -1,0 +1,237 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.  Tolerances: fragment and window eigenvalues 1e-8 Ha
+(FP64), matrix elements 1e-10 relative to max|H| (FP64)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from ofm_inputs import box_system, tiny_chain
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1011_4764_amd")
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+def _build(ctx, s, V=None):
+    V = s.potential() if V is None else V
+    return P.ofm_build_fragments(
+        ctx, (s.grid.nx, s.grid.ny, s.grid.nz), s.grid.h, V, s.frag_lo,
+        s.frag_dims, s.frag_states, origin=s.grid.origin)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.ofm_create(0, None, P.OFM_FP64)
+    yield c
+    c.close()
+
+
+# ------------------------------------------------------------------ stencil
+
+@pytest.mark.parametrize("dims", [(12, 12, 12), (7, 5, 9), (48, 40, 3),
+                                  (1, 1, 6), (33, 31, 2), (64, 64, 2)])
+def test_fragment_stencil(ctx, dims):
+    """H_j x on random vectors vs the oracle's sparse fragment operator:
+    ragged boxes, planes from 1 to 4096 points, 1-point axes."""
+    _say("stencil", dims)
+    rng = np.random.default_rng(sum(dims))
+    shape = (dims[0] + 3, dims[1] + 2, dims[2] + 1)
+    V = rng.standard_normal(shape[::-1])
+    lo = (2, 1, 0)
+    s = box_system(shape, 0.45, [lo], [dims], [1], V=V)
+    f = _build(ctx, s)
+    n = int(np.prod(dims))
+    x = rng.standard_normal((3, n))
+    y = P.ofm_apply_fragment_h(ctx, f, 0, x)
+    H = O.hamiltonian_box(V, 0.45, lo, dims, walls="box")
+    ref = (H @ x.T).T
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    _say("  rel err", err)
+    assert err < 1e-13
+
+
+# ------------------------------------------------------------------ H|phi>
+
+def test_whole_h_with_imported_states(ctx, tiny0, tiny0_oracle):
+    s, r = tiny0, tiny0_oracle
+    _say("whole-system H phi, tiny")
+    f = _build(ctx, s)
+    for j in range(s.n_frag):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    for j in range(s.n_frag):
+        lo, dims, dlo, dd, ns = f.geometry(j)
+        assert tuple(dlo) == tuple(r.hphi_box[j][0])
+        assert tuple(dd) == tuple(r.hphi_box[j][1])
+        got = P.ofm_get_hphi(f, j)
+        ref = r.hphi[j].T
+        assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max() * 10
+
+
+# ------------------------------------------------------------------ elements
+
+def _oracle_blocks(r, pj, pn):
+    idx = {p: k for k, p in enumerate(r.pairs)}
+    Hs, Ss = [], []
+    for j, n in zip(pj, pn):
+        k = idx[(int(j), int(n))]
+        Hb = r.H_blocks[k]
+        Sb = r.S_blocks[k]
+        if j == n:
+            Hb = 0.5 * (Hb + Hb.T)
+            Sb = 0.5 * (Sb + Sb.T)
+        Hs.append(Hb.ravel())
+        Ss.append(Sb.ravel())
+    return np.concatenate(Hs), np.concatenate(Ss)
+
+
+def test_elements_imported_states_tiny(ctx, tiny0, tiny0_oracle):
+    s, r = tiny0, tiny0_oracle
+    _say("elements, tiny, imported oracle states")
+    f = _build(ctx, s)
+    for j in range(s.n_frag):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    pj, pn, off = f.pairs()
+    assert [(int(a), int(b)) for a, b in zip(pj, pn)] == r.pairs
+    m = P.ofm_matrix_elements(ctx, f)
+    H, S = P.ofm_mats_copy(m)
+    Hr, Sr = _oracle_blocks(r, pj, pn)
+    scale = np.abs(Hr).max()
+    assert np.abs(H - Hr).max() / scale < 1e-10
+    assert np.abs(S - Sr).max() < 1e-10
+    # global solve on the same blocks
+    g = P.ofm_solve_global(ctx, m, 1e-6)
+    ref = O.global_solve(r.H, r.S, 1e-6)
+    assert g["n_kept"] == ref["n_kept"]
+    assert np.abs(g["E"] - ref["E"]).max() < 1e-10
+
+
+def test_elements_random_boxes(ctx):
+    """Uneven boxes with halo-only pairs, ragged overlaps and differing state
+    counts; oracle states imported so the comparison is gauge-free."""
+    _say("elements, random uneven boxes")
+    rng = np.random.default_rng(21)
+    shape = (30, 22, 18)
+    V = -np.abs(rng.standard_normal(shape[::-1]))
+    nf = 7
+    dims = rng.integers(5, 12, size=(nf, 3))
+    lo = np.array([[rng.integers(0, shape[a] - dims[f_, a] + 1)
+                    for a in range(3)] for f_ in range(nf)])
+    states = rng.integers(1, 9, size=nf)
+    r = O.run(V, 0.5, lo, dims, states, solve=False)
+    s = box_system(shape, 0.5, lo, dims, states, V=V)
+    f = _build(ctx, s)
+    for j in range(nf):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    herr = []
+    for j in range(nf):
+        e, phi = P.ofm_get_states(f, j)
+        assert np.abs(phi - r.phi[j].T).max() == 0.0
+        herr.append(np.abs(P.ofm_get_hphi(f, j) - r.hphi[j].T).max())
+    _say("  hphi errors per fragment", herr)
+    assert max(herr) < 1e-12
+    pj, pn, off = f.pairs()
+    assert [(int(a), int(b)) for a, b in zip(pj, pn)] == r.pairs
+    m = P.ofm_matrix_elements(ctx, f)
+    H, S = P.ofm_mats_copy(m)
+    Hr, Sr = _oracle_blocks(r, pj, pn)
+    _say("  S err", np.abs(S - Sr).max(), "H err", np.abs(H - Hr).max())
+    assert np.abs(S - Sr).max() < 1e-10
+    assert np.abs(H - Hr).max() / np.abs(Hr).max() < 1e-10
+
+
+# ------------------------------------------------------------------ eigensolver
+
+def _subspace_gap(A, B):
+    """Largest principal-angle sine between column spaces (orthonormal)."""
+    sv = np.linalg.svd(A.T @ B, compute_uv=False)
+    return float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2)))
+
+
+def test_fragment_eigenpairs_tiny(ctx, tiny0, tiny0_oracle):
+    s, r = tiny0, tiny0_oracle
+    _say("eigensolver, tiny")
+    f = _build(ctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    _say("  iters", it, "status", st)
+    assert st == 0 and cv.all()
+    ref = np.concatenate(r.eps)
+    assert np.abs(eps - ref).max() < 1e-8
+    for j in range(s.n_frag):
+        e, phi = P.ofm_get_states(f, j)
+        assert np.abs(phi @ phi.T - np.eye(len(e))).max() < 1e-12
+        assert _subspace_gap(phi.T, r.phi[j]) < 1e-7
+        # gauge: largest component positive
+        idx = np.argmax(np.abs(phi), axis=1)
+        assert np.all(phi[np.arange(len(e)), idx] > 0)
+
+
+def test_end_to_end_tiny_window(ctx, tiny0, tiny0_oracle):
+    """Full path on the tiny chain: fragment states, elements, global solve;
+    window eigenvalues (below the lowest basis cutoff) within 1e-8 Ha."""
+    s, r = tiny0, tiny0_oracle
+    _say("end to end, tiny")
+    f = _build(ctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0
+    m = P.ofm_matrix_elements(ctx, f)
+    lo, hi = O.window_below_cutoff(r.eps)
+    g = P.ofm_solve_global(ctx, m, 1e-6, -1e30, hi)
+    ref = r.solve["window"]
+    _say("  window", len(g["E"]), "vs", len(ref))
+    assert len(g["E"]) == len(ref)
+    assert np.abs(g["E"] - ref).max() < 1e-8
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_end_to_end_tiny_seeds(ctx, seed):
+    s = tiny_chain(seed)
+    _say("end to end, tiny seed", seed)
+    V = s.potential()
+    r = O.run(V, s.grid.h, s.frag_lo, s.frag_dims, s.frag_states)
+    f = _build(ctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0
+    assert np.abs(eps - np.concatenate(r.eps)).max() < 1e-8
+    m = P.ofm_matrix_elements(ctx, f)
+    g = P.ofm_solve_global(ctx, m, 1e-6, -1e30, O.window_below_cutoff(r.eps)[1])
+    assert np.abs(g["E"] - r.solve["window"]).max() < 1e-8
+
+
+def test_v0_box_closed_form(ctx):
+    """V = 0: fragment eigenvalues equal the closed-form box spectrum
+    (degenerate levels: eigenvalues only)."""
+    _say("V=0 closed form")
+    dims = (10, 9, 8)
+    V = np.zeros((8, 9, 10))
+    s = box_system((10, 9, 8), 0.5, [(0, 0, 0)], [dims], [5], V=V)
+    f = _build(ctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0
+    assert np.abs(eps - O.box_spectrum(dims, 0.5, 5)).max() < 1e-9
+
+
+# ------------------------------------------------------------------ errors
+
+def test_error_paths(ctx, tiny0):
+    s = tiny0
+    _say("error paths")
+    with pytest.raises(P.OfmError) as e:
+        P.ofm_build_fragments(ctx, (24, 12, 12), 0.5, s.potential(),
+                              [[20, 0, 0]], [[12, 12, 12]], [6])
+    assert e.value.status == P.OFM_E_INVALID
+    Vbad = s.potential().copy()
+    Vbad[3, 3, 3] = np.nan
+    with pytest.raises(P.OfmError) as e:
+        P.ofm_build_fragments(ctx, (24, 12, 12), 0.5, Vbad, s.frag_lo,
+                              s.frag_dims, s.frag_states)
+    assert e.value.status == P.OFM_E_INVALID
+    f = _build(ctx, s)
+    with pytest.raises(P.OfmError) as e:
+        P.ofm_matrix_elements(ctx, f)
+    assert e.value.status == P.OFM_E_STATE
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f, max_iter=1)
+    assert st == P.OFM_E_NOCONV and not cv.all()
