@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--window", type=float, default=0.3,
                     help="energy window above the lowest OFM eigenvalue (Ha)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8,
+    ap.add_argument("--cpu-sample", type=int, default=64,
                     help="fragments in the oracle's timed sample")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="run a device copy of this size first (counter "
@@ -109,9 +109,10 @@ def main():
         n = int(args.calibrate_copy_gib * (1 << 30) // 4)
         a = torch.ones(n, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)   # one elementwise kernel: reads a, writes b
         torch.cuda.synchronize()
-        log(f"copy calibration: {n * 4} bytes read, {n * 4} bytes written")
+        log(f"copy calibration: elementwise kernel, {n * 4} bytes read, "
+            f"{n * 4} bytes written")
         del a, b
 
     stream = torch.cuda.current_stream(dev)
