@@ -221,7 +221,10 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   auto rayleigh_ritz = [&]() {
     double nb, npt, nb2;
     sums(nb, npt, nb2);
-    k::gram<T>(c, f, X, HX, f->d_G, f->d_active, 2 * nb * w, nb2 * 2.0);
+    if constexpr (sizeof(T) == 8)
+      k::gram<T>(c, f, X, HX, f->d_G, f->d_active, 2 * nb * w, nb2 * 2.0);
+    else   // mixed form: Rayleigh-Ritz product as split-BF16 x3 on MFMA
+      k::gram_x3(c, f, X, HX, f->d_G, f->d_active, 2 * nb * w, nb2 * 2.0);
     k::rr_eig(s, f, f->d_G, f->d_Q, f->d_theta, f->d_active);
     k::rotate<T>(c, f, X, HX, f->d_Q, f->d_theta, f->d_res_partial,
                  f->d_active, 0, 4 * nb * w, nb2 * 4.0);

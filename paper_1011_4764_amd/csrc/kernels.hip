@@ -316,7 +316,7 @@ __global__ __launch_bounds__(WG) void k_gram(
   const int bw = fr.bw;
   const int nt = (bw + 15) / 16;
   int cs = (fr.ld + GCH - 1) / GCH;
-  cs = (cs + 15) / 16 * 16;
+  cs = (cs + 31) / 32 * 32;
   const int kb = ch * cs;
   const int ke = min(kb + cs, fr.ld);
   double* out = partial + (long long)fr.small_off * GCH + (long long)ch * bw * bw;
@@ -363,6 +363,94 @@ template void gram<double>(ofm_ctx*, const ofm_frags*, const double*,
                            const double*, double*, const int*, double, double);
 template void gram<float>(ofm_ctx*, const ofm_frags*, const float*,
                           const float*, double*, const int*, double, double);
+
+// ---------------------------------------------------------------------------
+// mixed form: 3-term split-BF16 products on MFMA (16x16x32) with FP32
+// accumulation.  a = a_hi + a_lo with a_hi = bf16(a), a_lo = bf16(a - a_hi);
+// a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi (the dropped a_lo b_lo term is
+// ~2^-16 |a b|).  Each chunk's FP32 sums are stored as FP64 partials and the
+// partials are added in FP64 by the consumer.
+// Operand placement as for the FP64 kernel, 8 consecutive points per lane;
+// accumulator item i of lane l holds row 4 (l/16) + i, column l % 16.
+// ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(const float* v, bf8v& hi, bf8v& lo) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const __bf16 h = (__bf16)v[t];
+    hi[t] = h;
+    lo[t] = (__bf16)(v[t] - (float)h);
+  }
+}
+
+__device__ __forceinline__ f4v mfma_x3(const float* a, const float* b, f4v acc) {
+  bf8v ah, al, bh, bl;
+  split8(a, ah, al);
+  split8(b, bh, bl);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ __forceinline__ void load8(const float* p, float* o) {
+  const f4v u = *reinterpret_cast<const f4v*>(p);
+  const f4v w = *reinterpret_cast<const f4v*>(p + 4);
+  o[0] = u[0]; o[1] = u[1]; o[2] = u[2]; o[3] = u[3];
+  o[4] = w[0]; o[5] = w[1]; o[6] = w[2]; o[7] = w[3];
+}
+
+__global__ __launch_bounds__(WG) void k_gram_x3(
+    const FragDev* __restrict__ F, int nf, const float* __restrict__ A,
+    const float* __restrict__ B, double* __restrict__ partial,
+    const int* __restrict__ active) {
+  const int j = blockIdx.x / GCH, ch = blockIdx.x % GCH;
+  if (j >= nf) return;
+  if (active && !active[j]) return;
+  const FragDev& fr = F[j];
+  const int bw = fr.bw;
+  const int nt = (bw + 15) / 16;
+  int cs = (fr.ld + GCH - 1) / GCH;
+  cs = (cs + 31) / 32 * 32;
+  const int kb = ch * cs;
+  const int ke = min(kb + cs, fr.ld);
+  double* out = partial + (long long)fr.small_off * GCH + (long long)ch * bw * bw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  int tile = 0;
+  for (int ti = 0; ti < nt; ++ti) {
+    for (int tj = 0; tj < nt; ++tj, ++tile) {
+      if ((tile & 3) != wave) continue;
+      const int ra = ti * 16 + r, rb = tj * 16 + r;
+      const bool va = ra < bw, vb = rb < bw;
+      const float* pa = A + fr.x_off + (long long)(va ? ra : 0) * fr.ld;
+      const float* pb = B + fr.x_off + (long long)(vb ? rb : 0) * fr.ld;
+      f4v acc = {0, 0, 0, 0};
+      // kb and ke are multiples of 32: uniform trip count across the wave
+      for (int k = kb + 8 * g; k < ke; k += 32) {
+        float a[8] = {0, 0, 0, 0, 0, 0, 0, 0}, b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (va) load8(pa + k, a);
+        if (vb) load8(pb + k, b);
+        acc = mfma_x3(a, b, acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ti * 16 + 4 * g + i, col = tj * 16 + r;
+        if (row < bw && col < bw) out[row * bw + col] = (double)acc[i];
+      }
+    }
+  }
+}
+
+void gram_x3(ofm_ctx* c, const ofm_frags* f, const float* A, const float* B,
+             double* G, const int* active, double bytes, double flops) {
+  Timed tm(c, "gram", bytes, flops);
+  hipLaunchKernelGGL(k_gram_x3, dim3(f->n_frag * GCH), dim3(WG), 0, c->stream,
+                     f->d_frag, f->n_frag, A, B, G, active);
+  OFM_HIP(hipGetLastError());
+}
 
 // sum the split-K partials of fragment fr into a symmetric LDS matrix
 __device__ void load_sym(const FragDev& fr, const double* __restrict__ partial,
@@ -929,13 +1017,95 @@ __global__ __launch_bounds__(WG) void k_pair(
   }
 }
 
+// mixed form of the pair contraction: split-BF16 x3 MFMA, FP32 sums flushed
+// into FP64 every 1024 points; diagonal S blocks are the identity (the
+// states are orthonormalised in FP64, and the dropped a_lo b_lo term would
+// bias their diagonal by ~2^-18)
+__global__ __launch_bounds__(WG) void k_pair_x3(
+    const PairTask* __restrict__ tasks, int ntask, const float* __restrict__ PHI,
+    const float* __restrict__ HPHI, double* __restrict__ Hout,
+    double* __restrict__ Sout) {
+  const int ti = blockIdx.x;
+  if (ti >= ntask) return;
+  const PairTask tk = tasks[ti];
+  double* C = (tk.which ? Hout : Sout) + tk.c_off;
+  if (tk.sym && tk.which == 0) {
+    for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG)
+      C[e] = (e / tk.mb == e % tk.mb) ? 1.0 : 0.0;
+    return;
+  }
+  const float* A = PHI + tk.a_off;
+  const float* B = (tk.which ? HPHI : PHI) + tk.b_off;
+  const int ox = tk.om[0], oy = tk.om[1];
+  const int K = ox * oy * tk.om[2];
+  const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
+  __shared__ double blk[SMAX * SLD];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  for (int tile = wave; tile < nta * ntb; tile += WG / 64) {
+    const int ta = tile / ntb, tb = tile % ntb;
+    const int ra = ta * 16 + r, rb = tb * 16 + r;
+    const bool va = ra < tk.ma, vb = rb < tk.mb;
+    const float* pa = A + (long long)(va ? ra : 0) * tk.lda;
+    const float* pb = B + (long long)(vb ? rb : 0) * tk.ldb;
+    f4v acc = {0, 0, 0, 0};
+    double tot[4] = {0, 0, 0, 0};
+    int since = 0;
+    for (int kb = 0; kb < K; kb += 32) {   // uniform trip count
+      float a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = kb + 8 * g + u;
+        a[u] = 0.f;
+        b[u] = 0.f;
+        if (k < K) {
+          const int x = k % ox, rr = k / ox;
+          const int y = rr % oy, z = rr / oy;
+          const int ia = (tk.a_org[0] + x) +
+                         tk.a_dims[0] * ((tk.a_org[1] + y) +
+                                         tk.a_dims[1] * (tk.a_org[2] + z));
+          const int ib = (tk.b_org[0] + x) +
+                         tk.b_dims[0] * ((tk.b_org[1] + y) +
+                                         tk.b_dims[1] * (tk.b_org[2] + z));
+          if (va) a[u] = pa[ia];
+          if (vb) b[u] = pb[ib];
+        }
+      }
+      acc = mfma_x3(a, b, acc);
+      if (++since == 32) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tot[i] += (double)acc[i];
+        acc = f4v{0, 0, 0, 0};
+        since = 0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      tot[i] += (double)acc[i];
+      const int row = ta * 16 + 4 * g + i, col = tb * 16 + r;
+      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = tot[i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
+    const int i = e / tk.mb, m = e % tk.mb;
+    double v = blk[i * SLD + m];
+    if (tk.sym) v = 0.5 * (v + blk[m * SLD + i]);
+    C[e] = v;
+  }
+}
+
 template <typename T>
 void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
                    int n_tasks, const T* phi, const T* hphi, double* H,
                    double* S, double flops, double bytes) {
   Timed tm(c, "elements", bytes, flops);
-  hipLaunchKernelGGL(k_pair<T>, dim3(n_tasks), dim3(WG), 0, c->stream, tasks,
-                     n_tasks, phi, hphi, H, S);
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL(k_pair<T>, dim3(n_tasks), dim3(WG), 0, c->stream, tasks,
+                       n_tasks, phi, hphi, H, S);
+  else
+    hipLaunchKernelGGL(k_pair_x3, dim3(n_tasks), dim3(WG), 0, c->stream, tasks,
+                       n_tasks, phi, hphi, H, S);
   OFM_HIP(hipGetLastError());
 }
 template void pair_elements<double>(ofm_ctx*, const ofm_frags*,

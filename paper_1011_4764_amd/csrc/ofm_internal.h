@@ -228,6 +228,8 @@ void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
 template <typename T>
 void gram(ofm_ctx* c, const ofm_frags* f, const T* A, const T* B, double* G,
           const int* active, double bytes, double flops);
+void gram_x3(ofm_ctx* c, const ofm_frags* f, const float* A, const float* B,
+             double* G, const int* active, double bytes, double flops);
 void cholinv(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
              const int* active, int* flags);
 void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,

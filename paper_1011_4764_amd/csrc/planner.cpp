@@ -64,9 +64,9 @@ void plan_fragments(ofm_frags* f, const ofm_grid& g, int n_frag,
     d.n_states = s;
     d.npts = (int)npts;
     d.bw = (int)std::min<long long>(s + guard, std::min<long long>(npts, 64));
-    d.ld = round_up(d.npts, 16);
+    d.ld = round_up(d.npts, 32);
     d.ndil = d.ddims[0] * d.ddims[1] * d.ddims[2];
-    d.ldd = round_up(d.ndil, 16);
+    d.ldd = round_up(d.ndil, 32);
     d.gfaces = (d.lo[0] == 0 ? FACE_XLO : 0) |
                (d.lo[0] + d.dims[0] == N[0] ? FACE_XHI : 0) |
                (d.lo[1] == 0 ? FACE_YLO : 0) |

@@ -1,0 +1,122 @@
+"""GPU parity of the mixed form (FP32 vectors and stencil, split-BF16 x3
+MFMA contractions, FP64 Cholesky / small eigensolves / global solve) against
+the FP64 oracle: eigenvalues within 1e-5 Ha, matrix elements within 1e-6
+relative to max|H|, diagonal S blocks exactly the identity."""
+import numpy as np
+import pytest
+
+import oracle as O
+from ofm_inputs import box_system, tiny_chain
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1011_4764_amd")
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+def _build(ctx, s, V=None):
+    V = s.potential() if V is None else V
+    return P.ofm_build_fragments(
+        ctx, (s.grid.nx, s.grid.ny, s.grid.nz), s.grid.h, V, s.frag_lo,
+        s.frag_dims, s.frag_states, origin=s.grid.origin)
+
+
+@pytest.fixture(scope="module")
+def mctx():
+    c = P.ofm_create(0, None, P.OFM_MIXED_BF16X3)
+    yield c
+    c.close()
+
+
+def test_mixed_stencil(mctx):
+    _say("mixed stencil")
+    rng = np.random.default_rng(3)
+    dims = (13, 11, 9)
+    shape = (16, 12, 10)
+    V = -np.abs(rng.standard_normal(shape[::-1]))
+    s = box_system(shape, 0.5, [(1, 1, 0)], [dims], [1], V=V)
+    f = _build(mctx, s)
+    x = rng.standard_normal((2, int(np.prod(dims))))
+    y = P.ofm_apply_fragment_h(mctx, f, 0, x)
+    ref = (O.hamiltonian_box(V, 0.5, (1, 1, 0), dims) @ x.T).T
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    _say("  rel err", err)
+    assert err < 2e-6
+
+
+def _blocks(r, pj, pn):
+    idx = {p: k for k, p in enumerate(r.pairs)}
+    Hs, Ss, diag = [], [], []
+    for j, n in zip(pj, pn):
+        k = idx[(int(j), int(n))]
+        Hb, Sb = r.H_blocks[k], r.S_blocks[k]
+        if j == n:
+            Hb = 0.5 * (Hb + Hb.T)
+            Sb = 0.5 * (Sb + Sb.T)
+        Hs.append(Hb.ravel())
+        Ss.append(Sb.ravel())
+        diag.append(np.full(Sb.size, j == n))
+    return np.concatenate(Hs), np.concatenate(Ss), np.concatenate(diag)
+
+
+@pytest.mark.parametrize("case", ["tiny", "random"])
+def test_mixed_elements_imported_states(mctx, case):
+    _say("mixed elements", case)
+    if case == "tiny":
+        s = tiny_chain(0)
+        V = s.potential()
+        lo, dims, st = s.frag_lo, s.frag_dims, s.frag_states
+        shape = (s.grid.nx, s.grid.ny, s.grid.nz)
+    else:
+        rng = np.random.default_rng(21)
+        shape = (30, 22, 18)
+        V = -np.abs(rng.standard_normal(shape[::-1]))
+        dims = rng.integers(5, 12, size=(7, 3))
+        lo = np.array([[rng.integers(0, shape[a] - dims[f_, a] + 1)
+                        for a in range(3)] for f_ in range(7)])
+        st = rng.integers(1, 9, size=7)
+    r = O.run(V, 0.5, lo, dims, st, solve=False)
+    s = box_system(shape, 0.5, lo, dims, st, V=V)
+    f = _build(mctx, s)
+    for j in range(len(st)):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    pj, pn, off = f.pairs()
+    m = P.ofm_matrix_elements(mctx, f)
+    H, S = P.ofm_mats_copy(m)
+    Hr, Sr, dg = _blocks(r, pj, pn)
+    eh = np.abs(H - Hr).max() / np.abs(Hr).max()
+    es = np.abs(S - Sr)[~dg].max() if (~dg).any() else 0.0
+    _say("  H rel", eh, "S offdiag", es)
+    assert eh < 1e-6
+    assert es < 1e-6
+    # diagonal S blocks are the identity exactly
+    k = 0
+    for j, n in zip(pj, pn):
+        sz = int(st[j]) * int(st[n])
+        if j == n:
+            assert np.array_equal(S[k:k + sz].reshape(st[j], st[j]),
+                                  np.eye(int(st[j])))
+        k += sz
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mixed_end_to_end_tiny(mctx, seed):
+    s = tiny_chain(seed)
+    _say("mixed end to end, tiny seed", seed)
+    V = s.potential()
+    r = O.run(V, s.grid.h, s.frag_lo, s.frag_dims, s.frag_states)
+    f = _build(mctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(mctx, f)
+    _say("  status", st, "iters", it)
+    assert st == 0
+    assert np.abs(eps - np.concatenate(r.eps)).max() < 1e-5
+    m = P.ofm_matrix_elements(mctx, f)
+    g = P.ofm_solve_global(mctx, m, 1e-6, -1e30,
+                           O.window_below_cutoff(r.eps)[1])
+    err = np.abs(g["E"] - r.solve["window"]).max()
+    _say("  window", len(g["E"]), "max err", err)
+    assert len(g["E"]) == len(r.solve["window"])
+    assert err < 1e-5
