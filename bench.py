@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--window", type=float, default=0.3,
                     help="energy window above the lowest OFM eigenvalue (Ha)")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="eigensolver residual bound (0: the form's default)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-form comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="fragments in the oracle's timed sample")
@@ -116,57 +120,70 @@ def main():
         del a, b
 
     stream = torch.cuda.current_stream(dev)
-    prec = P.OFM_FP64 if args.precision == "fp64" else P.OFM_MIXED_BF16X3
-    ctx = P.ofm_create(0, stream.cuda_stream, prec)
     V_dev = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
     torch.cuda.synchronize()
 
-    last = {}
+    def run_form(precision, tol, steps, warmup, profile):
+        prec = P.OFM_FP64 if precision == "fp64" else P.OFM_MIXED_BF16X3
+        ctx = P.ofm_create(0, stream.cuda_stream, prec)
+        last = {}
 
-    def step():
-        f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V_dev,
-                                  system.frag_lo, system.frag_dims,
-                                  system.frag_states, origin=g.origin)
-        st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
-        m = P.ofm_matrix_elements(ctx, f)
-        gs = P.ofm_solve_global(ctx, m, 1e-6)
-        E = gs["E"]
-        win = E[E <= E[0] + args.window]
-        last.update(status=st, iters=it, conv=cv, n_pairs=f.n_pairs,
-                    n_values=m.n_values, window=win, n_kept=gs["n_kept"],
-                    stages=ctx.stage_times())
-        m.close()
-        f.close()
+        def step():
+            f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V_dev,
+                                      system.frag_lo, system.frag_dims,
+                                      system.frag_states, origin=g.origin)
+            st, eps, it, cv = P.ofm_solve_fragments(ctx, f, tol=tol)
+            m = P.ofm_matrix_elements(ctx, f)
+            gs = P.ofm_solve_global(ctx, m, 1e-6)
+            E = gs["E"]
+            last.update(status=st, iters=it, conv=cv, n_pairs=f.n_pairs,
+                        n_values=m.n_values, E=E, n_kept=gs["n_kept"],
+                        stages=ctx.stage_times())
+            m.close()
+            f.close()
 
-    for w in range(args.warmup):
-        t = time.perf_counter()
-        step()
-        log(f"warmup {w}: {time.perf_counter() - t:.3f} s, status "
-            f"{last['status']}, iters max {int(last['iters'].max())}")
-    ctx.reset_stats()
-    ctx.set_profiling(True)
-    stage_sum = {"solve_ms": 0.0, "elements_ms": 0.0, "global_ms": 0.0}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step()
+        for w in range(warmup):
+            t = time.perf_counter()
+            step()
+            log(f"{precision} tol {tol or 'default'} warmup {w}: "
+                f"{time.perf_counter() - t:.3f} s, status {last['status']}, "
+                f"iters max {int(last['iters'].max())}")
+        ctx.reset_stats()
+        ctx.set_profiling(profile)
+        stage_sum = {"solve_ms": 0.0, "elements_ms": 0.0, "global_ms": 0.0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step()
+            for key in stage_sum:
+                stage_sum[key] += last["stages"][key]
+            log(f"{precision} step {k} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ctx.set_profiling(False)
+        res = {"ms_step": 1000.0 * elapsed / steps, "last": last}
         for key in stage_sum:
-            stage_sum[key] += last["stages"][key]
-        log(f"step {k} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.set_profiling(False)
-    ms_step = 1000.0 * elapsed / args.steps
-    st = ctx.kernel_stats("stencil")
-    el = ctx.kernel_stats("elements")
-    gr = ctx.kernel_stats("gram")
+            res[key] = stage_sum[key] / steps
+        res["stencil"] = ctx.kernel_stats("stencil")
+        res["elements"] = ctx.kernel_stats("elements")
+        res["gram"] = ctx.kernel_stats("gram")
+        ctx.close()
+        return res
+
+    main_form = run_form(args.precision, args.tol, args.steps, args.warmup,
+                         True)
+    last = main_form["last"]
+    ms_step = main_form["ms_step"]
+    st, el, gr = main_form["stencil"], main_form["elements"], main_form["gram"]
     avg_ms = st["ms"] / max(st["launches"], 1)
     bytes_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    solve_ms = stage_sum["solve_ms"] / args.steps
-    elem_ms = stage_sum["elements_ms"] / args.steps
-    glob_ms = stage_sum["global_ms"] / args.steps
+    solve_ms = main_form["solve_ms"]
+    elem_ms = main_form["elements_ms"]
+    glob_ms = main_form["global_ms"]
     n_elem = 2 * last["n_values"]
+    E = last["E"]
+    window = E[E <= E[0] + args.window]
     out = {
         "metric": "fragment eigenstates/s + H,S elements/s; mixed vs FP64 at 1e-5 Ha",
         "value": n_states / (ms_step * 1e-3),
@@ -191,7 +208,8 @@ def main():
             "outer_iterations_max": int(last["iters"].max()),
             "outer_iterations_mean": float(last["iters"].mean()),
             "all_converged": bool(last["conv"].all()),
-            "window_eigenvalues": int(len(last["window"])),
+            "window_Ha": [float(window[0]), float(window[-1])],
+            "window_eigenvalues": int(len(window)),
             "basis_kept": int(last["n_kept"]),
         },
         "roofline": {
@@ -214,7 +232,30 @@ def main():
                                             / FP64_PEAK_TFS) if el["ms"] else 0},
         },
     }
-    ctx.close()
+    if args.precision == "fp64" and not args.no_mixed:
+        # the same workload in the mixed form, and FP64 stopped at the mixed
+        # tolerance (equal accuracy); window eigenvalues compared to FP64's
+        mx = run_form("mixed", 0.0, args.steps, args.warmup, False)
+        eq = run_form("fp64", 2e-5, args.steps, args.warmup, False)
+        Em = mx["last"]["E"]
+        nw = len(window)
+        dE = float(np.abs(Em[:nw] - window).max())
+        out["mixed"] = {
+            "value": n_states / (mx["ms_step"] * 1e-3),
+            "ms_per_step": mx["ms_step"],
+            "fragment_eigenstates_per_s": n_states / (mx["solve_ms"] * 1e-3),
+            "hs_elements_per_s": 2 * mx["last"]["n_values"] / (mx["elements_ms"] * 1e-3),
+            "solve_ms": mx["solve_ms"], "elements_ms": mx["elements_ms"],
+            "global_ms": mx["global_ms"],
+            "outer_iterations_max": int(mx["last"]["iters"].max()),
+            "all_converged": bool(mx["last"]["conv"].all()),
+            "window_max_abs_dE_vs_fp64_Ha": dE,
+            "within_1e-5_Ha": bool(dE <= 1e-5),
+            "fragment_stage_speedup_vs_fp64_own_tol": solve_ms / mx["solve_ms"],
+            "fragment_stage_speedup_vs_fp64_equal_tol": eq["solve_ms"] / mx["solve_ms"],
+            "whole_step_speedup_vs_fp64": ms_step / mx["ms_step"],
+            "fp64_at_2e-5_solve_ms": eq["solve_ms"],
+        }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_sample, args.seed)

@@ -94,7 +94,10 @@ typedef struct {
   int degree;            /* Chebyshev filter degree per iteration [32]       */
   unsigned long long seed; /* start-vector seed [0]                          */
   int use_graph;         /* 1: replay each iteration as a HIP graph [1]      */
-  int autotune;          /* 1: time tile variants once per shape class [0]   */
+  int autotune;          /* >= 0: time the stencil variants on the first
+                            filter sweep, once per (precision, largest box
+                            plane) and context, and keep the fastest [on];
+                            -1: use the fixed default variant              */
 } ofm_solve_opts;
 
 typedef struct ofm_ctx ofm_ctx;
@@ -185,6 +188,12 @@ ofm_status ofm_get_hphi(const ofm_frags* f, int j, double* hphi);
    host in and out): the stencil of the eigensolver, exposed for checking. */
 ofm_status ofm_apply_fragment_h(ofm_ctx* ctx, ofm_frags* f, int j, int nvec,
                                 const double* x, double* y);
+
+/* Pin the stencil variant used for fragments f (0..2: 256, 512, 1024 plane
+   points per workgroup in FP64; 512, 1024, 2048 in the mixed form), or -1 to
+   let ofm_solve_fragments pick by timing the variants (the default).  Every
+   variant computes identical values. */
+ofm_status ofm_set_stencil_variant(ofm_frags* f, int variant);
 
 /* ---- matrix elements (Sec. II) ------------------------------------------ */
 

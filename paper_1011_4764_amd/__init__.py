@@ -9,6 +9,6 @@ from .ofm import (  # noqa: F401
     EXPORTS, OFM_FP64, OFM_MIXED_BF16X3, OFM_E_NOCONV, OFM_E_SINGULAR,
     OFM_E_INVALID, OFM_E_STATE, Context, Fragments, Mats, OfmError, lib,
     ofm_apply_fragment_h, ofm_build_fragments, ofm_create, ofm_get_hphi,
-    ofm_get_states, ofm_matrix_elements, ofm_mats_copy, ofm_set_states,
+    ofm_get_states, ofm_matrix_elements, ofm_mats_copy, ofm_set_states, ofm_set_stencil_variant,
     ofm_solve_fragments, ofm_solve_global, ofm_version, unpack_blocks,
 )

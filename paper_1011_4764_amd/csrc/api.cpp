@@ -156,7 +156,8 @@ T* arena(void* p) {
 
 void free_frags(ofm_frags* f) {
   void* ptrs[] = {f->d_frag, f->d_v, f->d_v32, f->d_x, f->d_p, f->d_hx,
-                  f->d_hphi, f->d_tiles, f->d_stiles, f->d_rtiles, f->d_G,
+                  f->d_hphi, f->d_tiles[0], f->d_tiles[1], f->d_tiles[2],
+                  f->d_stiles, f->d_rtiles, f->d_G,
                   f->d_Q, f->d_theta, f->d_res, f->d_res_partial, f->d_fs,
                   f->d_active, f->d_iters, f->d_conv, f->d_flags,
                   f->d_nactive};
@@ -170,6 +171,7 @@ struct SolveCfg {
   double tol;
   int max_iter, degree;
   unsigned long long seed;
+  bool autotune;
 };
 
 template <typename T>
@@ -190,6 +192,27 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   k::init_random<T>(s, f, X, cfg.seed);
 
   std::vector<int> act(nf, 1);
+  // stencil variant: cached per (precision, largest plane), else timed on
+  // the first filter sweep (steps 2..7 cycle through the variants; every
+  // variant computes identical values, so tuning never changes results)
+  const long long key = (long long)sizeof(T) * 1000000000LL + f->max_plane;
+  int var = f->variant;
+  bool tuning = false;
+  if (var < 0) {
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+      var = it->second;
+    } else {
+      var = 1;
+      tuning = cfg.autotune && cfg.degree >= 8;
+    }
+  }
+  hipEvent_t tev[6][2] = {};
+  if (tuning)
+    for (auto& e : tev) {
+      OFM_HIP(hipEventCreate(&e[0]));
+      OFM_HIP(hipEventCreate(&e[1]));
+    }
   // algorithmic bytes / flops of one pass over the active fragments
   auto sums = [&](double& nb, double& npt, double& nb2) {
     nb = npt = nb2 = 0;
@@ -214,8 +237,9 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   auto apply_plain = [&]() {
     double nb, npt, nb2;
     sums(nb, npt, nb2);
-    k::apply_h<T>(c, f, X, X, HX, f->d_tiles, f->n_tiles, f->d_active, 0,
-                  f->d_fs, 0, -1, (2 * nb + npt) * w, 28.0 * nb);
+    k::apply_h<T>(c, f, X, X, HX, f->d_tiles[var], f->n_tiles[var], var,
+                  f->d_active, 0, f->d_fs, 0, -1, (2 * nb + npt) * w,
+                  28.0 * nb);
   };
   int n_active = nf;
   auto rayleigh_ritz = [&]() {
@@ -251,13 +275,39 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       const T* prev = odd ? P : X;
       T* out = odd ? P : X;
       const double by = (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
-      k::apply_h<T>(c, f, in, prev, out, f->d_tiles, f->n_tiles, f->d_active,
-                    step, f->d_fs, 1, -1, by, 32.0 * nb);
+      int sv = var;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (tuning && step >= 2 && step < 8) {
+        sv = (step - 2) % k::NVARIANT;
+        e0 = tev[step - 2][0];
+        e1 = tev[step - 2][1];
+      }
+      k::apply_h<T>(c, f, in, prev, out, f->d_tiles[sv], f->n_tiles[sv], sv,
+                    f->d_active, step, f->d_fs, 1, -1, by, 32.0 * nb, e0, e1);
     }
     cholqr();
     apply_plain();
     rayleigh_ritz();
+    if (tuning) {
+      double tsum[k::NVARIANT] = {0, 0, 0};
+      for (int i = 0; i < 6; ++i) {
+        float ms = 0;
+        OFM_HIP(hipEventElapsedTime(&ms, tev[i][0], tev[i][1]));
+        tsum[i % k::NVARIANT] += ms;
+      }
+      int best = 0;
+      for (int v = 1; v < k::NVARIANT; ++v)
+        if (tsum[v] < tsum[best]) best = v;
+      var = best;
+      c->tuned[key] = best;
+      tuning = false;
+      for (auto& e : tev) {
+        (void)hipEventDestroy(e[0]);
+        (void)hipEventDestroy(e[1]);
+      }
+    }
   }
+  f->variant = var;
   // states: the lowest s_j Ritz vectors, sign gauge, whole-system H phi
   k::gauge<T>(s, f, X);
   k::whole_h<T>(c, f, X, arena<T>(f->d_hphi), -1);
@@ -373,26 +423,31 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
       plan_fragments(f, *grid, n_frag, frags, 8);
       plan_pairs(f, atom_xyz, frag_atom_ptr, frag_atom_idx, d_cut);
       // tile lists
-      std::vector<int2> tiles, stiles, rtiles;
+      std::vector<int2> stiles, rtiles;
       int th = 0;
       for (int j = 0; j < n_frag; ++j) {
         auto& d = f->host[j];
         d.th_off = th;
         th += d.bw;
-        for (int v = 0; v < d.bw; ++v) tiles.push_back(make_int2(j, v));
         for (int i = 0; i < d.n_states; ++i) stiles.push_back(make_int2(j, i));
         d.rt_begin = (int)rtiles.size();
         d.rt_count = (d.npts + k::RCH - 1) / k::RCH;
         for (int ch = 0; ch < d.rt_count; ++ch) rtiles.push_back(make_int2(j, ch));
       }
       f->th_total = th;
-      f->n_tiles = (int)tiles.size();
       f->n_stiles = (int)stiles.size();
       f->n_rtiles = (int)rtiles.size();
       hipStream_t s = c->stream;
       const size_t w = wsize(c);
       f->d_frag = dev_alloc<FragDev>(n_frag);
-      f->d_tiles = dev_alloc<int2>(tiles.size());
+      for (int v = 0; v < k::NVARIANT; ++v) {
+        auto tv = k::stencil_tiles(f, (int)w, v, 0, -1);
+        f->n_tiles[v] = (int)tv.size();
+        f->d_tiles[v] = dev_alloc<int2>(tv.size());
+        OFM_HIP(hipMemcpyAsync(f->d_tiles[v], tv.data(), sizeof(int2) * tv.size(),
+                               hipMemcpyHostToDevice, s));
+        OFM_HIP(hipStreamSynchronize(s));
+      }
       f->d_stiles = dev_alloc<int2>(stiles.size());
       f->d_rtiles = dev_alloc<int2>(rtiles.size());
       f->d_v = dev_alloc<double>(f->v_total);
@@ -419,8 +474,6 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
       OFM_HIP(hipMemsetAsync(f->d_theta, 0, sizeof(double) * th, s));
       OFM_HIP(hipMemcpyAsync(f->d_frag, f->host.data(),
                              sizeof(FragDev) * n_frag, hipMemcpyHostToDevice, s));
-      OFM_HIP(hipMemcpyAsync(f->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
-                             hipMemcpyHostToDevice, s));
       OFM_HIP(hipMemcpyAsync(f->d_stiles, stiles.data(),
                              sizeof(int2) * stiles.size(), hipMemcpyHostToDevice, s));
       OFM_HIP(hipMemcpyAsync(f->d_rtiles, rtiles.data(),
@@ -524,6 +577,7 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.degree = (opts && opts->degree > 0) ? opts->degree : 32;
     cfg.degree += cfg.degree & 1;   // even: the filtered block ends in X
     cfg.seed = opts ? opts->seed : 0;
+    cfg.autotune = !opts || opts->autotune >= 0;
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,
                 "guard vectors are fixed when the fragments are built");
@@ -628,7 +682,7 @@ ofm_status ofm_apply_fragment_h(ofm_ctx* c, ofm_frags* f, int j, int nvec,
     const size_t n = (size_t)nvec * d.ld;
     char* din = dev_alloc<char>(n * w);
     char* dout = dev_alloc<char>(n * w);
-    int2* dt = dev_alloc<int2>(nvec);
+    int2* dt = nullptr;
     try {
       std::vector<char> buf((size_t)nvec * d.npts * w);
       for (size_t i = 0; i < (size_t)nvec * d.npts; ++i) {
@@ -637,22 +691,23 @@ ofm_status ofm_apply_fragment_h(ofm_ctx* c, ofm_frags* f, int j, int nvec,
         else
           ((float*)buf.data())[i] = (float)x[i];
       }
-      std::vector<int2> t(nvec);
-      for (int v = 0; v < nvec; ++v) t[v] = make_int2(j, v);
+      const int var = f->variant >= 0 ? f->variant : 1;
+      std::vector<int2> t = k::stencil_tiles(f, (int)w, var, nvec, j);
       OFM_HIP(hipMemsetAsync(din, 0, n * w, c->stream));
       OFM_HIP(hipMemcpy2DAsync(din, (size_t)d.ld * w, buf.data(), d.npts * w,
                                d.npts * w, nvec, hipMemcpyHostToDevice, c->stream));
-      OFM_HIP(hipMemcpyAsync(dt, t.data(), sizeof(int2) * nvec,
+      dt = dev_alloc<int2>(t.size());
+      OFM_HIP(hipMemcpyAsync(dt, t.data(), sizeof(int2) * t.size(),
                              hipMemcpyHostToDevice, c->stream));
       // nvec may exceed b_j: the descriptor's ld is used, tiles list v < nvec
       if (w == 8)
         k::apply_h<double>(c, f, (const double*)din, (const double*)din,
-                           (double*)dout, dt, nvec, nullptr, 0, nullptr, 0, 0,
-                           0, 0);
+                           (double*)dout, dt, (int)t.size(), var, nullptr, 0,
+                           nullptr, 0, 0, 0, 0);
       else
         k::apply_h<float>(c, f, (const float*)din, (const float*)din,
-                          (float*)dout, dt, nvec, nullptr, 0, nullptr, 0, 0,
-                          0, 0);
+                          (float*)dout, dt, (int)t.size(), var, nullptr, 0,
+                          nullptr, 0, 0, 0, 0);
       OFM_HIP(hipMemcpy2DAsync(buf.data(), d.npts * w, dout, (size_t)d.ld * w,
                                d.npts * w, nvec, hipMemcpyDeviceToHost, c->stream));
       OFM_HIP(hipStreamSynchronize(c->stream));
@@ -670,6 +725,12 @@ ofm_status ofm_apply_fragment_h(ofm_ctx* c, ofm_frags* f, int j, int nvec,
     dev_free(dt);
     return OFM_OK;
   });
+}
+
+ofm_status ofm_set_stencil_variant(ofm_frags* f, int variant) {
+  if (!f || variant < -1 || variant >= k::NVARIANT) return OFM_E_INVALID;
+  f->variant = variant;
+  return OFM_OK;
 }
 
 ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {

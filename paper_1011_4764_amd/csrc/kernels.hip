@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 
 #include "ofm_internal.h"
 
@@ -127,6 +128,16 @@ template void init_random<float>(hipStream_t, const ofm_frags*, float*,
 //         s_k = 1/(2/s1 - s_{k-1}).
 // `prev` and `out` may alias (each point of `out` depends on `prev` at the
 // same point only); `in` must not alias either.
+// One workgroup handles a strip of SP = 256 PPT consecutive points of the
+// xy plane of one (fragment, vector) and marches along z.  Its LDS window is
+// the strip plus two rows on each side (the y neighbours); when the whole
+// plane fits in one strip there is no halo at all.  The +-1, +-2 z
+// neighbours of the strip's own points ride in a 5-deep register queue; V
+// and the previous Chebyshev vector are prefetched one plane ahead.  All
+// strips of a vector compute the same arithmetic per point, so every PPT
+// variant gives bit-identical results.
+constexpr int HALO_NX_MAX = 128;   // boxes may span at most 128 points in x
+
 template <typename T, int PPT>
 __global__ __launch_bounds__(WG) void k_apply_h(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
@@ -134,13 +145,20 @@ __global__ __launch_bounds__(WG) void k_apply_h(
     const T* prev, T* out, const FilterState* __restrict__ fs,
     const int* __restrict__ active, int step, int mode, double nh,
     long long base_override) {
+  constexpr int SP = PPT * WG;
+  constexpr int LW = SP + 4 * HALO_NX_MAX;
   const int t = xcd_tile(blockIdx.x, nblk_pad);
   if (t >= ntiles) return;
-  const int j = tiles[t].x, v = tiles[t].y;
+  const int j = tiles[t].x;
+  const int v = tiles[t].y >> 16, strip = tiles[t].y & 0xffff;
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
   const int nx = fr.dims[0], ny = fr.dims[1], nz = fr.dims[2];
   const int plane = nx * ny;
+  const int p0 = strip * SP;
+  const int p1 = min(p0 + SP, plane);
+  const int h0 = max(p0 - 2 * nx, 0), h1 = min(p1 + 2 * nx, plane);
+  const int nlo = p0 - h0, nhi = h1 - p1;
   const long long base =
       (base_override >= 0 ? base_override : fr.x_off) + (long long)v * fr.ld;
   const T* __restrict__ src = in + base;
@@ -169,17 +187,18 @@ __global__ __launch_bounds__(WG) void k_apply_h(
       beta = (T)(step == 1 ? 0.0 : -sp * sc);
     }
   }
+  const bool use_prev = (mode == 1 && step > 1);
 
-  __shared__ T lds[2][PPT * WG];
+  __shared__ T lds[2][LW];
   const int tid = threadIdx.x;
   int px[PPT], py[PPT], pp[PPT];
   bool ok[PPT];
-  T q0[PPT], q1[PPT], q2[PPT], q3[PPT], q4[PPT];
+  T q0[PPT], q1[PPT], q2[PPT], q3[PPT], q4[PPT], vn[PPT], pn[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int p = tid + k * WG;
-    ok[k] = p < plane;
-    pp[k] = ok[k] ? p : 0;
+    const int p = p0 + tid + k * WG;
+    ok[k] = p < p1;
+    pp[k] = ok[k] ? p : p0;
     px[k] = pp[k] % nx;
     py[k] = pp[k] / nx;
     q0[k] = 0;
@@ -187,33 +206,60 @@ __global__ __launch_bounds__(WG) void k_apply_h(
     q2[k] = ok[k] ? src[pp[k]] : T(0);
     q3[k] = (ok[k] && nz > 1) ? src[plane + pp[k]] : T(0);
     q4[k] = (ok[k] && nz > 2) ? src[2 * plane + pp[k]] : T(0);
+    vn[k] = ok[k] ? vv[pp[k]] : T(0);
+    pn[k] = (ok[k] && use_prev) ? pv[pp[k]] : T(0);
+  }
+  // halo slots (2 rows on each side of the strip): nlo + nhi <= 4 nx <= 2 WG
+  int hq[2];
+  bool hok[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int hidx = tid + u * WG;
+    if (hidx < nlo) {
+      hq[u] = h0 + hidx;
+      hok[u] = true;
+    } else if (hidx - nlo < nhi) {
+      hq[u] = p1 + (hidx - nlo);
+      hok[u] = true;
+    } else {
+      hq[u] = h0;
+      hok[u] = false;
+    }
   }
   const T tw0 = (T)W0, tw1 = (T)W1, tw2 = (T)W2, tnh = (T)nh;
   for (int z = 0; z < nz; ++z) {
-    T nxt[PPT], vz[PPT], pz[PPT];
     const int zoff = z * plane;
+    T nxt[PPT], vnx[PPT], pnx[PPT], hv[2];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       nxt[k] = (ok[k] && z + 3 < nz) ? src[zoff + 3 * plane + pp[k]] : T(0);
-      vz[k] = ok[k] ? vv[zoff + pp[k]] : T(0);
-      pz[k] = (ok[k] && mode == 1 && step > 1) ? pv[zoff + pp[k]] : T(0);
-      if (ok[k]) lds[z & 1][pp[k]] = q2[k];
+      vnx[k] = (ok[k] && z + 1 < nz) ? vv[zoff + plane + pp[k]] : T(0);
+      pnx[k] = (ok[k] && use_prev && z + 1 < nz) ? pv[zoff + plane + pp[k]]
+                                                  : T(0);
     }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) hv[u] = hok[u] ? src[zoff + hq[u]] : T(0);
+    T* L = lds[z & 1];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+      if (ok[k]) L[pp[k] - h0] = q2[k];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (hok[u]) L[hq[u] - h0] = hv[u];
     __syncthreads();
-    const T* L = lds[z & 1];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       if (!ok[k]) continue;
-      const int p = pp[k], x = px[k], y = py[k];
+      const int li = pp[k] - h0, x = px[k], y = py[k];
       const T c = q2[k];
-      const T xm1 = x >= 1 ? L[p - 1] : T(0);
-      const T xm2 = x >= 2 ? L[p - 2] : T(0);
-      const T xp1 = x + 1 < nx ? L[p + 1] : T(0);
-      const T xp2 = x + 2 < nx ? L[p + 2] : T(0);
-      const T ym1 = y >= 1 ? L[p - nx] : T(0);
-      const T ym2 = y >= 2 ? L[p - 2 * nx] : T(0);
-      const T yp1 = y + 1 < ny ? L[p + nx] : T(0);
-      const T yp2 = y + 2 < ny ? L[p + 2 * nx] : T(0);
+      const T xm1 = x >= 1 ? L[li - 1] : T(0);
+      const T xm2 = x >= 2 ? L[li - 2] : T(0);
+      const T xp1 = x + 1 < nx ? L[li + 1] : T(0);
+      const T xp2 = x + 2 < nx ? L[li + 2] : T(0);
+      const T ym1 = y >= 1 ? L[li - nx] : T(0);
+      const T ym2 = y >= 2 ? L[li - 2 * nx] : T(0);
+      const T yp1 = y + 1 < ny ? L[li + nx] : T(0);
+      const T yp2 = y + 2 < ny ? L[li + 2 * nx] : T(0);
       // walls at every box face: odd image of the second ghost
       const int nfaces = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) +
                          (z == 0) + (z == nz - 1);
@@ -221,13 +267,13 @@ __global__ __launch_bounds__(WG) void k_apply_h(
                     tw1 * ((xm1 + xp1) + (ym1 + yp1) + (q1[k] + q3[k])) +
                     tw2 * ((xm2 + xp2) + (ym2 + yp2) + (q0[k] + q4[k])) -
                     tw2 * T(nfaces) * c;
-      const T hv = tnh * lap + vz[k] * c;
+      const T hval = tnh * lap + vn[k] * c;
       T o;
       if (mode == 0)
-        o = hv;
+        o = hval;
       else
-        o = alpha * hv + gamma * c + beta * pz[k];
-      dst[zoff + p] = o;
+        o = alpha * hval + gamma * c + beta * pn[k];
+      dst[zoff + pp[k]] = o;
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -236,15 +282,42 @@ __global__ __launch_bounds__(WG) void k_apply_h(
       q2[k] = q3[k];
       q3[k] = q4[k];
       q4[k] = nxt[k];
+      vn[k] = vnx[k];
+      pn[k] = pnx[k];
     }
   }
 }
 
+// PPT of stencil variant i for storage type T
+int stencil_ppt(int elem_bytes, int variant) {
+  static const int p64[NVARIANT] = {1, 2, 4};
+  static const int p32[NVARIANT] = {2, 4, 8};
+  return elem_bytes == 8 ? p64[variant] : p32[variant];
+}
+
+// tiles (fragment, vector << 16 | strip) of one stencil variant for the
+// vectors v < nvec(j) of every fragment (or of fragment `only` alone)
+std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
+                                int variant, int nvec_only, int only) {
+  const int sp = stencil_ppt(elem_bytes, variant) * WG;
+  std::vector<int2> t;
+  for (int j = 0; j < f->n_frag; ++j) {
+    if (only >= 0 && j != only) continue;
+    const FragDev& d = f->host[j];
+    const int ns = (d.dims[0] * d.dims[1] + sp - 1) / sp;
+    const int nv = nvec_only > 0 ? nvec_only : d.bw;
+    for (int v = 0; v < nv; ++v)
+      for (int s = 0; s < ns; ++s) t.push_back(make_int2(j, (v << 16) | s));
+  }
+  return t;
+}
+
 template <typename T>
 void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
-             T* out, const int2* tiles, int ntiles, const int* active,
-             int step, const FilterState* fs, int mode,
-             long long base_override, double alg_bytes, double flops) {
+             T* out, const int2* tiles, int ntiles, int variant,
+             const int* active, int step, const FilterState* fs, int mode,
+             long long base_override, double alg_bytes, double flops,
+             hipEvent_t ev0, hipEvent_t ev1) {
   const T* Vj;
   if constexpr (sizeof(T) == 8)
     Vj = (const T*)f->d_v;
@@ -253,32 +326,30 @@ void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
   const double nh = -0.5 / (f->grid.h * f->grid.h);
   const int nblk = pad8(ntiles);
   Timed tm(c, "stencil", alg_bytes, flops);
-  if (f->max_plane <= 2 * WG)
-    hipLaunchKernelGGL((k_apply_h<T, 2>), dim3(nblk), dim3(WG), 0, c->stream,
-                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
-                       active, step, mode, nh, base_override);
-  else if (f->max_plane <= 4 * WG)
-    hipLaunchKernelGGL((k_apply_h<T, 4>), dim3(nblk), dim3(WG), 0, c->stream,
-                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
-                       active, step, mode, nh, base_override);
-  else if (f->max_plane <= 9 * WG)
-    hipLaunchKernelGGL((k_apply_h<T, 9>), dim3(nblk), dim3(WG), 0, c->stream,
-                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
-                       active, step, mode, nh, base_override);
-  else
-    hipLaunchKernelGGL((k_apply_h<T, 16>), dim3(nblk), dim3(WG), 0, c->stream,
-                       f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,
-                       active, step, mode, nh, base_override);
+  if (ev0) OFM_HIP(hipEventRecord(ev0, c->stream));
+  const int ppt = stencil_ppt(sizeof(T), variant);
+#define LAUNCH(P)                                                            \
+  hipLaunchKernelGGL((k_apply_h<T, P>), dim3(nblk), dim3(WG), 0, c->stream,  \
+                     f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,  \
+                     active, step, mode, nh, base_override)
+  if (ppt == 1) LAUNCH(1);
+  else if (ppt == 2) LAUNCH(2);
+  else if (ppt == 4) LAUNCH(4);
+  else LAUNCH(8);
+#undef LAUNCH
+  if (ev1) OFM_HIP(hipEventRecord(ev1, c->stream));
   OFM_HIP(hipGetLastError());
 }
 template void apply_h<double>(ofm_ctx*, const ofm_frags*, const double*,
-                              const double*, double*, const int2*, int,
+                              const double*, double*, const int2*, int, int,
                               const int*, int, const FilterState*, int,
-                              long long, double, double);
+                              long long, double, double, hipEvent_t,
+                              hipEvent_t);
 template void apply_h<float>(ofm_ctx*, const ofm_frags*, const float*,
-                             const float*, float*, const int2*, int,
+                             const float*, float*, const int2*, int, int,
                              const int*, int, const FilterState*, int,
-                             long long, double, double);
+                             long long, double, double, hipEvent_t,
+                             hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // Gram products G = A^T B per fragment (FP64 MFMA 16x16x4)

@@ -89,6 +89,7 @@ struct ofm_ctx {
   double t_solve = 0, t_elem = 0, t_global = 0;
   void* blas = nullptr;    // rocblas_handle, created lazily
   int live = 0;            // fragment / matrix handles made with this context
+  std::map<long long, int> tuned;  // stencil variant per (precision, plane class)
   int n_cu = 256;
 };
 
@@ -114,8 +115,9 @@ struct ofm_frags {
   void* d_hphi = nullptr;      // whole-system H phi on dilated boxes (T)
   // tile lists: (fragment, vector < b_j), (fragment, state < s_j) and
   // (fragment, 256-point chunk)
-  int2* d_tiles = nullptr;
-  int n_tiles = 0;
+  int2* d_tiles[3] = {nullptr, nullptr, nullptr};   // per stencil variant
+  int n_tiles[3] = {0, 0, 0};
+  int variant = -1;            // stencil variant in use (-1: not chosen)
   int2* d_stiles = nullptr;
   int n_stiles = 0;
   int2* d_rtiles = nullptr;
@@ -220,11 +222,16 @@ void restrict_potential(hipStream_t s, const double* V, const ofm_grid& g,
 template <typename T>
 void init_random(hipStream_t s, const ofm_frags* f, T* X,
                  unsigned long long seed);
+constexpr int NVARIANT = 3;   // stencil variants (points per thread)
+int stencil_ppt(int elem_bytes, int variant);
+std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
+                                int variant, int nvec_only, int only);
 template <typename T>
 void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
-             T* out, const int2* tiles, int ntiles, const int* active,
-             int step, const FilterState* fs, int mode,
-             long long base_override, double alg_bytes, double flops);
+             T* out, const int2* tiles, int ntiles, int variant,
+             const int* active, int step, const FilterState* fs, int mode,
+             long long base_override, double alg_bytes, double flops,
+             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void gram(ofm_ctx* c, const ofm_frags* f, const T* A, const T* B, double* G,
           const int* active, double bytes, double flops);

@@ -51,9 +51,11 @@ void plan_fragments(ofm_frags* f, const ofm_grid& g, int n_frag,
     }
     OFM_REQUIRE(npts <= (1LL << 24), OFM_E_INVALID,
                 "fragment " + std::to_string(j) + " box too large");
-    OFM_REQUIRE(d.dims[0] * d.dims[1] <= 4096, OFM_E_INVALID,
+    OFM_REQUIRE((long long)d.dims[0] * d.dims[1] <= (1 << 22), OFM_E_INVALID,
+                "fragment " + std::to_string(j) + ": xy plane too large");
+    OFM_REQUIRE(d.dims[0] <= 128, OFM_E_INVALID,
                 "fragment " + std::to_string(j) +
-                    ": an xy plane of a box may hold at most 4096 points");
+                    ": a box may span at most 128 points along x");
     const int s = fr[j].n_states;
     OFM_REQUIRE(s >= 1 && s <= npts, OFM_E_INVALID,
                 "fragment " + std::to_string(j) +

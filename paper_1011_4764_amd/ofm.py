@@ -32,6 +32,7 @@ EXPORTS = [
     "ofm_matrix_elements", "ofm_mats_info", "ofm_mats_copy",
     "ofm_mats_destroy", "ofm_solve_global", "ofm_set_profiling",
     "ofm_kernel_stats", "ofm_reset_stats", "ofm_stage_times",
+    "ofm_set_stencil_variant",
 ]
 
 
@@ -104,6 +105,7 @@ def lib():
             "ofm_kernel_stats": ([_P, C.c_char_p, _LL, _D, _D, _D], C.c_int),
             "ofm_reset_stats": ([_P], C.c_int),
             "ofm_stage_times": ([_P, _D, _D, _D], C.c_int),
+            "ofm_set_stencil_variant": ([_P, C.c_int], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -314,6 +316,11 @@ def ofm_get_hphi(frags: Fragments, j):
     out = np.zeros((s, dd[0] * dd[1] * dd[2]))
     _check(lib().ofm_get_hphi(frags.handle, j, _dp(out)), frags.ctx.handle)
     return out
+
+
+def ofm_set_stencil_variant(frags: Fragments, variant: int):
+    _check(lib().ofm_set_stencil_variant(frags.handle, int(variant)),
+           frags.ctx.handle)
 
 
 def ofm_apply_fragment_h(ctx: Context, frags: Fragments, j, x):

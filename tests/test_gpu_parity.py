@@ -32,18 +32,22 @@ def ctx():
 
 # ------------------------------------------------------------------ stencil
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("dims", [(12, 12, 12), (7, 5, 9), (48, 40, 3),
-                                  (1, 1, 6), (33, 31, 2), (64, 64, 2)])
-def test_fragment_stencil(ctx, dims):
+                                  (1, 1, 6), (33, 31, 2), (64, 64, 2),
+                                  (128, 3, 4), (5, 300, 3)])
+def test_fragment_stencil(ctx, dims, variant):
     """H_j x on random vectors vs the oracle's sparse fragment operator:
-    ragged boxes, planes from 1 to 4096 points, 1-point axes."""
-    _say("stencil", dims)
+    ragged boxes, planes from 1 to 4096 points split into strips with halo
+    rows, 1-point axes, the widest allowed x extent; every stencil variant."""
+    _say("stencil", dims, "variant", variant)
     rng = np.random.default_rng(sum(dims))
     shape = (dims[0] + 3, dims[1] + 2, dims[2] + 1)
     V = rng.standard_normal(shape[::-1])
     lo = (2, 1, 0)
     s = box_system(shape, 0.45, [lo], [dims], [1], V=V)
     f = _build(ctx, s)
+    P.ofm_set_stencil_variant(f, variant)
     n = int(np.prod(dims))
     x = rng.standard_normal((3, n))
     y = P.ofm_apply_fragment_h(ctx, f, 0, x)
