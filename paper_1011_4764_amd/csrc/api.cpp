@@ -192,6 +192,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   k::init_random<T>(s, f, X, cfg.seed);
 
   std::vector<int> act(nf, 1);
+  std::vector<FilterState> fsh(nf);
   // stencil variant: cached per (precision, largest plane), else timed on
   // the first filter sweep (steps 2..7 cycle through the variants; every
   // variant computes identical values, so tuning never changes results)
@@ -259,6 +260,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                            hipMemcpyDeviceToHost, s));
     OFM_HIP(hipMemcpyAsync(act.data(), f->d_active, sizeof(int) * nf,
                            hipMemcpyDeviceToHost, s));
+    OFM_HIP(hipMemcpyAsync(fsh.data(), f->d_fs, sizeof(FilterState) * nf,
+                           hipMemcpyDeviceToHost, s));
     OFM_HIP(hipStreamSynchronize(s));
     collect_stats(c);
   };
@@ -267,8 +270,13 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   apply_plain();
   rayleigh_ritz();
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
-    double nb, npt, nb2;
-    sums(nb, npt, nb2);
+    // filter work: unlocked vectors of the active fragments
+    double nb = 0, npt = 0;
+    for (int j = 0; j < nf; ++j)
+      if (act[j] && fsh[j].lock < f->host[j].bw) {
+        nb += (double)f->host[j].npts * (f->host[j].bw - fsh[j].lock);
+        npt += f->host[j].npts;
+      }
     for (int step = 1; step <= cfg.degree; ++step) {
       const bool odd = step & 1;
       const T* in = odd ? X : P;

@@ -152,6 +152,9 @@ __global__ __launch_bounds__(WG) void k_apply_h(
   const int j = tiles[t].x;
   const int v = tiles[t].y >> 16, strip = tiles[t].y & 0xffff;
   if (active && !active[j]) return;
+  // converged leading Ritz vectors are locked: the filter leaves them as they
+  // are (they stay in the orthogonalisation and the Rayleigh-Ritz step)
+  if (mode == 1 && v < fs[j].lock) return;
   const FragDev& fr = F[j];
   const int nx = fr.dims[0], ny = fr.dims[1], nz = fr.dims[2];
   const int plane = nx * ny;
@@ -234,8 +237,9 @@ __global__ __launch_bounds__(WG) void k_apply_h(
     for (int k = 0; k < PPT; ++k) {
       nxt[k] = (ok[k] && z + 3 < nz) ? src[zoff + 3 * plane + pp[k]] : T(0);
       vnx[k] = (ok[k] && z + 1 < nz) ? vv[zoff + plane + pp[k]] : T(0);
-      pnx[k] = (ok[k] && use_prev && z + 1 < nz) ? pv[zoff + plane + pp[k]]
-                                                  : T(0);
+      pnx[k] = (ok[k] && use_prev && z + 1 < nz)
+                   ? __builtin_nontemporal_load(&pv[zoff + plane + pp[k]])
+                   : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) hv[u] = hok[u] ? src[zoff + hq[u]] : T(0);
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(WG) void k_apply_h(
         o = hval;
       else
         o = alpha * hval + gamma * c + beta * pn[k];
-      dst[zoff + pp[k]] = o;
+      __builtin_nontemporal_store(o, &dst[zoff + pp[k]]);
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -852,35 +856,59 @@ template void rotate<float>(ofm_ctx*, const ofm_frags*, float*, float*,
 // ---------------------------------------------------------------------------
 // end of an outer iteration: residual norms, convergence, filter bounds
 // ---------------------------------------------------------------------------
-__global__ void k_finalize(const FragDev* __restrict__ F, int nf,
-                           const double* __restrict__ theta,
-                           const double* __restrict__ res_partial,
-                           FilterState* __restrict__ fs, int* __restrict__ active,
-                           int* __restrict__ iters,
-                           unsigned char* __restrict__ conv, double tol,
-                           int* __restrict__ n_active, double* __restrict__ res,
-                           double upper_kin) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// one workgroup per fragment: residual norms (chunk partials summed in a
+// fixed order), convergence, locking of the converged leading Ritz vectors
+// (the filter skips them) and the next filter interval
+__global__ __launch_bounds__(WG) void k_finalize(
+    const FragDev* __restrict__ F, int nf, const double* __restrict__ theta,
+    const double* __restrict__ res_partial, FilterState* __restrict__ fs,
+    int* __restrict__ active, int* __restrict__ iters,
+    unsigned char* __restrict__ conv, double tol, int* __restrict__ n_active,
+    double* __restrict__ res, double upper_kin) {
+  const int j = blockIdx.x;
   if (j >= nf) return;
   if (!active[j]) return;
   const FragDev& fr = F[j];
-  double worst = 0;
-  for (int i = 0; i < fr.bw; ++i) {
+  const int bw = fr.bw;
+  constexpr int PARTS = 16;
+  __shared__ double part[SMAX][PARTS];
+  __shared__ double rn[SMAX];
+  for (int e = threadIdx.x; e < bw * PARTS; e += WG) {
+    const int i = e / PARTS, q = e % PARTS;
     double s = 0;
-    for (int t = fr.rt_begin; t < fr.rt_begin + fr.rt_count; ++t)
+    for (int t = fr.rt_begin + q; t < fr.rt_begin + fr.rt_count; t += PARTS)
       s += res_partial[(long long)t * SMAX + i];
-    const double r = sqrt(s);
-    res[fr.th_off + i] = r;
-    if (i < fr.n_states) worst = fmax(worst, r);
+    part[i][q] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < bw; i += WG) {
+    double s = 0;
+    for (int q = 0; q < PARTS; ++q) s += part[i][q];
+    rn[i] = sqrt(s);
+    res[fr.th_off + i] = rn[i];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double worst = 0;
+  int lock = 0;
+  bool prefix = true;
+  for (int i = 0; i < fr.n_states; ++i) {
+    worst = fmax(worst, rn[i]);
+    if (prefix && rn[i] <= tol)
+      lock = i + 1;
+    else
+      prefix = false;
   }
   iters[j] += 1;
   FilterState st;
   st.upper = upper_kin + fmax(fr.vmax, 0.0);
-  st.lower = theta[fr.th_off + fr.bw - 1];
+  st.lower = theta[fr.th_off + bw - 1];
   st.scale = theta[fr.th_off];
-  st.pad = worst;
+  st.worst = worst;
+  st.lock = lock;
+  st.pad = 0;
   fs[j] = st;
-  if (worst <= tol || fr.bw == fr.npts) {
+  if (worst <= tol || bw == fr.npts) {
     active[j] = 0;
     conv[j] = 1;
   } else {
@@ -893,9 +921,9 @@ void finalize_iter(hipStream_t s, const ofm_frags* f, const double* theta,
                    int* iters, unsigned char* conv, double tol, int* n_active,
                    double* res) {
   const double h = f->grid.h;
-  hipLaunchKernelGGL(k_finalize, dim3((f->n_frag + 127) / 128), dim3(128), 0,
-                     s, f->d_frag, f->n_frag, theta, res_partial, fs, active,
-                     iters, conv, tol, n_active, res, 8.0 / (h * h));
+  hipLaunchKernelGGL(k_finalize, dim3(f->n_frag), dim3(WG), 0, s, f->d_frag,
+                     f->n_frag, theta, res_partial, fs, active, iters, conv,
+                     tol, n_active, res, 8.0 / (h * h));
   OFM_HIP(hipGetLastError());
 }
 

@@ -62,7 +62,9 @@ struct FilterState {
   double lower;   // lower end of the damped interval (largest block Ritz value)
   double upper;   // upper bound of the spectrum
   double scale;   // point normalised to 1 (smallest Ritz value)
-  double pad;
+  double worst;   // largest residual over the wanted states
+  int lock;       // leading Ritz vectors already converged (not filtered)
+  int pad;
 };
 
 struct KernelStat {

@@ -14,7 +14,7 @@ import weakref
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libofm.so")
+LIB_PATH = os.environ.get("OFM_LIB") or os.path.join(_HERE, "libofm.so")
 
 OFM_OK, OFM_E_INVALID, OFM_E_NOMEM, OFM_E_DEVICE = 0, -1, -2, -3
 OFM_E_NOCONV, OFM_E_SINGULAR, OFM_E_STATE = -4, -5, -6
