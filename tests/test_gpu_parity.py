@@ -239,3 +239,55 @@ def test_error_paths(ctx, tiny0):
     assert e.value.status == P.OFM_E_STATE
     st, eps, it, cv = P.ofm_solve_fragments(ctx, f, max_iter=1)
     assert st == P.OFM_E_NOCONV and not cv.all()
+
+
+# ------------------------------------------------------------------ global solve
+
+def _run_path(ctx, lo, dims, st, V, h=0.5):
+    s = box_system((V.shape[2], V.shape[1], V.shape[0]), h, lo, dims, st, V=V)
+    f = _build(ctx, s)
+    r = O.run(V, h, lo, dims, st, solve=False)
+    for j in range(len(st)):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    return f, r
+
+
+def test_global_duplicate_fragment_drops_directions(ctx, tiny0):
+    """A duplicated fragment makes S exactly singular in s_j directions: the
+    GPU keeps the same count as the oracle and the same eigenvalues."""
+    _say("global solve, duplicated fragment")
+    s = tiny0
+    V = s.potential()
+    lo = np.vstack([s.frag_lo, s.frag_lo[1:2]])
+    dims = np.vstack([s.frag_dims, s.frag_dims[1:2]])
+    st = np.concatenate([s.frag_states, [6]])
+    f, r = _run_path(ctx, lo, dims, st, V)
+    m = P.ofm_matrix_elements(ctx, f)
+    H, S = P.ofm_mats_copy(m)
+    Hd, Sd = P.unpack_blocks(f, H, S)
+    ref = O.global_solve(Hd, Sd, 1e-6)
+    g = P.ofm_solve_global(ctx, m, 1e-6)
+    _say("  kept", g["n_kept"], "oracle", ref["n_kept"])
+    assert g["n_kept"] == ref["n_kept"] == 18
+    assert np.abs(g["E"] - ref["E"]).max() < 1e-8
+    assert abs(g["s_min"] - ref["s_min_kept"]) < 1e-10
+
+
+def test_global_direct_path_and_vectors(ctx, tiny0, tiny0_oracle):
+    """Nothing is dropped on the tiny case, so thresholds 1e-6 and 0 agree;
+    the returned coefficients solve H c = E S c with c^T S c = 1."""
+    _say("global solve, thresholds and vectors")
+    s, r = tiny0, tiny0_oracle
+    f = _build(ctx, s)
+    for j in range(s.n_frag):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    m = P.ofm_matrix_elements(ctx, f)
+    g1 = P.ofm_solve_global(ctx, m, 1e-6, want_vectors=True)
+    g0 = P.ofm_solve_global(ctx, m, 0.0)
+    assert np.abs(g1["E"] - g0["E"]).max() < 1e-10
+    H, S = P.ofm_mats_copy(m)
+    Hd, Sd = P.unpack_blocks(f, H, S)
+    Cm = g1["C"]
+    res = Hd @ Cm - (Sd @ Cm) * g1["E"]
+    assert np.abs(res).max() < 1e-9
+    assert np.abs(np.diag(Cm.T @ Sd @ Cm) - 1).max() < 1e-10
