@@ -93,7 +93,9 @@ typedef struct {
   int guard;             /* extra block vectors beyond s_j [8]               */
   int degree;            /* Chebyshev filter degree per iteration [32]       */
   unsigned long long seed; /* start-vector seed [0]                          */
-  int use_graph;         /* 1: replay each iteration as a HIP graph [1]      */
+  int use_graph;         /* >= 0: the Chebyshev filter sweep is captured once
+                            as a HIP graph and replayed every iteration [on];
+                            -1: launch its kernels one by one               */
   int autotune;          /* >= 0: time the stencil variants on the first
                             filter sweep, once per (precision, largest box
                             plane) and context, and keep the fastest [on];

@@ -80,8 +80,8 @@ size_t wsize(const ofm_ctx* c) { return c->precision == OFM_FP64 ? 8 : 4; }
 // timing brackets
 // --------------------------------------------------------------------------
 namespace ofm {
-Timed::Timed(ofm_ctx* ctx, const char* family, double by, double fl)
-    : c(ctx), fam(family), bytes(by), flops(fl) {
+Timed::Timed(ofm_ctx* ctx, const char* family, double by, double fl, int n)
+    : c(ctx), fam(family), bytes(by), flops(fl), launches(n) {
   if (!c || !c->profiling) return;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     a = b = nullptr;
@@ -92,14 +92,14 @@ Timed::Timed(ofm_ctx* ctx, const char* family, double by, double fl)
 Timed::~Timed() {
   if (!a) return;
   (void)hipEventRecord(b, c->stream);
-  c->pending.push_back({fam, a, b, bytes, flops});
+  c->pending.push_back({fam, a, b, bytes, flops, launches});
 }
 void collect_stats(ofm_ctx* c) {
   for (auto& p : c->pending) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       auto& s = c->stats[p.fam];
-      s.launches += 1;
+      s.launches += p.launches;
       s.ms += ms;
       s.bytes += p.bytes;
       s.flops += p.flops;
@@ -172,6 +172,7 @@ struct SolveCfg {
   int max_iter, degree;
   unsigned long long seed;
   bool autotune;
+  bool use_graph;
 };
 
 template <typename T>
@@ -193,6 +194,13 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
 
   std::vector<int> act(nf, 1);
   std::vector<FilterState> fsh(nf);
+  hipGraphExec_t sweep_exec = nullptr;
+  struct GraphGuard {
+    hipGraphExec_t* e;
+    ~GraphGuard() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+    }
+  } graph_guard{&sweep_exec};
   // stencil variant: cached per (precision, largest plane), else timed on
   // the first filter sweep (steps 2..7 cycle through the variants; every
   // variant computes identical values, so tuning never changes results)
@@ -277,21 +285,51 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         nb += (double)f->host[j].npts * (f->host[j].bw - fsh[j].lock);
         npt += f->host[j].npts;
       }
-    for (int step = 1; step <= cfg.degree; ++step) {
-      const bool odd = step & 1;
-      const T* in = odd ? X : P;
-      const T* prev = odd ? P : X;
-      T* out = odd ? P : X;
-      const double by = (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
-      int sv = var;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (tuning && step >= 2 && step < 8) {
-        sv = (step - 2) % k::NVARIANT;
-        e0 = tev[step - 2][0];
-        e1 = tev[step - 2][1];
+    auto sweep = [&](bool timed_each) {
+      for (int step = 1; step <= cfg.degree; ++step) {
+        const bool odd = step & 1;
+        const T* in = odd ? X : P;
+        const T* prev = odd ? P : X;
+        T* out = odd ? P : X;
+        const double by = (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
+        int sv = var;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tuning && step >= 2 && step < 8) {
+          sv = (step - 2) % k::NVARIANT;
+          e0 = tev[step - 2][0];
+          e1 = tev[step - 2][1];
+        }
+        k::apply_h<T>(timed_each ? c : nullptr, f, in, prev, out,
+                      f->d_tiles[sv], f->n_tiles[sv], sv, f->d_active, step,
+                      f->d_fs, 1, -1, by, 32.0 * nb, e0, e1);
       }
-      k::apply_h<T>(c, f, in, prev, out, f->d_tiles[sv], f->n_tiles[sv], sv,
-                    f->d_active, step, f->d_fs, 1, -1, by, 32.0 * nb, e0, e1);
+    };
+    if (tuning || !cfg.use_graph) {
+      sweep(true);
+    } else {
+      // the sweep is static (tiles, buffers and step coefficients fixed;
+      // the active flags, locks and intervals are read from device memory),
+      // so it is captured once and replayed every outer iteration
+      if (!sweep_exec) {
+        hipGraph_t g = nullptr;
+        OFM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+          sweep(false);
+        } catch (...) {
+          (void)hipStreamEndCapture(s, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        OFM_HIP(hipStreamEndCapture(s, &g));
+        const hipError_t ie = hipGraphInstantiate(&sweep_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        OFM_HIP(ie);
+      }
+      double by = 0;
+      for (int step = 1; step <= cfg.degree; ++step)
+        by += (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
+      Timed tm(c, "stencil", by, 32.0 * nb * cfg.degree, cfg.degree);
+      OFM_HIP(hipGraphLaunch(sweep_exec, s));
     }
     cholqr();
     apply_plain();
@@ -586,6 +624,7 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.degree += cfg.degree & 1;   // even: the filtered block ends in X
     cfg.seed = opts ? opts->seed : 0;
     cfg.autotune = !opts || opts->autotune >= 0;
+    cfg.use_graph = !opts || opts->use_graph >= 0;
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,
                 "guard vectors are fixed when the fragments are built");

@@ -330,10 +330,11 @@ void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
   const double nh = -0.5 / (f->grid.h * f->grid.h);
   const int nblk = pad8(ntiles);
   Timed tm(c, "stencil", alg_bytes, flops);
-  if (ev0) OFM_HIP(hipEventRecord(ev0, c->stream));
+  hipStream_t stream = f->ctx->stream;
+  if (ev0) OFM_HIP(hipEventRecord(ev0, stream));
   const int ppt = stencil_ppt(sizeof(T), variant);
 #define LAUNCH(P)                                                            \
-  hipLaunchKernelGGL((k_apply_h<T, P>), dim3(nblk), dim3(WG), 0, c->stream,  \
+  hipLaunchKernelGGL((k_apply_h<T, P>), dim3(nblk), dim3(WG), 0, stream,     \
                      f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,  \
                      active, step, mode, nh, base_override)
   if (ppt == 1) LAUNCH(1);
@@ -341,7 +342,7 @@ void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
   else if (ppt == 4) LAUNCH(4);
   else LAUNCH(8);
 #undef LAUNCH
-  if (ev1) OFM_HIP(hipEventRecord(ev1, c->stream));
+  if (ev1) OFM_HIP(hipEventRecord(ev1, stream));
   OFM_HIP(hipGetLastError());
 }
 template void apply_h<double>(ofm_ctx*, const ofm_frags*, const double*,

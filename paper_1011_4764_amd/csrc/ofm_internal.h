@@ -86,7 +86,12 @@ struct ofm_ctx {
   bool profiling = false;
   std::map<std::string, ofm::KernelStat> stats;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
-  struct Pending { std::string fam; hipEvent_t a, b; double bytes, flops; };
+  struct Pending {
+    std::string fam;
+    hipEvent_t a, b;
+    double bytes, flops;
+    int launches;
+  };
   std::vector<Pending> pending;
   double t_solve = 0, t_elem = 0, t_global = 0;
   void* blas = nullptr;    // rocblas_handle, created lazily
@@ -197,8 +202,10 @@ struct Timed {
   ofm_ctx* c;
   std::string fam;
   double bytes, flops;
+  int launches;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(ofm_ctx* ctx, const char* family, double by, double fl);
+  // `n` launches of the family happen between construction and destruction
+  Timed(ofm_ctx* ctx, const char* family, double by, double fl, int n = 1);
   ~Timed();
 };
 void collect_stats(ofm_ctx* c);

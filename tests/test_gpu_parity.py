@@ -291,3 +291,32 @@ def test_global_direct_path_and_vectors(ctx, tiny0, tiny0_oracle):
     res = Hd @ Cm - (Sd @ Cm) * g1["E"]
     assert np.abs(res).max() < 1e-9
     assert np.abs(np.diag(Cm.T @ Sd @ Cm) - 1).max() < 1e-10
+
+
+def test_graph_replay_and_variants_bit_identical(ctx):
+    """The HIP-graph replay of the filter sweep, one-by-one launches and every
+    stencil variant compute the same values bit for bit (uneven boxes, two
+    strips per plane for the smaller variants)."""
+    _say("graph replay / stencil variants")
+    rng = np.random.default_rng(8)
+    shape = (40, 36, 20)
+    V = -np.abs(rng.standard_normal(shape[::-1]))
+    lo = [(0, 0, 0), (14, 10, 4), (20, 16, 6)]
+    dims = [(22, 20, 12), (19, 24, 14), (20, 20, 14)]
+    st = [5, 7, 4]
+    s = box_system(shape, 0.5, lo, dims, st, V=V)
+    outs = []
+    for use_graph, variant in [(0, -1), (-1, 0), (0, 1), (-1, 2)]:
+        f = _build(ctx, s)
+        if variant >= 0:
+            P.ofm_set_stencil_variant(f, variant)
+        stt, eps, it, cv = P.ofm_solve_fragments(ctx, f, use_graph=use_graph)
+        assert stt == 0
+        outs.append((eps, [P.ofm_get_states(f, j)[1] for j in range(3)]))
+        f.close()
+    for eps, phis in outs[1:]:
+        assert np.array_equal(eps, outs[0][0])
+        for a, b in zip(phis, outs[0][1]):
+            assert np.array_equal(a, b)
+    ref = O.run(V, 0.5, lo, dims, st, solve=False)
+    assert np.abs(outs[0][0] - np.concatenate(ref.eps)).max() < 1e-8
