@@ -57,6 +57,22 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(config, precision):
+    """HBM traffic per stencil launch from the committed rocprofv3 counter
+    summary of this workload, if the kernel source has not changed since the
+    counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"stencil_{config}_{precision}.md")
+    src = os.path.join(ROOT, "paper_1011_4764_amd", "csrc", "kernels.hip")
+    try:
+        line = [l for l in open(path) if l.startswith("traffic: ")][-1]
+        rec = json.loads(line[len("traffic: "):])
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    return rec["bytes_per_launch"] if rec.get("kernels_hip_sha1") == sha else None
+
+
 def cpu_baseline(system, n_sample, seed):
     """The CPU oracle, as it stands, on a seeded sample of fragments of the
     same workload: their eigenpairs, whole-system H|phi> and the pair blocks
@@ -216,7 +232,9 @@ def main():
             "kernel": "k_apply_h (Chebyshev filter step of H_j)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.config, args.precision),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + "
+                            "WRITE_SIZE, copy-calibrated)",
             "launches": st["launches"], "avg_launch_ms": avg_ms,
             "alg_bytes_per_launch": bytes_launch,
         },
@@ -235,7 +253,7 @@ def main():
     if args.precision == "fp64" and not args.no_mixed:
         # the same workload in the mixed form, and FP64 stopped at the mixed
         # tolerance (equal accuracy); window eigenvalues compared to FP64's
-        mx = run_form("mixed", 0.0, args.steps, args.warmup, False)
+        mx = run_form("mixed", 0.0, args.steps, args.warmup, True)
         eq = run_form("fp64", 2e-5, args.steps, args.warmup, False)
         Em = mx["last"]["E"]
         nw = len(window)
@@ -256,6 +274,18 @@ def main():
             "whole_step_speedup_vs_fp64": ms_step / mx["ms_step"],
             "fp64_at_2e-5_solve_ms": eq["solve_ms"],
         }
+        ms_ = mx["stencil"]
+        if ms_["launches"]:
+            a_ms = ms_["ms"] / ms_["launches"]
+            ach = ms_["bytes"] / ms_["launches"] / (a_ms * 1e-3) / 1e9
+            out["mixed"]["stencil_roofline"] = {
+                "kernel": "k_apply_h<float>", "bound": "hbm", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": a_ms,
+                "launches": ms_["launches"]}
+        me = mx["elements"]
+        if me["ms"]:
+            out["mixed"]["elements_TFLOPs_useful"] = me["flops"] / me["ms"] / 1e9
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_sample, args.seed)
