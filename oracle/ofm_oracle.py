@@ -209,9 +209,13 @@ def apply_whole_H(V, h, lo, dims, phi):
 # pair set and matrix elements (Sec. II)
 # --------------------------------------------------------------------------
 
-def pair_list(frag_lo, frag_dims, reach=REACH):
+def pair_list(frag_lo, frag_dims, reach=REACH, d_cut=None, atoms=None,
+              frag_atom_ptr=None, frag_atom_idx=None):
     """All pairs j <= n (diagonal included) whose boxes come within the
-    stencil reach of each other, in lexicographic (j, n) order."""
+    stencil reach of each other, in lexicographic (j, n) order.
+
+    With d_cut > 0 (Sec. III-C), an off-diagonal pair is kept only if the
+    closest two atoms of the two fragments are less than d_cut apart."""
     lo = np.asarray(frag_lo, dtype=np.int64)
     hi = lo + np.asarray(frag_dims, dtype=np.int64)   # exclusive
     nf = lo.shape[0]
@@ -221,6 +225,21 @@ def pair_list(frag_lo, frag_dims, reach=REACH):
                     axis=1)
         for n in np.nonzero(ok)[0]:
             out.append((j, j + int(n)))
+    if d_cut is not None and d_cut > 0:
+        def members(f):
+            return np.asarray(frag_atom_idx[frag_atom_ptr[f]:
+                                            frag_atom_ptr[f + 1]])
+        kept = []
+        for (j, n) in out:
+            if j == n:
+                kept.append((j, n))
+                continue
+            a, b = atoms[members(j)], atoms[members(n)]
+            if len(a) and len(b):
+                d = np.sqrt(((a[:, None, :] - b[None, :, :]) ** 2).sum(-1))
+                if d.min() < d_cut:
+                    kept.append((j, n))
+        out = kept
     return out
 
 
@@ -375,9 +394,11 @@ def window_below_cutoff(eps):
 
 
 def run(V, h, frag_lo, frag_dims, frag_states, tau=1e-6, window=None,
-        states=None, fragments=None, solve=True):
+        states=None, fragments=None, solve=True, d_cut=None, atoms=None,
+        frag_atom_ptr=None, frag_atom_idx=None):
     """Fragment states -> whole-H products -> pair blocks -> global solve.
 
+    ``d_cut`` and the atom lists prune the pair set by atom distance.
     ``states`` may supply (eps, phi) per fragment to skip the eigensolves.
     ``fragments`` restricts the eigensolves / products to a subset (the
     blocks and the global solve then need every fragment they touch)."""
@@ -395,7 +416,9 @@ def run(V, h, frag_lo, frag_dims, frag_states, tau=1e-6, window=None,
                                              int(frag_states[j]))
         dlo, dd, hp = apply_whole_H(V, h, frag_lo[j], frag_dims[j], phi[j])
         hphi[j], hbox[j] = hp, (dlo, dd)
-    pairs = [p for p in pair_list(frag_lo, frag_dims)
+    pairs = [p for p in pair_list(frag_lo, frag_dims, d_cut=d_cut,
+                                  atoms=atoms, frag_atom_ptr=frag_atom_ptr,
+                                  frag_atom_idx=frag_atom_idx)
              if phi[p[0]] is not None and phi[p[1]] is not None]
     Sb, Hb, H2 = [], [], []
     for (j, n) in pairs:

@@ -1051,6 +1051,46 @@ template void whole_h<float>(ofm_ctx*, const ofm_frags*, const float*, float*,
 // ---------------------------------------------------------------------------
 // grouped pair contraction: one workgroup per (pair, S|H) block
 // ---------------------------------------------------------------------------
+// Position of a lane inside the overlap cuboid, advanced point by point
+// (x fastest) instead of recomputed with divisions.
+struct Cursor {
+  int x, y, z;
+};
+__device__ __forceinline__ Cursor cursor_at(int k, int ox, int oy) {
+  Cursor c;
+  c.x = k % ox;
+  const int r = k / ox;
+  c.y = r % oy;
+  c.z = r / oy;
+  return c;
+}
+__device__ __forceinline__ void step1(Cursor& c, int ox, int oy) {
+  if (++c.x == ox) {
+    c.x = 0;
+    if (++c.y == oy) {
+      c.y = 0;
+      ++c.z;
+    }
+  }
+}
+__device__ __forceinline__ void stepn(Cursor& c, int d, int ox, int oy) {
+  c.x += d;
+  while (c.x >= ox) {
+    c.x -= ox;
+    if (++c.y == oy) {
+      c.y = 0;
+      ++c.z;
+    }
+  }
+}
+__device__ __forceinline__ int box_index(const int* org, const int* dims,
+                                         const Cursor& c) {
+  return (org[0] + c.x) + dims[0] * ((org[1] + c.y) + dims[1] * (org[2] + c.z));
+}
+
+// Work split of one block over the 4 waves: blocks with fewer than four
+// 16x16 tiles split the contraction length instead (k-slices), so every wave
+// has work; the slices are summed in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_pair(
     const PairTask* __restrict__ tasks, int ntask, const T* __restrict__ PHI,
@@ -1065,50 +1105,68 @@ __global__ __launch_bounds__(WG) void k_pair(
   const int ox = tk.om[0], oy = tk.om[1];
   const int K = ox * oy * tk.om[2];
   const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
+  const int ntiles = nta * ntb;
+  const int ks = ntiles >= 4 ? 1 : 4 / ntiles;
+  const int nch = (K + 15) / 16;
   __shared__ double blk[SMAX * SLD];
+  __shared__ double part[4][256];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  for (int tile = wave; tile < nta * ntb; tile += WG / 64) {
+  for (int unit = wave; unit < ntiles * ks; unit += WG / 64) {
+    const int tile = unit / ks, slice = unit % ks;
     const int ta = tile / ntb, tb = tile % ntb;
     const int ra = ta * 16 + r, rb = tb * 16 + r;
     const bool va = ra < tk.ma, vb = rb < tk.mb;
     const T* pa = A + (long long)(va ? ra : 0) * tk.lda;
     const T* pb = B + (long long)(vb ? rb : 0) * tk.ldb;
+    const int c0 = (int)((long long)slice * nch / ks);
+    const int c1 = (int)((long long)(slice + 1) * nch / ks);
+    int k = 16 * c0 + 4 * g;
+    Cursor cur = cursor_at(min(k, max(K - 1, 0)), ox, oy);
     d4 acc = {0, 0, 0, 0};
-    // the trip count must be uniform across the wave: an MFMA reads every
-    // lane's operands, so lanes may not leave the loop early
-    for (int kb = 0; kb < K; kb += 16) {
+    // the trip count is uniform across the wave: an MFMA reads every lane's
+    // operands, so lanes may not leave the loop early
+    for (int kb = 16 * c0; kb < 16 * c1; kb += 16) {
       double a[4], b[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int k = kb + 4 * g + u;
         a[u] = 0;
         b[u] = 0;
-        if (k < K) {
-          const int x = k % ox, rr = k / ox;
-          const int y = rr % oy, z = rr / oy;
-          const int ia = (tk.a_org[0] + x) +
-                         tk.a_dims[0] * ((tk.a_org[1] + y) +
-                                         tk.a_dims[1] * (tk.a_org[2] + z));
-          const int ib = (tk.b_org[0] + x) +
-                         tk.b_dims[0] * ((tk.b_org[1] + y) +
-                                         tk.b_dims[1] * (tk.b_org[2] + z));
-          if (va) a[u] = (double)pa[ia];
-          if (vb) b[u] = (double)pb[ib];
+        if (k + u < K) {
+          if (va) a[u] = (double)pa[box_index(tk.a_org, tk.a_dims, cur)];
+          if (vb) b[u] = (double)pb[box_index(tk.b_org, tk.b_dims, cur)];
+          step1(cur, ox, oy);
         }
       }
       acc = mfma_f64(a[0], b[0], acc);
       acc = mfma_f64(a[1], b[1], acc);
       acc = mfma_f64(a[2], b[2], acc);
       acc = mfma_f64(a[3], b[3], acc);
+      k += 16;
+      if (k < K) stepn(cur, 12, ox, oy);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = ta * 16 + g + 4 * i, col = tb * 16 + r;
-      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = acc[i];
+      const int rl = g + 4 * i;
+      if (ks == 1) {
+        const int row = ta * 16 + rl, col = tb * 16 + r;
+        if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = acc[i];
+      } else {
+        part[unit][rl * 16 + r] = acc[i];
+      }
     }
   }
   __syncthreads();
+  if (ks > 1) {
+    for (int e = threadIdx.x; e < ntiles * 256; e += WG) {
+      const int tile = e / 256, rl = (e % 256) / 16, cl = e % 16;
+      double v = 0;
+      for (int sl = 0; sl < ks; ++sl) v += part[tile * ks + sl][rl * 16 + cl];
+      const int row = (tile / ntb) * 16 + rl, col = (tile % ntb) * 16 + cl;
+      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = v;
+    }
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
     const int i = e / tk.mb, m = e % tk.mb;
     double v = blk[i * SLD + m];
@@ -1139,36 +1197,37 @@ __global__ __launch_bounds__(WG) void k_pair_x3(
   const int ox = tk.om[0], oy = tk.om[1];
   const int K = ox * oy * tk.om[2];
   const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
+  const int ntiles = nta * ntb;
+  const int ks = ntiles >= 4 ? 1 : 4 / ntiles;
+  const int nch = (K + 31) / 32;
   __shared__ double blk[SMAX * SLD];
+  __shared__ double part[4][256];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  for (int tile = wave; tile < nta * ntb; tile += WG / 64) {
+  for (int unit = wave; unit < ntiles * ks; unit += WG / 64) {
+    const int tile = unit / ks, slice = unit % ks;
     const int ta = tile / ntb, tb = tile % ntb;
     const int ra = ta * 16 + r, rb = tb * 16 + r;
     const bool va = ra < tk.ma, vb = rb < tk.mb;
     const float* pa = A + (long long)(va ? ra : 0) * tk.lda;
     const float* pb = B + (long long)(vb ? rb : 0) * tk.ldb;
+    const int c0 = (int)((long long)slice * nch / ks);
+    const int c1 = (int)((long long)(slice + 1) * nch / ks);
+    int k = 32 * c0 + 8 * g;
+    Cursor cur = cursor_at(min(k, max(K - 1, 0)), ox, oy);
     f4v acc = {0, 0, 0, 0};
     double tot[4] = {0, 0, 0, 0};
     int since = 0;
-    for (int kb = 0; kb < K; kb += 32) {   // uniform trip count
+    for (int kb = 32 * c0; kb < 32 * c1; kb += 32) {   // uniform trip count
       float a[8], b[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int k = kb + 8 * g + u;
         a[u] = 0.f;
         b[u] = 0.f;
-        if (k < K) {
-          const int x = k % ox, rr = k / ox;
-          const int y = rr % oy, z = rr / oy;
-          const int ia = (tk.a_org[0] + x) +
-                         tk.a_dims[0] * ((tk.a_org[1] + y) +
-                                         tk.a_dims[1] * (tk.a_org[2] + z));
-          const int ib = (tk.b_org[0] + x) +
-                         tk.b_dims[0] * ((tk.b_org[1] + y) +
-                                         tk.b_dims[1] * (tk.b_org[2] + z));
-          if (va) a[u] = pa[ia];
-          if (vb) b[u] = pb[ib];
+        if (k + u < K) {
+          if (va) a[u] = pa[box_index(tk.a_org, tk.a_dims, cur)];
+          if (vb) b[u] = pb[box_index(tk.b_org, tk.b_dims, cur)];
+          step1(cur, ox, oy);
         }
       }
       acc = mfma_x3(a, b, acc);
@@ -1178,15 +1237,32 @@ __global__ __launch_bounds__(WG) void k_pair_x3(
         acc = f4v{0, 0, 0, 0};
         since = 0;
       }
+      k += 32;
+      if (k < K) stepn(cur, 24, ox, oy);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       tot[i] += (double)acc[i];
-      const int row = ta * 16 + 4 * g + i, col = tb * 16 + r;
-      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = tot[i];
+      const int rl = 4 * g + i;
+      if (ks == 1) {
+        const int row = ta * 16 + rl, col = tb * 16 + r;
+        if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = tot[i];
+      } else {
+        part[unit][rl * 16 + r] = tot[i];
+      }
     }
   }
   __syncthreads();
+  if (ks > 1) {
+    for (int e = threadIdx.x; e < ntiles * 256; e += WG) {
+      const int tile = e / 256, rl = (e % 256) / 16, cl = e % 16;
+      double v = 0;
+      for (int sl = 0; sl < ks; ++sl) v += part[tile * ks + sl][rl * 16 + cl];
+      const int row = (tile / ntb) * 16 + rl, col = (tile % ntb) * 16 + cl;
+      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = v;
+    }
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
     const int i = e / tk.mb, m = e % tk.mb;
     double v = blk[i * SLD + m];

@@ -62,7 +62,7 @@ def _blocks(r, pj, pn):
     return np.concatenate(Hs), np.concatenate(Ss), np.concatenate(diag)
 
 
-@pytest.mark.parametrize("case", ["tiny", "random"])
+@pytest.mark.parametrize("case", ["tiny", "random", "random_wide"])
 def test_mixed_elements_imported_states(mctx, case):
     _say("mixed elements", case)
     if case == "tiny":
@@ -77,7 +77,8 @@ def test_mixed_elements_imported_states(mctx, case):
         dims = rng.integers(5, 12, size=(7, 3))
         lo = np.array([[rng.integers(0, shape[a] - dims[f_, a] + 1)
                         for a in range(3)] for f_ in range(7)])
-        st = rng.integers(1, 9, size=7)
+        st = rng.integers(1, 9, size=7) if case == "random" else \
+            rng.integers(14, 41, size=7)
     r = O.run(V, 0.5, lo, dims, st, solve=False)
     s = box_system(shape, 0.5, lo, dims, st, V=V)
     f = _build(mctx, s)

@@ -113,10 +113,12 @@ def test_elements_imported_states_tiny(ctx, tiny0, tiny0_oracle):
     assert np.abs(g["E"] - ref["E"]).max() < 1e-10
 
 
-def test_elements_random_boxes(ctx):
+@pytest.mark.parametrize("srange", [(1, 9), (14, 41)])
+def test_elements_random_boxes(ctx, srange):
     """Uneven boxes with halo-only pairs, ragged overlaps and differing state
-    counts; oracle states imported so the comparison is gauge-free."""
-    _say("elements, random uneven boxes")
+    counts (1 to 9 MFMA tiles per block); oracle states imported so the
+    comparison is gauge-free."""
+    _say("elements, random uneven boxes, states", srange)
     rng = np.random.default_rng(21)
     shape = (30, 22, 18)
     V = -np.abs(rng.standard_normal(shape[::-1]))
@@ -124,7 +126,7 @@ def test_elements_random_boxes(ctx):
     dims = rng.integers(5, 12, size=(nf, 3))
     lo = np.array([[rng.integers(0, shape[a] - dims[f_, a] + 1)
                     for a in range(3)] for f_ in range(nf)])
-    states = rng.integers(1, 9, size=nf)
+    states = rng.integers(srange[0], srange[1], size=nf)
     r = O.run(V, 0.5, lo, dims, states, solve=False)
     s = box_system(shape, 0.5, lo, dims, states, V=V)
     f = _build(ctx, s)
@@ -320,3 +322,27 @@ def test_graph_replay_and_variants_bit_identical(ctx):
             assert np.array_equal(a, b)
     ref = O.run(V, 0.5, lo, dims, st, solve=False)
     assert np.abs(outs[0][0] - np.concatenate(ref.eps)).max() < 1e-8
+
+
+@pytest.mark.parametrize("d_cut", [1.5, 3.0])
+def test_distance_cutoff_end_to_end(ctx, tiny0, d_cut):
+    """The planner's atom-distance pruning gives the oracle's pair list, and
+    the pruned basis gives the oracle's pruned window eigenvalues."""
+    s = tiny0
+    _say("d_cut", d_cut)
+    kw = dict(atoms=s.atoms, frag_atom_ptr=s.frag_atom_ptr,
+              frag_atom_idx=s.frag_atom_idx)
+    r = O.run(s.potential(), 0.5, s.frag_lo, s.frag_dims, s.frag_states,
+              d_cut=d_cut, **kw)
+    f = P.ofm_build_fragments(
+        ctx, (24, 12, 12), 0.5, s.potential(), s.frag_lo, s.frag_dims,
+        s.frag_states, atom_xyz=s.atoms, frag_atom_ptr=s.frag_atom_ptr,
+        frag_atom_idx=s.frag_atom_idx, d_cut=d_cut)
+    pj, pn, off = f.pairs()
+    assert [(int(a), int(b)) for a, b in zip(pj, pn)] == r.pairs
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0
+    m = P.ofm_matrix_elements(ctx, f)
+    g = P.ofm_solve_global(ctx, m, 1e-6, -1e30,
+                           O.window_below_cutoff(r.eps)[1])
+    assert np.abs(g["E"] - r.solve["window"]).max() < 1e-8

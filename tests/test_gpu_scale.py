@@ -1,0 +1,108 @@
+"""Full-size run of the polythiophene-like system (4096 overlapping trimer
+fragments, 32^3..48^3 boxes, 24 states each, 98,304 basis states) in the
+mixed form: every fragment converges; a sample of three overlapping
+fragments is checked against the oracle's own eigenpairs (1e-5 Ha); with the
+oracle's states imported for that sample, its blocks match the oracle's
+(1e-6 of max|H|); properties that hold at any size are checked on all
+blocks (S_jj = I exactly, |S| <= 1)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from ofm_inputs import thiophene_polymer
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+P = pytest.importorskip("paper_1011_4764_amd")
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+def _sample(s):
+    """Three consecutive trimers of chain 0 with the smallest total volume."""
+    vol = s.frag_dims.prod(1)
+    best = min(range(0, 62), key=lambda k: vol[k:k + 3].sum())
+    return [best, best + 1, best + 2]
+
+
+@pytest.mark.timeout(600)
+def test_thiophene_mixed_full_size():
+    s = thiophene_polymer(0)
+    V = s.potential()
+    g = s.grid
+    _say("thiophene", g.nx, g.ny, g.nz, s.n_frag, "fragments", s.n_basis,
+         "states")
+    ctx = P.ofm_create(0, None, P.OFM_MIXED_BF16X3)
+    t0 = time.perf_counter()
+    f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
+                              s.frag_dims, s.frag_states, origin=g.origin)
+    t1 = time.perf_counter()
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    t2 = time.perf_counter()
+    m = P.ofm_matrix_elements(ctx, f)
+    t3 = time.perf_counter()
+    times = ctx.stage_times()
+    _say(f"build {t1 - t0:.2f} s, fragments {t2 - t1:.2f} s "
+         f"({s.n_basis / (t2 - t1):.0f} eigenstates/s, iterations max "
+         f"{it.max()} mean {it.mean():.1f}), elements {t3 - t2:.2f} s "
+         f"({2 * m.n_values / (t3 - t2):.3g} elements/s, {f.n_pairs} pairs)")
+    _say("library stage times", times)
+    assert st == 0 and cv.all()
+    H, S = P.ofm_mats_copy(m)
+    pj, pn, off = f.pairs()
+    st_ = s.frag_states
+    diag = pj == pn
+    for p in np.nonzero(diag)[0]:
+        k = int(st_[pj[p]])
+        assert np.array_equal(S[off[p]:off[p] + k * k].reshape(k, k),
+                              np.eye(k))
+    assert np.abs(S).max() <= 1 + 1e-6
+    m.close()
+    # sampled fragments against the oracle's own eigenpairs
+    samp = _sample(s)
+    _say("sample", samp, [tuple(s.frag_dims[j]) for j in samp])
+    boff = np.concatenate([[0], np.cumsum(st_)])
+    ref_states = {}
+    for j in samp:
+        e_o, phi_o = O.fragment_states(V, g.h, s.frag_lo[j], s.frag_dims[j],
+                                       int(st_[j]))
+        ref_states[j] = (e_o, phi_o)
+        err = np.abs(eps[boff[j]:boff[j + 1]] - e_o).max()
+        _say(f"  fragment {j}: max |eps - oracle| {err:.2e} Ha")
+        assert err < 1e-5
+    # import the oracle's states for the sample; compare their blocks
+    for j in samp:
+        P.ofm_set_states(f, j, ref_states[j][1].T, ref_states[j][0])
+    m = P.ofm_matrix_elements(ctx, f)
+    H, S = P.ofm_mats_copy(m)
+    hp, hbox = {}, {}
+    for j in samp:
+        dlo, dd, hpj = O.apply_whole_H(V, g.h, s.frag_lo[j], s.frag_dims[j],
+                                       ref_states[j][1])
+        hp[j], hbox[j] = hpj, (dlo, dd)
+    phi = {j: ref_states[j][1] for j in samp}
+    checked = 0
+    for p in range(len(pj)):
+        j, n = int(pj[p]), int(pn[p])
+        if j not in samp or n not in samp:
+            continue
+        Sb, Hb, _ = O.pair_blocks(j, n, s.frag_lo, s.frag_dims, phi, hp, hbox)
+        if j == n:
+            Hb = 0.5 * (Hb + Hb.T)
+            Sb = np.eye(Sb.shape[0])
+        k = Sb.size
+        gH = H[off[p]:off[p] + k].reshape(Hb.shape)
+        gS = S[off[p]:off[p] + k].reshape(Sb.shape)
+        eh = np.abs(gH - Hb).max() / max(np.abs(Hb).max(), 1e-300)
+        es = np.abs(gS - Sb).max()
+        _say(f"  block ({j},{n}): H rel {eh:.2e}, S {es:.2e}")
+        assert eh < 1e-6 and es < 1e-6
+        checked += 1
+    assert checked == 6
+    m.close()
+    f.close()
+    ctx.close()

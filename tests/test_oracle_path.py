@@ -253,3 +253,32 @@ def test_error_shrinks_with_fragment_width():
     assert errs[-1] < 1e-12
     for a, b in zip(errs, errs[1:]):
         assert b <= a * 1.1 + 1e-12
+
+
+def test_distance_cutoff_pairs(tiny0):
+    """Atom-distance pruning (Sec. III-C): on the tiny chain the end
+    fragments' closest atoms are one chain spacing (about 2 bohr) apart, so a
+    1.5 bohr cutoff drops exactly the pair (0, 2), a 3 bohr cutoff keeps
+    everything; brute-force distances decide the same."""
+    s = tiny0
+    full = O.pair_list(s.frag_lo, s.frag_dims)
+    kw = dict(atoms=s.atoms, frag_atom_ptr=s.frag_atom_ptr,
+              frag_atom_idx=s.frag_atom_idx)
+    assert O.pair_list(s.frag_lo, s.frag_dims, d_cut=3.0, **kw) == full
+    cut = O.pair_list(s.frag_lo, s.frag_dims, d_cut=1.5, **kw)
+    assert set(full) - set(cut) == {(0, 2)}
+    a0 = s.atoms[s.frag_atom_idx[s.frag_atom_ptr[0]:s.frag_atom_ptr[1]]]
+    a2 = s.atoms[s.frag_atom_idx[s.frag_atom_ptr[2]:s.frag_atom_ptr[3]]]
+    dmin = min(np.linalg.norm(p - q) for p in a0 for q in a2)
+    assert 1.5 < dmin < 3.0
+    # the pruned pencil is the full one with the (0, 2) blocks zeroed
+    r = O.run(s.potential(), 0.5, s.frag_lo, s.frag_dims, s.frag_states,
+              d_cut=1.5, **kw)
+    assert r.pairs == cut
+    ref = O.run(s.potential(), 0.5, s.frag_lo, s.frag_dims, s.frag_states)
+    H0 = ref.H.copy()
+    H0[0:6, 12:18] = 0.0
+    H0[12:18, 0:6] = 0.0
+    assert np.array_equal(r.H, H0)
+    assert np.array_equal(r.S, ref.S)      # the (0, 2) overlap is zero anyway
+    assert np.abs(r.solve["E"] - ref.solve["E"]).max() > 1e-3
