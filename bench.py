@@ -46,6 +46,10 @@ def parse():
                     help="energy window above the lowest OFM eigenvalue (Ha)")
     ap.add_argument("--tol", type=float, default=0.0,
                     help="eigensolver residual bound (0: the form's default)")
+    ap.add_argument("--degree", type=int, default=0,
+                    help="Chebyshev filter degree, FP64 runs (0: default)")
+    ap.add_argument("--degree-mixed", type=int, default=0,
+                    help="Chebyshev filter degree, mixed runs (0: default)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-form comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -148,7 +152,9 @@ def main():
             f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V_dev,
                                       system.frag_lo, system.frag_dims,
                                       system.frag_states, origin=g.origin)
-            st, eps, it, cv = P.ofm_solve_fragments(ctx, f, tol=tol)
+            deg = args.degree if precision == "fp64" else args.degree_mixed
+            st, eps, it, cv = P.ofm_solve_fragments(ctx, f, tol=tol,
+                                                    degree=deg)
             m = P.ofm_matrix_elements(ctx, f)
             gs = P.ofm_solve_global(ctx, m, 1e-6)
             E = gs["E"]

@@ -7,9 +7,11 @@
 // Chebyshev-filtered block subspace iteration:
 //   X <- p_d(H_j) X          (degree-d scaled Chebyshev filter damping
 //                             [theta_b, lambda_max], every fragment at once)
-//   X <- X R^-1  (twice)     (CholQR2, FP64 Cholesky of the Gram matrix)
-//   HX <- H_j X; G = X^T HX; G = Y Theta Y^T  (Rayleigh-Ritz, FP64 Jacobi)
-//   X <- X Y, HX <- HX Y, r_i = ||HX_i - theta_i X_i||
+//   X <- X R1^-1; R2 from X^T X  (CholQR2, FP64 Cholesky of the Gram
+//                                 matrices; R2 is not applied separately)
+//   HX <- H_j X; G = R2^-T X^T HX R2^-1 = Y Theta Y^T  (Rayleigh-Ritz, FP64
+//                                 Jacobi)
+//   X <- X R2^-1 Y, HX <- HX R2^-1 Y, r_i = ||HX_i - theta_i X_i||
 // until every wanted residual is below tol; a converged fragment drops out
 // of all later launches.  The Chebyshev filter plays the role of the
 // preconditioner of a block-Davidson correction step.
@@ -233,15 +235,17 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         nb2 += (double)d.npts * d.bw * d.bw;
       }
   };
+  // CholQR2: the first factor is applied to X; the second one (R2^-1, left
+  // in d_Q) is folded into the Rayleigh-Ritz rotation
   auto cholqr = [&]() {
     double nb, npt, nb2;
     sums(nb, npt, nb2);
-    for (int pass = 0; pass < 2; ++pass) {
-      k::gram<T>(c, f, X, X, f->d_G, f->d_active, nb * w, nb2 * 2.0 * 0.5);
-      k::cholinv(s, f, f->d_G, f->d_Q, f->d_active, f->d_flags);
-      k::rotate<T>(c, f, X, nullptr, f->d_Q, nullptr, nullptr, f->d_active,
-                   1, 2 * nb * w, nb2 * 2.0 * 0.5);
-    }
+    k::gram<T>(c, f, X, X, f->d_G, f->d_active, nb * w, nb2 * 2.0 * 0.5);
+    k::cholinv(s, f, f->d_G, f->d_Q, f->d_active, f->d_flags);
+    k::rotate<T>(c, f, X, nullptr, f->d_Q, nullptr, nullptr, f->d_active, 1,
+                 2 * nb * w, nb2 * 2.0 * 0.5);
+    k::gram<T>(c, f, X, X, f->d_G, f->d_active, nb * w, nb2 * 2.0 * 0.5);
+    k::cholinv(s, f, f->d_G, f->d_Q, f->d_active, f->d_flags);
   };
   auto apply_plain = [&]() {
     double nb, npt, nb2;
@@ -258,7 +262,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       k::gram<T>(c, f, X, HX, f->d_G, f->d_active, 2 * nb * w, nb2 * 2.0);
     else   // mixed form: Rayleigh-Ritz product as split-BF16 x3 on MFMA
       k::gram_x3(c, f, X, HX, f->d_G, f->d_active, 2 * nb * w, nb2 * 2.0);
-    k::rr_eig(s, f, f->d_G, f->d_Q, f->d_theta, f->d_active);
+    k::rr_eig(s, f, f->d_G, f->d_Q, f->d_theta, f->d_active, 1);
     k::rotate<T>(c, f, X, HX, f->d_Q, f->d_theta, f->d_res_partial,
                  f->d_active, 0, 4 * nb * w, nb2 * 4.0);
     OFM_HIP(hipMemsetAsync(f->d_nactive, 0, sizeof(int), s));

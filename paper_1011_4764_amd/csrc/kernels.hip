@@ -642,10 +642,14 @@ void cholinv(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz: cyclic two-sided Jacobi on the symmetric projected matrix
 // ---------------------------------------------------------------------------
+// With `pre`, Q holds on entry the inverse R^-1 of the last Cholesky factor
+// of X^T X (the second CholQR pass, not applied to X): the projected matrix
+// becomes R^-T (X^T H X) R^-1 and the rotation returned is R^-1 Y, so the
+// second orthonormalisation and the Rayleigh-Ritz rotation cost one pass.
 __global__ __launch_bounds__(WG) void k_rr_eig(
     const FragDev* __restrict__ F, int nf, const double* __restrict__ partial,
     double* __restrict__ Q, double* __restrict__ theta,
-    const int* __restrict__ active) {
+    const int* __restrict__ active, int pre) {
   const int j = blockIdx.x;
   if (j >= nf) return;
   if (active && !active[j]) return;
@@ -653,11 +657,42 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
   const int n = fr.bw;
   __shared__ double A[SMAX * SLD];
   __shared__ double U[SMAX * SLD];
+  __shared__ double Pm[SMAX * SLD];
   __shared__ double cs[SMAX / 2], sn[SMAX / 2];
   __shared__ int pp[SMAX / 2], qq[SMAX / 2];
   __shared__ double red[WG / 64];
   __shared__ double offn, totn;
   load_sym(fr, partial, A, SLD, 0);
+  if (pre) {
+    const double* Qj0 = Q + fr.small_off;
+    for (int e = threadIdx.x; e < n * n; e += WG)
+      Pm[(e / n) * SLD + e % n] = Qj0[e];
+    __syncthreads();
+    // U = A P, then A = P^T U (symmetrised)
+    for (int e = threadIdx.x; e < n * n; e += WG) {
+      const int r = e / n, c = e % n;
+      double acc = 0;
+      for (int k = 0; k < n; ++k) acc += A[r * SLD + k] * Pm[k * SLD + c];
+      U[r * SLD + c] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += WG) {
+      const int r = e / n, c = e % n;
+      double acc = 0;
+      for (int k = 0; k < n; ++k) acc += Pm[k * SLD + r] * U[k * SLD + c];
+      A[r * SLD + c] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += WG) {
+      const int r = e / n, c = e % n;
+      if (c > r) {
+        const double m = 0.5 * (A[r * SLD + c] + A[c * SLD + r]);
+        A[r * SLD + c] = m;
+        A[c * SLD + r] = m;
+      }
+    }
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < n * n; e += WG)
     U[(e / n) * SLD + e % n] = (e / n == e % n) ? 1.0 : 0.0;
   const int n2 = n + (n & 1);       // round-robin over an even count
@@ -750,14 +785,22 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
       rank += (dm < d) || (dm == d && m < i);
     }
     theta[fr.th_off + rank] = d;
-    for (int k2 = 0; k2 < n; ++k2) Qj[k2 * n + rank] = U[k2 * SLD + i];
+    if (pre) {
+      for (int k2 = 0; k2 < n; ++k2) {
+        double acc = 0;
+        for (int mm = 0; mm < n; ++mm) acc += Pm[k2 * SLD + mm] * U[mm * SLD + i];
+        Qj[k2 * n + rank] = acc;
+      }
+    } else {
+      for (int k2 = 0; k2 < n; ++k2) Qj[k2 * n + rank] = U[k2 * SLD + i];
+    }
   }
 }
 
 void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
-            double* theta, const int* active) {
+            double* theta, const int* active, int pre) {
   hipLaunchKernelGGL(k_rr_eig, dim3(f->n_frag), dim3(WG), 0, s, f->d_frag,
-                     f->n_frag, G, Q, theta, active);
+                     f->n_frag, G, Q, theta, active, pre);
   OFM_HIP(hipGetLastError());
 }
 
@@ -776,11 +819,12 @@ __global__ __launch_bounds__(RCH) void k_rotate(
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
   const int bw = fr.bw;
-  __shared__ double q[SMAX * SMAX];
+  // products accumulate in the storage type (FP32 in the mixed form)
+  __shared__ T q[SMAX * SMAX];
   __shared__ double th[SMAX];
   __shared__ double red[RCH / 64][SMAX];
   const double* Qj = Q + fr.small_off;
-  for (int e = threadIdx.x; e < bw * bw; e += RCH) q[e] = Qj[e];
+  for (int e = threadIdx.x; e < bw * bw; e += RCH) q[e] = (T)Qj[e];
   if (HX)
     for (int i = threadIdx.x; i < bw; i += RCH) th[i] = theta[fr.th_off + i];
   __syncthreads();
@@ -801,13 +845,13 @@ __global__ __launch_bounds__(RCH) void k_rotate(
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = 0; i < bw; ++i) {
-    double a = 0, h = 0;
+    T a = 0, h = 0;
 #pragma unroll
     for (int k = 0; k < BMAX; ++k) {
       if (k < bw && (!upper || k <= i)) {
-        const double qk = q[k * bw + i];
-        a += (double)x[k] * qk;
-        if (HX) h += (double)hx[k] * qk;
+        const T qk = q[k * bw + i];
+        a += x[k] * qk;
+        if (HX) h += hx[k] * qk;
       }
     }
     if (ok) xp[(long long)i * fr.ld] = (T)a;

@@ -249,7 +249,7 @@ void gram_x3(ofm_ctx* c, const ofm_frags* f, const float* A, const float* B,
 void cholinv(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
              const int* active, int* flags);
 void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
-            double* theta, const int* active);
+            double* theta, const int* active, int pre);
 template <typename T>
 void rotate(ofm_ctx* c, const ofm_frags* f, T* X, T* HX, const double* Q,
             const double* theta, double* res_partial, const int* active,
