@@ -191,6 +191,23 @@ ofm_status ofm_get_hphi(const ofm_frags* f, int j, double* hphi);
 ofm_status ofm_apply_fragment_h(ofm_ctx* ctx, ofm_frags* f, int j, int nvec,
                                 const double* x, double* y);
 
+/* Build every fragment Hamiltonian from the wells of the fragment's own
+   atoms instead of the global V restricted to the box (the paper builds the
+   fragment Hamiltonian from the fragment's own charge density, Sec. II):
+   V_j(r) = sum_{a in fragment j} -Z_a exp(-|r - R_a|^2 / (2 sigma^2)) for
+   |r - R_a| < r_cut, at the box's grid points (origin + index * h).
+   H|phi> keeps the whole-system V given to ofm_build_fragments.
+   atom_xyz: 3*n_atoms doubles; Z: n_atoms; frag_atom_ptr: n_frag + 1;
+   frag_atom_idx: the atoms of each fragment (all host).  Call before
+   ofm_solve_fragments; states computed earlier are not recomputed.
+   Errors: OFM_E_INVALID for sigma or r_cut <= 0, non-finite inputs, or an
+   atom index outside [0, n_atoms). */
+ofm_status ofm_set_fragment_wells(ofm_frags* f, int n_atoms,
+                                  const double* atom_xyz, const double* Z,
+                                  double sigma, double r_cut,
+                                  const long long* frag_atom_ptr,
+                                  const int* frag_atom_idx);
+
 /* Pin the stencil variant used for fragments f (0..2: 256, 512, 1024 plane
    points per workgroup in FP64; 512, 1024, 2048 in the mixed form), or -1 to
    let ofm_solve_fragments pick by timing the variants (the default).  Every

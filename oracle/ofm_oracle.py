@@ -51,7 +51,7 @@ __all__ = [
     "hamiltonian_box", "fragment_states", "canonical_sign", "dilated_box",
     "apply_whole_H", "pair_list", "pair_blocks", "assemble", "global_solve",
     "full_grid_eigs", "line_spectrum", "box_spectrum", "OracleResult",
-    "run", "window_below_cutoff",
+    "run", "window_below_cutoff", "own_wells",
 ]
 
 #: stencil reach (points) of the 4th-order central second difference
@@ -130,9 +130,10 @@ def _slice(V, lo, dims):
              lo[0]:lo[0] + dims[0]]
 
 
-def hamiltonian_box(V, h, lo, dims, walls="box"):
+def hamiltonian_box(V, h, lo, dims, walls="box", Vbox=None):
     """Sparse H restricted to a box.  walls="box": the fragment Hamiltonian
-    (walls at the box faces, V restricted to the box).  walls="global": the
+    (walls at the box faces, V restricted to the box, or the box potential
+    ``Vbox`` (dims[2], dims[1], dims[0]) when given).  walls="global": the
     rows/columns of the whole-system Hamiltonian that fall in the box."""
     nz, ny, nx = V.shape
     lo = tuple(int(v) for v in lo)
@@ -141,7 +142,20 @@ def hamiltonian_box(V, h, lo, dims, walls="box"):
         T = kinetic_box(dims, (0, 0, 0), dims, h)
     else:
         T = kinetic_box((nx, ny, nz), lo, dims, h)
-    return (T + sp.diags(_slice(V, lo, dims).ravel())).tocsr()
+    vb = _slice(V, lo, dims) if Vbox is None else np.asarray(Vbox)
+    return (T + sp.diags(vb.ravel())).tocsr()
+
+
+def own_wells(h, origin, lo, dims, atoms, Z, members, sigma=0.8, r_cut=8.0):
+    """Potential of a fragment's own atoms on its box: the wells of the atoms
+    listed in ``members`` only (the fragment Hamiltonian built from the
+    fragment's own atoms, as the paper builds it from the fragment's own
+    charge density, Sec. II)."""
+    members = np.asarray(members, dtype=np.int64)
+    box_origin = np.asarray(origin, float) + h * np.asarray(lo, float)
+    return gaussian_potential(tuple(int(d) for d in dims), h, box_origin,
+                              np.asarray(atoms)[members],
+                              np.asarray(Z)[members], sigma, r_cut)
 
 
 def canonical_sign(phi):
@@ -154,11 +168,12 @@ def canonical_sign(phi):
     return phi
 
 
-def fragment_states(V, h, lo, dims, s, dense_max=14000):
+def fragment_states(V, h, lo, dims, s, dense_max=14000, Vbox=None):
     """Lowest s eigenpairs of the fragment Hamiltonian: dense symmetric
     eigensolver for boxes up to dense_max points, ARPACK (smallest
-    algebraic, tol 1e-12) above that.  Returns (eps (s,), phi (n_j, s))."""
-    H = hamiltonian_box(V, h, lo, dims, walls="box")
+    algebraic, tol 1e-12) above that.  Returns (eps (s,), phi (n_j, s)).
+    ``Vbox`` replaces the global V on the box (own-atoms fragment)."""
+    H = hamiltonian_box(V, h, lo, dims, walls="box", Vbox=Vbox)
     n = H.shape[0]
     if n <= dense_max:
         w, U = sla.eigh(H.toarray(), subset_by_index=[0, s - 1],
@@ -395,10 +410,12 @@ def window_below_cutoff(eps):
 
 def run(V, h, frag_lo, frag_dims, frag_states, tau=1e-6, window=None,
         states=None, fragments=None, solve=True, d_cut=None, atoms=None,
-        frag_atom_ptr=None, frag_atom_idx=None):
+        frag_atom_ptr=None, frag_atom_idx=None, own=None):
     """Fragment states -> whole-H products -> pair blocks -> global solve.
 
     ``d_cut`` and the atom lists prune the pair set by atom distance.
+    ``own = (origin, Z, sigma, r_cut)`` builds every fragment Hamiltonian
+    from the wells of the fragment's own atoms (H|phi> keeps the global V).
     ``states`` may supply (eps, phi) per fragment to skip the eigensolves.
     ``fragments`` restricts the eigensolves / products to a subset (the
     blocks and the global solve then need every fragment they touch)."""
@@ -412,8 +429,15 @@ def run(V, h, frag_lo, frag_dims, frag_states, tau=1e-6, window=None,
         if states is not None:
             eps[j], phi[j] = states[0][j], states[1][j]
         else:
+            vb = None
+            if own is not None:   # (origin, Z, sigma, r_cut): own-atoms wells
+                o_origin, o_Z, o_sigma, o_rc = own
+                vb = own_wells(h, o_origin, frag_lo[j], frag_dims[j], atoms,
+                               o_Z, frag_atom_idx[frag_atom_ptr[j]:
+                                                  frag_atom_ptr[j + 1]],
+                               o_sigma, o_rc)
             eps[j], phi[j] = fragment_states(V, h, frag_lo[j], frag_dims[j],
-                                             int(frag_states[j]))
+                                             int(frag_states[j]), Vbox=vb)
         dlo, dd, hp = apply_whole_H(V, h, frag_lo[j], frag_dims[j], phi[j])
         hphi[j], hbox[j] = hp, (dlo, dd)
     pairs = [p for p in pair_list(frag_lo, frag_dims, d_cut=d_cut,

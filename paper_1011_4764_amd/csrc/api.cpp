@@ -157,6 +157,10 @@ T* arena(void* p) {
 }
 
 void free_frags(ofm_frags* f) {
+  if (f->own_wells) {
+    dev_free(f->d_vf);
+    dev_free(f->d_vf32);
+  }
   void* ptrs[] = {f->d_frag, f->d_v, f->d_v32, f->d_x, f->d_p, f->d_hx,
                   f->d_hphi, f->d_tiles[0], f->d_tiles[1], f->d_tiles[2],
                   f->d_stiles, f->d_rtiles, f->d_G,
@@ -502,6 +506,8 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
       f->d_rtiles = dev_alloc<int2>(rtiles.size());
       f->d_v = dev_alloc<double>(f->v_total);
       f->d_v32 = dev_alloc<float>(f->v_total);
+      f->d_vf = f->d_v;
+      f->d_vf32 = f->d_v32;
       f->d_x = dev_alloc<char>(f->x_total * w);
       f->d_p = dev_alloc<char>(f->x_total * w);
       f->d_hx = dev_alloc<char>(f->x_total * w);
@@ -774,6 +780,74 @@ ofm_status ofm_apply_fragment_h(ofm_ctx* c, ofm_frags* f, int j, int nvec,
     dev_free(din);
     dev_free(dout);
     dev_free(dt);
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_set_fragment_wells(ofm_frags* f, int n_atoms,
+                                  const double* atom_xyz, const double* Z,
+                                  double sigma, double r_cut,
+                                  const long long* frag_atom_ptr,
+                                  const int* frag_atom_idx) {
+  if (!f) return OFM_E_INVALID;
+  ofm_ctx* c = f->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(n_atoms >= 1 && atom_xyz && Z && frag_atom_ptr && frag_atom_idx,
+                OFM_E_INVALID, "atoms, depths and fragment lists are required");
+    OFM_REQUIRE(std::isfinite(sigma) && sigma > 0 && std::isfinite(r_cut) &&
+                    r_cut > 0, OFM_E_INVALID, "sigma and r_cut must be > 0");
+    for (long long a = 0; a < 3LL * n_atoms; ++a)
+      OFM_REQUIRE(std::isfinite(atom_xyz[a]), OFM_E_INVALID,
+                  "non-finite atom coordinate");
+    for (int a = 0; a < n_atoms; ++a)
+      OFM_REQUIRE(std::isfinite(Z[a]), OFM_E_INVALID, "non-finite well depth");
+    const int nf = f->n_frag;
+    OFM_REQUIRE(frag_atom_ptr[0] == 0, OFM_E_INVALID, "frag_atom_ptr[0] != 0");
+    for (int j = 0; j < nf; ++j)
+      OFM_REQUIRE(frag_atom_ptr[j + 1] >= frag_atom_ptr[j], OFM_E_INVALID,
+                  "frag_atom_ptr must be non-decreasing");
+    const long long nnz = frag_atom_ptr[nf];
+    for (long long a = 0; a < nnz; ++a)
+      OFM_REQUIRE(frag_atom_idx[a] >= 0 && frag_atom_idx[a] < n_atoms,
+                  OFM_E_INVALID, "atom index out of range");
+    use_device(c);
+    hipStream_t s = c->stream;
+    if (!f->own_wells) {
+      f->d_vf = dev_alloc<double>(f->v_total);
+      f->d_vf32 = dev_alloc<float>(f->v_total);
+      f->own_wells = true;
+    }
+    double* dxyz = dev_alloc<double>(3LL * n_atoms);
+    double* dZ = dev_alloc<double>(n_atoms);
+    long long* dptr = dev_alloc<long long>(nf + 1);
+    int* didx = dev_alloc<int>(nnz);
+    int* bad = dev_alloc<int>(1);
+    try {
+      OFM_HIP(hipMemcpyAsync(dxyz, atom_xyz, sizeof(double) * 3 * n_atoms,
+                             hipMemcpyHostToDevice, s));
+      OFM_HIP(hipMemcpyAsync(dZ, Z, sizeof(double) * n_atoms,
+                             hipMemcpyHostToDevice, s));
+      OFM_HIP(hipMemcpyAsync(dptr, frag_atom_ptr, sizeof(long long) * (nf + 1),
+                             hipMemcpyHostToDevice, s));
+      if (nnz)
+        OFM_HIP(hipMemcpyAsync(didx, frag_atom_idx, sizeof(int) * nnz,
+                               hipMemcpyHostToDevice, s));
+      k::fragment_wells(s, f, dxyz, dZ, dptr, didx, sigma, r_cut);
+      // the filter's spectral bound follows the fragment potential
+      OFM_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+      hipLaunchKernelGGL(k_vstats, dim3(nf), dim3(256), 0, s, f->d_frag, nf,
+                         f->d_vf, bad);
+      OFM_HIP(hipGetLastError());
+      std::vector<FragDev> back(nf);
+      OFM_HIP(hipMemcpyAsync(back.data(), f->d_frag, sizeof(FragDev) * nf,
+                             hipMemcpyDeviceToHost, s));
+      OFM_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < nf; ++j) f->host[j].vmax = back[j].vmax;
+    } catch (...) {
+      dev_free(dxyz); dev_free(dZ); dev_free(dptr); dev_free(didx); dev_free(bad);
+      throw;
+    }
+    dev_free(dxyz); dev_free(dZ); dev_free(dptr); dev_free(didx); dev_free(bad);
     return OFM_OK;
   });
 }

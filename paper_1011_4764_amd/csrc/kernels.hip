@@ -75,6 +75,53 @@ void restrict_potential(hipStream_t s, const double* V, const ofm_grid& g,
 }
 
 // ---------------------------------------------------------------------------
+// own-atoms fragment potential: wells of the fragment's atoms on its box
+// ---------------------------------------------------------------------------
+__global__ void k_wells(const FragDev* __restrict__ F, int nf,
+                        const double* __restrict__ xyz,
+                        const double* __restrict__ Z,
+                        const long long* __restrict__ ptr,
+                        const int* __restrict__ idx, double ox, double oy,
+                        double oz, double h, double inv2s2, double rc2,
+                        double* __restrict__ out, float* __restrict__ out32) {
+  const int j = blockIdx.y;
+  if (j >= nf) return;
+  const FragDev f = F[j];
+  const long long a0 = ptr[j], a1 = ptr[j + 1];
+  for (int p = blockIdx.x * WG + threadIdx.x; p < f.npts;
+       p += gridDim.x * WG) {
+    const int x = p % f.dims[0];
+    const int y = (p / f.dims[0]) % f.dims[1];
+    const int z = p / (f.dims[0] * f.dims[1]);
+    const double rx = ox + (f.lo[0] + x) * h, ry = oy + (f.lo[1] + y) * h,
+                 rz = oz + (f.lo[2] + z) * h;
+    double v = 0;
+    for (long long a = a0; a < a1; ++a) {
+      const int at = idx[a];
+      const double dx = rx - xyz[3 * at], dy = ry - xyz[3 * at + 1],
+                   dz = rz - xyz[3 * at + 2];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < rc2) v -= Z[at] * exp(-r2 * inv2s2);
+    }
+    out[f.v_off + p] = v;
+    out32[f.v_off + p] = (float)v;
+  }
+}
+
+void fragment_wells(hipStream_t s, const ofm_frags* f, const double* xyz,
+                    const double* Z, const long long* ptr, const int* idx,
+                    double sigma, double r_cut) {
+  int maxp = 0;
+  for (auto& d : f->host) maxp = std::max(maxp, d.npts);
+  dim3 grid((maxp + WG - 1) / WG, f->n_frag);
+  hipLaunchKernelGGL(k_wells, grid, dim3(WG), 0, s, f->d_frag, f->n_frag, xyz,
+                     Z, ptr, idx, f->grid.origin[0], f->grid.origin[1],
+                     f->grid.origin[2], f->grid.h, 1.0 / (2.0 * sigma * sigma),
+                     r_cut * r_cut, f->d_vf, f->d_vf32);
+  OFM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // seeded start vectors: splitmix64 of (seed, fragment, vector, point)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
@@ -322,11 +369,11 @@ void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
              const int* active, int step, const FilterState* fs, int mode,
              long long base_override, double alg_bytes, double flops,
              hipEvent_t ev0, hipEvent_t ev1) {
-  const T* Vj;
+  const T* Vj;   // potential of the fragment Hamiltonians
   if constexpr (sizeof(T) == 8)
-    Vj = (const T*)f->d_v;
+    Vj = (const T*)f->d_vf;
   else
-    Vj = (const T*)f->d_v32;
+    Vj = (const T*)f->d_vf32;
   const double nh = -0.5 / (f->grid.h * f->grid.h);
   const int nblk = pad8(ntiles);
   Timed tm(c, "stencil", alg_bytes, flops);

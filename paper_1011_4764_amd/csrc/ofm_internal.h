@@ -114,8 +114,11 @@ struct ofm_frags {
   int small_total = 0;
   int max_bw = 0, max_plane = 0, max_states = 0;
   ofm::FragDev* d_frag = nullptr;
-  double* d_v = nullptr;       // V restricted to boxes (FP64)
+  double* d_v = nullptr;       // V restricted to boxes (FP64): whole H
   float* d_v32 = nullptr;      // same, FP32 (mixed form)
+  double* d_vf = nullptr;      // potential of the fragment Hamiltonians
+  float* d_vf32 = nullptr;     // (aliases d_v / d_v32 unless own wells set)
+  bool own_wells = false;
   void* d_x = nullptr;         // block vectors (T)
   void* d_p = nullptr;         // filter work vectors (T)
   void* d_hx = nullptr;        // H times block vectors (T)
@@ -228,6 +231,9 @@ void destroy_blas(ofm_ctx* c);
 namespace k {
 void restrict_potential(hipStream_t s, const double* V, const ofm_grid& g,
                         const ofm_frags* f);
+void fragment_wells(hipStream_t s, const ofm_frags* f, const double* xyz,
+                    const double* Z, const long long* ptr, const int* idx,
+                    double sigma, double r_cut);
 template <typename T>
 void init_random(hipStream_t s, const ofm_frags* f, T* X,
                  unsigned long long seed);

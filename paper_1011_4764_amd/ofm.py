@@ -32,7 +32,7 @@ EXPORTS = [
     "ofm_matrix_elements", "ofm_mats_info", "ofm_mats_copy",
     "ofm_mats_destroy", "ofm_solve_global", "ofm_set_profiling",
     "ofm_kernel_stats", "ofm_reset_stats", "ofm_stage_times",
-    "ofm_set_stencil_variant",
+    "ofm_set_stencil_variant", "ofm_set_fragment_wells",
 ]
 
 
@@ -106,6 +106,8 @@ def lib():
             "ofm_reset_stats": ([_P], C.c_int),
             "ofm_stage_times": ([_P, _D, _D, _D], C.c_int),
             "ofm_set_stencil_variant": ([_P, C.c_int], C.c_int),
+            "ofm_set_fragment_wells": ([_P, C.c_int, _D, _D, C.c_double,
+                                        C.c_double, _LL, _I], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -318,6 +320,17 @@ def ofm_get_hphi(frags: Fragments, j):
     out = np.zeros((s, dd[0] * dd[1] * dd[2]))
     _check(lib().ofm_get_hphi(frags.handle, j, _dp(out)), frags.ctx.handle)
     return out
+
+
+def ofm_set_fragment_wells(frags: Fragments, atom_xyz, Z, frag_atom_ptr,
+                           frag_atom_idx, sigma=0.8, r_cut=8.0):
+    ax = np.ascontiguousarray(atom_xyz, np.float64).reshape(-1, 3)
+    z = np.ascontiguousarray(Z, np.float64)
+    ap = np.ascontiguousarray(frag_atom_ptr, np.int64)
+    ai = np.ascontiguousarray(frag_atom_idx, np.int32)
+    _check(lib().ofm_set_fragment_wells(
+        frags.handle, ax.shape[0], _dp(ax), _dp(z), float(sigma), float(r_cut),
+        ap.ctypes.data_as(_LL), ai.ctypes.data_as(_I)), frags.ctx.handle)
 
 
 def ofm_set_stencil_variant(frags: Fragments, variant: int):

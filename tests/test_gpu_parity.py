@@ -346,3 +346,78 @@ def test_distance_cutoff_end_to_end(ctx, tiny0, d_cut):
     g = P.ofm_solve_global(ctx, m, 1e-6, -1e30,
                            O.window_below_cutoff(r.eps)[1])
     assert np.abs(g["E"] - r.solve["window"]).max() < 1e-8
+
+
+def test_own_atoms_end_to_end(ctx, tiny0):
+    """Fragment Hamiltonians built from each fragment's own wells: the
+    fragment eigenpairs, the blocks (whole-system V in H|phi>) and the
+    window eigenvalues match the oracle run with the same own-atoms
+    fragments."""
+    s = tiny0
+    V = s.potential()
+    own = (s.grid.origin, s.Z, 0.8, 8.0)
+    r = O.run(V, 0.5, s.frag_lo, s.frag_dims, s.frag_states, atoms=s.atoms,
+              frag_atom_ptr=s.frag_atom_ptr, frag_atom_idx=s.frag_atom_idx,
+              own=own)
+    f = P.ofm_build_fragments(ctx, (24, 12, 12), 0.5, V, s.frag_lo,
+                              s.frag_dims, s.frag_states, origin=s.grid.origin)
+    P.ofm_set_fragment_wells(f, s.atoms, s.Z, s.frag_atom_ptr,
+                             s.frag_atom_idx, sigma=0.8, r_cut=8.0)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0 and cv.all()
+    err = np.abs(eps - np.concatenate(r.eps)).max()
+    _say("own-atoms eps err", err)
+    assert err < 1e-8
+    m = P.ofm_matrix_elements(ctx, f)
+    g = P.ofm_solve_global(ctx, m, 1e-6, -1e30,
+                           O.window_below_cutoff(r.eps)[1])
+    assert np.abs(g["E"] - r.solve["window"]).max() < 1e-8
+    m.close()
+    # with the oracle's states imported (gauge-free), H|phi> still uses the
+    # whole-system V: blocks match the oracle's to 1e-10
+    for j in range(s.n_frag):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    pj, pn, off = f.pairs()
+    m = P.ofm_matrix_elements(ctx, f)
+    H, S = P.ofm_mats_copy(m)
+    Hr, Sr = _oracle_blocks(r, pj, pn)
+    assert np.abs(H - Hr).max() < 1e-10 * np.abs(Hr).max()
+    assert np.abs(S - Sr).max() < 1e-10
+    m.close()
+    f.close()
+
+
+def test_own_atoms_whole_grid_is_global_v(ctx, tiny0):
+    """One fragment spanning the grid that owns every atom sees exactly the
+    global V: its eigenpairs equal those of the global-V fragment."""
+    s = tiny0
+    V = s.potential()
+    lo = np.zeros((1, 3), np.int64)
+    dims = np.array([[24, 12, 12]])
+    nst = np.array([8])
+    out = []
+    for own in (False, True):
+        f = P.ofm_build_fragments(ctx, (24, 12, 12), 0.5, V, lo, dims, nst,
+                                  origin=s.grid.origin)
+        if own:
+            P.ofm_set_fragment_wells(f, s.atoms, s.Z, [0, len(s.Z)],
+                                     np.arange(len(s.Z)))
+        st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+        assert st == 0
+        out.append(eps)
+        f.close()
+    assert np.abs(out[0] - out[1]).max() < 1e-10
+
+
+def test_own_atoms_invalid(ctx, tiny0):
+    s = tiny0
+    f = P.ofm_build_fragments(ctx, (24, 12, 12), 0.5, s.potential(),
+                              s.frag_lo, s.frag_dims, s.frag_states)
+    bad = np.array(s.frag_atom_idx, copy=True)
+    bad[0] = len(s.Z)
+    with pytest.raises(P.OfmError, match="OFM_E_INVALID"):
+        P.ofm_set_fragment_wells(f, s.atoms, s.Z, s.frag_atom_ptr, bad)
+    with pytest.raises(P.OfmError, match="OFM_E_INVALID"):
+        P.ofm_set_fragment_wells(f, s.atoms, s.Z, s.frag_atom_ptr,
+                                 s.frag_atom_idx, sigma=0.0)
+    f.close()

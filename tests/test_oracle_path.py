@@ -282,3 +282,36 @@ def test_distance_cutoff_pairs(tiny0):
     assert np.array_equal(r.H, H0)
     assert np.array_equal(r.S, ref.S)      # the (0, 2) overlap is zero anyway
     assert np.abs(r.solve["E"] - ref.solve["E"]).max() > 1e-3
+
+
+def test_own_atoms_fragments(tiny0):
+    """Fragment Hamiltonians built from each fragment's own wells: a fragment
+    that owns every atom and spans the whole grid sees exactly the global V;
+    the OFM pencil built on own-atoms states is still a Galerkin projection
+    of the whole-grid H (variational bound), and its H blocks still use the
+    global V (brute force)."""
+    s = tiny0
+    V = s.potential()
+    allm = np.arange(len(s.Z))
+    Vw = O.own_wells(0.5, s.grid.origin, (0, 0, 0), (24, 12, 12), s.atoms,
+                     s.Z, allm)
+    assert np.abs(Vw - V).max() < 1e-15
+    own = (s.grid.origin, s.Z, 0.8, 8.0)
+    kw = dict(atoms=s.atoms, frag_atom_ptr=s.frag_atom_ptr,
+              frag_atom_idx=s.frag_atom_idx, own=own)
+    r = O.run(V, 0.5, s.frag_lo, s.frag_dims, s.frag_states, **kw)
+    full = O.full_grid_eigs(V, 0.5, len(r.solve["E"]))
+    assert np.all(r.solve["E"] - full >= -1e-12)
+    ref = O.run(V, 0.5, s.frag_lo, s.frag_dims, s.frag_states)
+    assert np.abs(np.concatenate(r.eps) - np.concatenate(ref.eps)).max() > 1e-3
+    # blocks: B^T H_whole B with the own-atoms states
+    Hg = O.hamiltonian_box(V, 0.5, (0, 0, 0), (24, 12, 12))
+    B = []
+    for j in range(3):
+        z = np.zeros((12, 12, 24, 6))
+        lo, d = s.frag_lo[j], s.frag_dims[j]
+        z[:, :, lo[0]:lo[0] + d[0]] = r.phi[j].reshape(d[2], d[1], d[0], 6)
+        B.append(z.reshape(-1, 6))
+    B = np.hstack(B)
+    Hb = B.T @ (Hg @ B)
+    assert np.abs(r.H - 0.5 * (Hb + Hb.T)).max() < 1e-12
