@@ -65,16 +65,25 @@ def measured_traffic(config, precision):
     """HBM traffic per stencil launch from the committed rocprofv3 counter
     summary of this workload, if the kernel source has not changed since the
     counters were taken (else None)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"stencil_{config}_{precision}.md")
-    src = os.path.join(ROOT, "paper_1011_4764_amd", "csrc", "kernels.hip")
     try:
         line = [l for l in open(path) if l.startswith("traffic: ")][-1]
         rec = json.loads(line[len("traffic: "):])
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+        sha = stencil_source_sha1()
     except (OSError, IndexError, ValueError):
         return None
-    return rec["bytes_per_launch"] if rec.get("kernels_hip_sha1") == sha else None
+    return rec["bytes_per_launch"] if rec.get("stencil_src_sha1") == sha else None
+
+
+def stencil_source_sha1():
+    """SHA-1 over the stencil kernel's sources (stencil.hip, kdev.h)."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in ("stencil.hip", "kdev.h"):
+        with open(os.path.join(ROOT, "paper_1011_4764_amd", "csrc", name),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def cpu_baseline(system, n_sample, seed):

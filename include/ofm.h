@@ -100,6 +100,11 @@ typedef struct {
                             filter sweep, once per (precision, largest box
                             plane) and context, and keep the fastest [on];
                             -1: use the fixed default variant              */
+  int resident;          /* >= 0: in the mixed form, boxes of at most 32
+                            points per axis run the whole filter in one
+                            launch with the vector held on chip (same bits
+                            as the per-step launches) [on]; -1: per-step
+                            launches for every box                         */
 } ofm_solve_opts;
 
 typedef struct ofm_ctx ofm_ctx;

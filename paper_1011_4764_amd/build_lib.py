@@ -10,8 +10,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["csrc/kernels.hip", "csrc/api.cpp", "csrc/planner.cpp",
-       "csrc/global_solve.cpp"]
+SRC = ["csrc/stencil.hip", "csrc/kernels.hip", "csrc/api.cpp",
+       "csrc/planner.cpp", "csrc/global_solve.cpp"]
 LIB = os.path.join(HERE, "libofm.so")
 
 # Packed FP32 instructions are disabled for all device code (some of their
@@ -24,16 +24,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
-    for src in SRC:
+    objs, procs = [], []
+    for src in SRC:   # one hipcc per source, run side by side
         obj = os.path.join(HERE, "csrc", os.path.basename(src) + ".o")
         cmd = [hipcc, *FLAGS, "-c", "-x", "hip", os.path.join(HERE, src),
                "-I", os.path.join(ROOT, "include"),
                "-I", os.path.join(HERE, "csrc"), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((src, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
            "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas",

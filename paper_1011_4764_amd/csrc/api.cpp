@@ -163,6 +163,8 @@ void free_frags(ofm_frags* f) {
   }
   void* ptrs[] = {f->d_frag, f->d_v, f->d_v32, f->d_x, f->d_p, f->d_hx,
                   f->d_hphi, f->d_tiles[0], f->d_tiles[1], f->d_tiles[2],
+                  f->d_ftiles, f->d_tiles_nr[0], f->d_tiles_nr[1],
+                  f->d_tiles_nr[2],
                   f->d_stiles, f->d_rtiles, f->d_G,
                   f->d_Q, f->d_theta, f->d_res, f->d_res_partial, f->d_fs,
                   f->d_active, f->d_iters, f->d_conv, f->d_flags,
@@ -179,6 +181,7 @@ struct SolveCfg {
   unsigned long long seed;
   bool autotune;
   bool use_graph;
+  bool resident;
 };
 
 template <typename T>
@@ -285,14 +288,33 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   cholqr();
   apply_plain();
   rayleigh_ritz();
+  // mixed form: boxes of at most 32^3 run the whole filter on chip
+  const bool res = sizeof(T) == 4 && cfg.resident && f->n_ftiles > 0;
+  int2* const* sweep_tiles = res ? f->d_tiles_nr : f->d_tiles;
+  const int* sweep_n = res ? f->n_tiles_nr : f->n_tiles;
+  if (res && sweep_n[var] == 0) tuning = false;   // nothing left to tune
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
-    // filter work: unlocked vectors of the active fragments
-    double nb = 0, npt = 0;
+    // filter work: unlocked vectors of the active fragments (strip launches
+    // and on-chip filter separately)
+    double nb = 0, npt = 0, rnb = 0, rnpt = 0;
     for (int j = 0; j < nf; ++j)
       if (act[j] && fsh[j].lock < f->host[j].bw) {
-        nb += (double)f->host[j].npts * (f->host[j].bw - fsh[j].lock);
-        npt += f->host[j].npts;
+        const double u = (double)f->host[j].npts * (f->host[j].bw - fsh[j].lock);
+        if (res && k::resident_eligible((int)w, f->host[j])) {
+          rnb += u;
+          rnpt += f->host[j].npts;
+        } else {
+          nb += u;
+          npt += f->host[j].npts;
+        }
       }
+    if (res && rnb > 0) {
+      // HBM: y_0 and V read, y_d written, once per filter
+      if constexpr (sizeof(T) == 4)
+        k::filter_resident(c, f, X, f->d_ftiles, f->n_ftiles, f->d_active,
+                           f->d_fs, cfg.degree, 3 * rnb * w,
+                           32.0 * rnb * cfg.degree);
+    }
     auto sweep = [&](bool timed_each) {
       for (int step = 1; step <= cfg.degree; ++step) {
         const bool odd = step & 1;
@@ -308,11 +330,13 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
           e1 = tev[step - 2][1];
         }
         k::apply_h<T>(timed_each ? c : nullptr, f, in, prev, out,
-                      f->d_tiles[sv], f->n_tiles[sv], sv, f->d_active, step,
+                      sweep_tiles[sv], sweep_n[sv], sv, f->d_active, step,
                       f->d_fs, 1, -1, by, 32.0 * nb, e0, e1);
       }
     };
-    if (tuning || !cfg.use_graph) {
+    if (sweep_n[var] == 0) {
+      // every box took the on-chip filter
+    } else if (tuning || !cfg.use_graph) {
       sweep(true);
     } else {
       // the sweep is static (tiles, buffers and step coefficients fixed;
@@ -501,6 +525,26 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
         OFM_HIP(hipMemcpyAsync(f->d_tiles[v], tv.data(), sizeof(int2) * tv.size(),
                                hipMemcpyHostToDevice, s));
         OFM_HIP(hipStreamSynchronize(s));
+        auto tn = k::stencil_tiles(f, (int)w, v, 0, -1, true);
+        f->n_tiles_nr[v] = (int)tn.size();
+        f->d_tiles_nr[v] = dev_alloc<int2>(tn.size());
+        if (!tn.empty())
+          OFM_HIP(hipMemcpyAsync(f->d_tiles_nr[v], tn.data(),
+                                 sizeof(int2) * tn.size(),
+                                 hipMemcpyHostToDevice, s));
+        OFM_HIP(hipStreamSynchronize(s));
+      }
+      {
+        std::vector<int2> ft;
+        for (int j = 0; j < n_frag; ++j)
+          if (k::resident_eligible((int)w, f->host[j]))
+            for (int v = 0; v < f->host[j].bw; ++v) ft.push_back(make_int2(j, v));
+        f->n_ftiles = (int)ft.size();
+        f->d_ftiles = dev_alloc<int2>(ft.size());
+        if (!ft.empty())
+          OFM_HIP(hipMemcpyAsync(f->d_ftiles, ft.data(), sizeof(int2) * ft.size(),
+                                 hipMemcpyHostToDevice, s));
+        OFM_HIP(hipStreamSynchronize(s));
       }
       f->d_stiles = dev_alloc<int2>(stiles.size());
       f->d_rtiles = dev_alloc<int2>(rtiles.size());
@@ -635,6 +679,7 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.seed = opts ? opts->seed : 0;
     cfg.autotune = !opts || opts->autotune >= 0;
     cfg.use_graph = !opts || opts->use_graph >= 0;
+    cfg.resident = !opts || opts->resident >= 0;
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,
                 "guard vectors are fixed when the fragments are built");

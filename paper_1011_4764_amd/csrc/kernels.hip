@@ -1,10 +1,6 @@
-// HIP kernels of the OFM hot path for gfx950 (MI355X, CDNA4).
+// HIP kernels of the OFM hot path for gfx950 (MI355X, CDNA4); the fragment
+// Hamiltonian stencil k_apply_h lives in stencil.hip.
 //
-//  * k_apply_h      fragment Hamiltonian H_j = -1/2 Lap + V_j on a box, one
-//                   workgroup per (fragment, vector): the xy plane is staged in
-//                   LDS, z neighbours ride in a 5-deep register queue while the
-//                   workgroup marches along z (every input value read from HBM
-//                   once).  Also runs the scaled three-term Chebyshev step.
 //  * k_gram         G = A^T B per fragment over its box points, FP64 MFMA
 //                   (16x16x4) with split-K partials summed in fixed order.
 //  * k_cholinv      Cholesky of a Gram matrix and the inverse of its factor
@@ -20,26 +16,11 @@
 #include <cmath>
 #include <vector>
 
+#include "kdev.h"
 #include "ofm_internal.h"
 
 namespace ofm {
 namespace k {
-
-constexpr int WG = 256;
-
-// 4th-order central second-difference weights (times 1/h^2)
-constexpr double W0 = -2.5, W1 = 4.0 / 3.0, W2 = -1.0 / 12.0;
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-// Workgroup i is dispatched to XCD i % 8; remap so that each XCD receives a
-// contiguous range of logical tiles (tiles of one fragment share V_j and
-// their neighbours' planes in that XCD's L2).
-__device__ __forceinline__ int xcd_tile(int bid, int nblk_pad) {
-  const int per = nblk_pad >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
-static int pad8(int n) { return (n + 7) / 8 * 8; }
 
 // ---------------------------------------------------------------------------
 // potential restricted to every box
@@ -164,244 +145,6 @@ template void init_random<double>(hipStream_t, const ofm_frags*, double*,
 template void init_random<float>(hipStream_t, const ofm_frags*, float*,
                                  unsigned long long);
 
-// ---------------------------------------------------------------------------
-// fragment Hamiltonian / Chebyshev step
-// ---------------------------------------------------------------------------
-// mode 0: out = H_j in
-// mode 1: step k of the scaled Chebyshev filter on [lower, upper] normalised
-//         at `scale`:  Y_1 = (s1/e)(H - c) Y_0,
-//         Y_k = (2 s_k/e)(H - c) Y_{k-1} - s_{k-1} s_k Y_{k-2},
-//         e = (upper-lower)/2, c = (upper+lower)/2, s1 = e/(scale-c),
-//         s_k = 1/(2/s1 - s_{k-1}).
-// `prev` and `out` may alias (each point of `out` depends on `prev` at the
-// same point only); `in` must not alias either.
-// One workgroup handles a strip of SP = 256 PPT consecutive points of the
-// xy plane of one (fragment, vector) and marches along z.  Its LDS window is
-// the strip plus two rows on each side (the y neighbours); when the whole
-// plane fits in one strip there is no halo at all.  The +-1, +-2 z
-// neighbours of the strip's own points ride in a 5-deep register queue; V
-// and the previous Chebyshev vector are prefetched one plane ahead.  All
-// strips of a vector compute the same arithmetic per point, so every PPT
-// variant gives bit-identical results.
-constexpr int HALO_NX_MAX = 128;   // boxes may span at most 128 points in x
-
-template <typename T, int PPT>
-__global__ __launch_bounds__(WG) void k_apply_h(
-    const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
-    int nblk_pad, const T* __restrict__ Vj, const T* __restrict__ in,
-    const T* prev, T* out, const FilterState* __restrict__ fs,
-    const int* __restrict__ active, int step, int mode, double nh,
-    long long base_override) {
-  constexpr int SP = PPT * WG;
-  constexpr int LW = SP + 4 * HALO_NX_MAX;
-  const int t = xcd_tile(blockIdx.x, nblk_pad);
-  if (t >= ntiles) return;
-  const int j = tiles[t].x;
-  const int v = tiles[t].y >> 16, strip = tiles[t].y & 0xffff;
-  if (active && !active[j]) return;
-  // converged leading Ritz vectors are locked: the filter leaves them as they
-  // are (they stay in the orthogonalisation and the Rayleigh-Ritz step)
-  if (mode == 1 && v < fs[j].lock) return;
-  const FragDev& fr = F[j];
-  const int nx = fr.dims[0], ny = fr.dims[1], nz = fr.dims[2];
-  const int plane = nx * ny;
-  const int p0 = strip * SP;
-  const int p1 = min(p0 + SP, plane);
-  const int h0 = max(p0 - 2 * nx, 0), h1 = min(p1 + 2 * nx, plane);
-  const int nlo = p0 - h0, nhi = h1 - p1;
-  const long long base =
-      (base_override >= 0 ? base_override : fr.x_off) + (long long)v * fr.ld;
-  const T* __restrict__ src = in + base;
-  const T* pv = prev + base;
-  T* dst = out + base;
-  const T* __restrict__ vv = Vj + fr.v_off;
-
-  T alpha = 1, gamma = 0, beta = 0;
-  if (mode == 1) {
-    const FilterState st = fs[j];
-    const double e = 0.5 * (st.upper - st.lower);
-    if (!(e > 1e-12 * fabs(st.upper))) {
-      alpha = 0; gamma = 1; beta = 0;   // degenerate interval: identity
-    } else {
-      const double c = 0.5 * (st.upper + st.lower);
-      const double s1 = e / (st.scale - c);
-      double sp = s1, sc = s1;
-      const double tau = 2.0 / s1;
-      for (int k = 2; k <= step; ++k) {
-        sp = sc;
-        sc = 1.0 / (tau - sp);
-      }
-      const double a = (step == 1 ? sc : 2.0 * sc) / e;
-      alpha = (T)a;
-      gamma = (T)(-c * a);
-      beta = (T)(step == 1 ? 0.0 : -sp * sc);
-    }
-  }
-  const bool use_prev = (mode == 1 && step > 1);
-
-  __shared__ T lds[2][LW];
-  const int tid = threadIdx.x;
-  int px[PPT], py[PPT], pp[PPT];
-  bool ok[PPT];
-  T q0[PPT], q1[PPT], q2[PPT], q3[PPT], q4[PPT], vn[PPT], pn[PPT];
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int p = p0 + tid + k * WG;
-    ok[k] = p < p1;
-    pp[k] = ok[k] ? p : p0;
-    px[k] = pp[k] % nx;
-    py[k] = pp[k] / nx;
-    q0[k] = 0;
-    q1[k] = 0;
-    q2[k] = ok[k] ? src[pp[k]] : T(0);
-    q3[k] = (ok[k] && nz > 1) ? src[plane + pp[k]] : T(0);
-    q4[k] = (ok[k] && nz > 2) ? src[2 * plane + pp[k]] : T(0);
-    vn[k] = ok[k] ? vv[pp[k]] : T(0);
-    pn[k] = (ok[k] && use_prev) ? pv[pp[k]] : T(0);
-  }
-  // halo slots (2 rows on each side of the strip): nlo + nhi <= 4 nx <= 2 WG
-  int hq[2];
-  bool hok[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int hidx = tid + u * WG;
-    if (hidx < nlo) {
-      hq[u] = h0 + hidx;
-      hok[u] = true;
-    } else if (hidx - nlo < nhi) {
-      hq[u] = p1 + (hidx - nlo);
-      hok[u] = true;
-    } else {
-      hq[u] = h0;
-      hok[u] = false;
-    }
-  }
-  const T tw0 = (T)W0, tw1 = (T)W1, tw2 = (T)W2, tnh = (T)nh;
-  for (int z = 0; z < nz; ++z) {
-    const int zoff = z * plane;
-    T nxt[PPT], vnx[PPT], pnx[PPT], hv[2];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      nxt[k] = (ok[k] && z + 3 < nz) ? src[zoff + 3 * plane + pp[k]] : T(0);
-      vnx[k] = (ok[k] && z + 1 < nz) ? vv[zoff + plane + pp[k]] : T(0);
-      pnx[k] = (ok[k] && use_prev && z + 1 < nz)
-                   ? __builtin_nontemporal_load(&pv[zoff + plane + pp[k]])
-                   : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) hv[u] = hok[u] ? src[zoff + hq[u]] : T(0);
-    T* L = lds[z & 1];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k)
-      if (ok[k]) L[pp[k] - h0] = q2[k];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (hok[u]) L[hq[u] - h0] = hv[u];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      if (!ok[k]) continue;
-      const int li = pp[k] - h0, x = px[k], y = py[k];
-      const T c = q2[k];
-      const T xm1 = x >= 1 ? L[li - 1] : T(0);
-      const T xm2 = x >= 2 ? L[li - 2] : T(0);
-      const T xp1 = x + 1 < nx ? L[li + 1] : T(0);
-      const T xp2 = x + 2 < nx ? L[li + 2] : T(0);
-      const T ym1 = y >= 1 ? L[li - nx] : T(0);
-      const T ym2 = y >= 2 ? L[li - 2 * nx] : T(0);
-      const T yp1 = y + 1 < ny ? L[li + nx] : T(0);
-      const T yp2 = y + 2 < ny ? L[li + 2 * nx] : T(0);
-      // walls at every box face: odd image of the second ghost
-      const int nfaces = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) +
-                         (z == 0) + (z == nz - 1);
-      const T lap = tw0 * T(3) * c +
-                    tw1 * ((xm1 + xp1) + (ym1 + yp1) + (q1[k] + q3[k])) +
-                    tw2 * ((xm2 + xp2) + (ym2 + yp2) + (q0[k] + q4[k])) -
-                    tw2 * T(nfaces) * c;
-      const T hval = tnh * lap + vn[k] * c;
-      T o;
-      if (mode == 0)
-        o = hval;
-      else
-        o = alpha * hval + gamma * c + beta * pn[k];
-      __builtin_nontemporal_store(o, &dst[zoff + pp[k]]);
-    }
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      q0[k] = q1[k];
-      q1[k] = q2[k];
-      q2[k] = q3[k];
-      q3[k] = q4[k];
-      q4[k] = nxt[k];
-      vn[k] = vnx[k];
-      pn[k] = pnx[k];
-    }
-  }
-}
-
-// PPT of stencil variant i for storage type T
-int stencil_ppt(int elem_bytes, int variant) {
-  static const int p64[NVARIANT] = {1, 2, 4};
-  static const int p32[NVARIANT] = {2, 4, 8};
-  return elem_bytes == 8 ? p64[variant] : p32[variant];
-}
-
-// tiles (fragment, vector << 16 | strip) of one stencil variant for the
-// vectors v < nvec(j) of every fragment (or of fragment `only` alone)
-std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
-                                int variant, int nvec_only, int only) {
-  const int sp = stencil_ppt(elem_bytes, variant) * WG;
-  std::vector<int2> t;
-  for (int j = 0; j < f->n_frag; ++j) {
-    if (only >= 0 && j != only) continue;
-    const FragDev& d = f->host[j];
-    const int ns = (d.dims[0] * d.dims[1] + sp - 1) / sp;
-    const int nv = nvec_only > 0 ? nvec_only : d.bw;
-    for (int v = 0; v < nv; ++v)
-      for (int s = 0; s < ns; ++s) t.push_back(make_int2(j, (v << 16) | s));
-  }
-  return t;
-}
-
-template <typename T>
-void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
-             T* out, const int2* tiles, int ntiles, int variant,
-             const int* active, int step, const FilterState* fs, int mode,
-             long long base_override, double alg_bytes, double flops,
-             hipEvent_t ev0, hipEvent_t ev1) {
-  const T* Vj;   // potential of the fragment Hamiltonians
-  if constexpr (sizeof(T) == 8)
-    Vj = (const T*)f->d_vf;
-  else
-    Vj = (const T*)f->d_vf32;
-  const double nh = -0.5 / (f->grid.h * f->grid.h);
-  const int nblk = pad8(ntiles);
-  Timed tm(c, "stencil", alg_bytes, flops);
-  hipStream_t stream = f->ctx->stream;
-  if (ev0) OFM_HIP(hipEventRecord(ev0, stream));
-  const int ppt = stencil_ppt(sizeof(T), variant);
-#define LAUNCH(P)                                                            \
-  hipLaunchKernelGGL((k_apply_h<T, P>), dim3(nblk), dim3(WG), 0, stream,     \
-                     f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,  \
-                     active, step, mode, nh, base_override)
-  if (ppt == 1) LAUNCH(1);
-  else if (ppt == 2) LAUNCH(2);
-  else if (ppt == 4) LAUNCH(4);
-  else LAUNCH(8);
-#undef LAUNCH
-  if (ev1) OFM_HIP(hipEventRecord(ev1, stream));
-  OFM_HIP(hipGetLastError());
-}
-template void apply_h<double>(ofm_ctx*, const ofm_frags*, const double*,
-                              const double*, double*, const int2*, int, int,
-                              const int*, int, const FilterState*, int,
-                              long long, double, double, hipEvent_t,
-                              hipEvent_t);
-template void apply_h<float>(ofm_ctx*, const ofm_frags*, const float*,
-                             const float*, float*, const int2*, int, int,
-                             const int*, int, const FilterState*, int,
-                             long long, double, double, hipEvent_t,
-                             hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // Gram products G = A^T B per fragment (FP64 MFMA 16x16x4)

@@ -127,6 +127,12 @@ struct ofm_frags {
   // (fragment, 256-point chunk)
   int2* d_tiles[3] = {nullptr, nullptr, nullptr};   // per stencil variant
   int n_tiles[3] = {0, 0, 0};
+  // FP32: (fragment, vector) tiles of the boxes the on-chip filter takes,
+  // and the strip tiles of the remaining boxes per variant
+  int2* d_ftiles = nullptr;
+  int n_ftiles = 0;
+  int2* d_tiles_nr[3] = {nullptr, nullptr, nullptr};
+  int n_tiles_nr[3] = {0, 0, 0};
   int variant = -1;            // stencil variant in use (-1: not chosen)
   int2* d_stiles = nullptr;
   int n_stiles = 0;
@@ -240,7 +246,14 @@ void init_random(hipStream_t s, const ofm_frags* f, T* X,
 constexpr int NVARIANT = 3;   // stencil variants (points per thread)
 int stencil_ppt(int elem_bytes, int variant);
 std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
-                                int variant, int nvec_only, int only);
+                                int variant, int nvec_only, int only,
+                                bool skip_resident = false);
+// whole Chebyshev filter with the vector on chip (FP32, boxes <= 32^3)
+bool resident_eligible(int elem_bytes, const FragDev& d);
+void filter_resident(ofm_ctx* c, const ofm_frags* f, float* X,
+                     const int2* tiles, int ntiles, const int* active,
+                     const FilterState* fs, int degree, double alg_bytes,
+                     double flops);
 template <typename T>
 void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
              T* out, const int2* tiles, int ntiles, int variant,

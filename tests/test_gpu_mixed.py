@@ -121,3 +121,50 @@ def test_mixed_end_to_end_tiny(mctx, seed):
     _say("  window", len(g["E"]), "max err", err)
     assert len(g["E"]) == len(r.solve["window"])
     assert err < 1e-5
+
+
+def _wells_system(seed):
+    """Uneven boxes: three of at most 32 points per axis (one with a full
+    32-point z column) take the on-chip filter, one 36 points wide in x
+    takes the per-step launches."""
+    rng = np.random.default_rng(seed)
+    shape = (48, 20, 34)
+    h = 0.5
+    zz, yy, xx = np.meshgrid(*[np.arange(n) * h for n in shape[::-1]],
+                             indexing="ij")
+    V = np.zeros(shape[::-1])
+    for _ in range(8):
+        c = rng.uniform(0, 1, 3) * np.array(shape) * h
+        V -= np.exp(-((xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2)
+                    / (2 * 0.8 ** 2))
+    lo = [(0, 0, 0), (10, 4, 4), (30, 2, 1), (40, 12, 20)]
+    dims = [(12, 12, 12), (36, 10, 10), (8, 8, 32), (5, 7, 3)]
+    return box_system(shape, h, lo, dims, [6, 4, 5, 2], V=V)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_resident_filter_bit_identical(mctx, seed):
+    """The on-chip whole-filter kernel gives the same bits as the per-step
+    strip launches: eigenvalues, iteration counts and states."""
+    s = _wells_system(seed)
+    out = []
+    for res, graph in ((0, 0), (-1, 0), (-1, -1)):
+        _say("resident", res, "graph", graph, "seed", seed)
+        f = _build(mctx, s)
+        st, eps, it, cv = P.ofm_solve_fragments(mctx, f, resident=res,
+                                                use_graph=graph)
+        assert st == 0 and cv.all()
+        phis = [P.ofm_get_states(f, j)[1] for j in range(s.n_frag)]
+        out.append((eps, it, phis))
+        f.close()
+    for eps, it, phis in out[1:]:
+        assert np.array_equal(eps, out[0][0])
+        assert np.array_equal(it, out[0][1])
+        for a, b in zip(phis, out[0][2]):
+            assert np.array_equal(a, b)
+    # and the eigenvalues agree with the oracle's to the mixed tolerance
+    r = O.run(s.potential(), s.grid.h, s.frag_lo, s.frag_dims, s.frag_states,
+              solve=False)
+    err = np.abs(out[0][0] - np.concatenate(r.eps)).max()
+    _say("  eps err vs oracle", err)
+    assert err < 1e-5
