@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6         # MI355X FP64 (vector and matrix), TFLOP/s
+# LDS: 128 B per clock per CU, 256 CUs, 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
+LDS_BYTES_PER_POINT_STEP = 11 * 4   # on-chip filter, FP32
 
 
 def log(*a):
@@ -61,11 +64,11 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(config, precision):
-    """HBM traffic per stencil launch from the committed rocprofv3 counter
-    summary of this workload, if the kernel source has not changed since the
+def measured_traffic(stem):
+    """HBM traffic per launch from the committed rocprofv3 counter summary
+    profiles/<stem>.md, if the stencil sources have not changed since the
     counters were taken (else None)."""
-    path = os.path.join(ROOT, "profiles", f"stencil_{config}_{precision}.md")
+    path = os.path.join(ROOT, "profiles", f"{stem}.md")
     try:
         line = [l for l in open(path) if l.startswith("traffic: ")][-1]
         rec = json.loads(line[len("traffic: "):])
@@ -198,6 +201,7 @@ def main():
         res["stencil"] = ctx.kernel_stats("stencil")
         res["elements"] = ctx.kernel_stats("elements")
         res["gram"] = ctx.kernel_stats("gram")
+        res["filter"] = ctx.kernel_stats("filter")
         ctx.close()
         return res
 
@@ -247,7 +251,7 @@ def main():
             "kernel": "k_apply_h (Chebyshev filter step of H_j)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.config, args.precision),
+            "traffic": measured_traffic(f"stencil_{args.config}_{args.precision}"),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + "
                             "WRITE_SIZE, copy-calibrated)",
             "launches": st["launches"], "avg_launch_ms": avg_ms,
@@ -282,6 +286,8 @@ def main():
             "global_ms": mx["global_ms"],
             "outer_iterations_max": int(mx["last"]["iters"].max()),
             "all_converged": bool(mx["last"]["conv"].all()),
+            "window_Ha": [float(x) for x in Em[:nw]],
+            "basis_kept": int(mx["last"]["n_kept"]),
             "window_max_abs_dE_vs_fp64_Ha": dE,
             "within_1e-5_Ha": bool(dE <= 1e-5),
             "fragment_stage_speedup_vs_fp64_own_tol": solve_ms / mx["solve_ms"],
@@ -298,6 +304,23 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": a_ms,
                 "launches": ms_["launches"]}
+        mf = mx["filter"]
+        if mf["launches"]:
+            # on-chip filter: per point and step 9 LDS reads and 2 LDS
+            # accesses of the column swap (4 B each); 32 flops per point-step
+            a_ms = mf["ms"] / mf["launches"]
+            psteps = mf["flops"] / 32.0 / mf["launches"]
+            lds = psteps * LDS_BYTES_PER_POINT_STEP / (a_ms * 1e-3) / 1e9
+            out["mixed"]["filter_roofline"] = {
+                "kernel": "k_filter_resident (whole Chebyshev filter, vector "
+                          "in LDS)",
+                "bound": "lds", "achieved": lds, "peak": LDS_PEAK_GBS,
+                "unit": "GB/s", "frac": lds / LDS_PEAK_GBS,
+                "avg_launch_ms": a_ms, "launches": mf["launches"],
+                "point_steps_per_s": psteps / (a_ms * 1e-3),
+                "hbm_alg_bytes_per_launch": mf["bytes"] / mf["launches"],
+                "hbm_traffic": measured_traffic(f"filter_{args.config}_mixed"),
+                "hbm_GBps": mf["bytes"] / mf["launches"] / (a_ms * 1e-3) / 1e9}
         me = mx["elements"]
         if me["ms"]:
             out["mixed"]["elements_TFLOPs_useful"] = me["flops"] / me["ms"] / 1e9

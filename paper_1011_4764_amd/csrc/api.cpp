@@ -309,10 +309,11 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         }
       }
     if (res && rnb > 0) {
-      // HBM: y_0 and V read, y_d written, once per filter
+      // HBM: y_0 read and y_d written per vector, V_j once per fragment
+      // (its 24 vector workgroups share it through L2), once per filter
       if constexpr (sizeof(T) == 4)
         k::filter_resident(c, f, X, f->d_ftiles, f->n_ftiles, f->d_active,
-                           f->d_fs, cfg.degree, 3 * rnb * w,
+                           f->d_fs, cfg.degree, (2 * rnb + rnpt) * w,
                            32.0 * rnb * cfg.degree);
     }
     auto sweep = [&](bool timed_each) {

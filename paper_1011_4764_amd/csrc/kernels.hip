@@ -169,18 +169,21 @@ __device__ __forceinline__ void load4(const T* p, double* o) {
   }
 }
 
-// symmetric (upper tiles only) when A == B
-template <typename T>
+// One workgroup per (fragment, contraction chunk).  Every wave computes all
+// 16x16 tiles of the block (NT x NT tiles, the upper ones only when A == B)
+// over its own interleaved share of the chunk, so each row segment is
+// loaded once; the four waves' tiles are then summed in LDS in wave order.
+template <typename T, int NT, bool SYM>
 __global__ __launch_bounds__(WG) void k_gram(
     const FragDev* __restrict__ F, int nf, const T* __restrict__ A,
     const T* __restrict__ B, double* __restrict__ partial,
-    const int* __restrict__ active, int symmetric) {
+    const int* __restrict__ active) {
+  constexpr int NTILE = SYM ? NT * (NT + 1) / 2 : NT * NT;
   const int j = blockIdx.x / GCH, ch = blockIdx.x % GCH;
   if (j >= nf) return;
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
   const int bw = fr.bw;
-  const int nt = (bw + 15) / 16;
   int cs = (fr.ld + GCH - 1) / GCH;
   cs = (cs + 31) / 32 * 32;
   const int kb = ch * cs;
@@ -188,41 +191,91 @@ __global__ __launch_bounds__(WG) void k_gram(
   double* out = partial + (long long)fr.small_off * GCH + (long long)ch * bw * bw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  int tile = 0;
-  for (int ti = 0; ti < nt; ++ti) {
-    for (int tj = symmetric ? ti : 0; tj < nt; ++tj, ++tile) {
-      if ((tile & 3) != wave) continue;
-      const int ra = ti * 16 + r, rb = tj * 16 + r;
-      const bool va = ra < bw, vb = rb < bw;
-      const T* pa = A + fr.x_off + (long long)(va ? ra : 0) * fr.ld;
-      const T* pb = B + fr.x_off + (long long)(vb ? rb : 0) * fr.ld;
-      d4 acc = {0, 0, 0, 0};
-      // kb and ke are multiples of 16, so every lane runs the same trip
-      // count (an MFMA reads all lanes' operands)
-      for (int k = kb + 4 * g; k < ke; k += 16) {
-        double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
-        if (va) load4(pa + k, a);
-        if (vb) load4(pb + k, b);
-        acc = mfma_f64(a[0], b[0], acc);
-        acc = mfma_f64(a[1], b[1], acc);
-        acc = mfma_f64(a[2], b[2], acc);
-        acc = mfma_f64(a[3], b[3], acc);
+  const T* pa[NT];
+  const T* pb[NT];
+  bool va[NT], vb[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int row = t * 16 + r;
+    va[t] = row < bw;
+    pa[t] = A + fr.x_off + (long long)(va[t] ? row : 0) * fr.ld;
+    vb[t] = va[t];
+    pb[t] = B + fr.x_off + (long long)(vb[t] ? row : 0) * fr.ld;
+  }
+  d4 acc[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) acc[t] = d4{0, 0, 0, 0};
+  // kb and ke are multiples of 16: every lane of a wave runs the same trip
+  // count (an MFMA reads all lanes' operands)
+  for (int k = kb + 16 * wave + 4 * g; k < ke; k += 64) {
+    double a[NT][4], b[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      a[t][0] = a[t][1] = a[t][2] = a[t][3] = 0;
+      if (va[t]) load4(pa[t] + k, a[t]);
+      if constexpr (!SYM) {
+        b[t][0] = b[t][1] = b[t][2] = b[t][3] = 0;
+        if (vb[t]) load4(pb[t] + k, b[t]);
       }
+    }
+    int tile = 0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int tj = SYM ? ti : 0; tj < NT; ++tj, ++tile)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[tile] = mfma_f64(a[ti][u], SYM ? a[tj][u] : b[tj][u], acc[tile]);
+  }
+  // sum the waves' tiles in wave order
+  __shared__ double red[NTILE * 4 * 64];
+  for (int w = 1; w < WG / 64; ++w) {
+    if (wave == w)
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[(t * 4 + i) * 64 + lane] = acc[t][i];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[t][i] += red[(t * 4 + i) * 64 + lane];
+    __syncthreads();
+  }
+  if (wave != 0) return;
+  int tile = 0;
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int tj = SYM ? ti : 0; tj < NT; ++tj, ++tile)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = ti * 16 + g + 4 * i, col = tj * 16 + r;
-        if (row < bw && col < bw) out[row * bw + col] = acc[i];
+        if (row < bw && col < bw) out[row * bw + col] = acc[tile][i];
       }
-    }
-  }
 }
 
 template <typename T>
 void gram(ofm_ctx* c, const ofm_frags* f, const T* A, const T* B, double* G,
           const int* active, double bytes, double flops) {
   Timed tm(c, "gram", bytes, flops);
-  hipLaunchKernelGGL(k_gram<T>, dim3(f->n_frag * GCH), dim3(WG), 0, c->stream,
-                     f->d_frag, f->n_frag, A, B, G, active, A == B ? 1 : 0);
+  const int nt = (f->max_bw + 15) / 16;
+  const bool sym = A == B;
+#define GRAM(NT)                                                             \
+  if (sym)                                                                   \
+    hipLaunchKernelGGL((k_gram<T, NT, true>), dim3(f->n_frag * GCH),         \
+                       dim3(WG), 0, c->stream, f->d_frag, f->n_frag, A, B,   \
+                       G, active);                                           \
+  else                                                                       \
+    hipLaunchKernelGGL((k_gram<T, NT, false>), dim3(f->n_frag * GCH),        \
+                       dim3(WG), 0, c->stream, f->d_frag, f->n_frag, A, B,   \
+                       G, active)
+  if (nt <= 1) GRAM(1);
+  else if (nt == 2) GRAM(2);
+  else if (nt == 3) GRAM(3);
+  else GRAM(4);
+#undef GRAM
   OFM_HIP(hipGetLastError());
 }
 template void gram<double>(ofm_ctx*, const ofm_frags*, const double*,
@@ -323,7 +376,7 @@ __device__ void load_sym(const FragDev& fr, const double* __restrict__ partial,
                          double* M, int ldm, int symmetric) {
   const int bw = fr.bw;
   const double* base = partial + (long long)fr.small_off * GCH;
-  for (int e = threadIdx.x; e < bw * bw; e += WG) {
+  for (int e = threadIdx.x; e < bw * bw; e += blockDim.x) {
     const int i = e / bw, jj = e % bw;
     if (symmetric && jj < i) continue;
     double s = 0;
@@ -333,7 +386,7 @@ __device__ void load_sym(const FragDev& fr, const double* __restrict__ partial,
   }
   __syncthreads();
   if (!symmetric) {   // symmetrise (A + A^T)/2
-    for (int e = threadIdx.x; e < bw * bw; e += WG) {
+    for (int e = threadIdx.x; e < bw * bw; e += blockDim.x) {
       const int i = e / bw, jj = e % bw;
       if (jj <= i) continue;
       const double m = 0.5 * (M[i * ldm + jj] + M[jj * ldm + i]);
@@ -436,7 +489,8 @@ void cholinv(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
 // of X^T X (the second CholQR pass, not applied to X): the projected matrix
 // becomes R^-T (X^T H X) R^-1 and the rotation returned is R^-1 Y, so the
 // second orthonormalisation and the Rayleigh-Ritz rotation cost one pass.
-__global__ __launch_bounds__(WG) void k_rr_eig(
+constexpr int RRW = WG;   // threads per fragment
+__global__ __launch_bounds__(RRW) void k_rr_eig(
     const FragDev* __restrict__ F, int nf, const double* __restrict__ partial,
     double* __restrict__ Q, double* __restrict__ theta,
     const int* __restrict__ active, int pre) {
@@ -450,30 +504,30 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
   __shared__ double Pm[SMAX * SLD];
   __shared__ double cs[SMAX / 2], sn[SMAX / 2];
   __shared__ int pp[SMAX / 2], qq[SMAX / 2];
-  __shared__ double red[WG / 64];
+  __shared__ double red[RRW / 64];
   __shared__ double offn, totn;
   load_sym(fr, partial, A, SLD, 0);
   if (pre) {
     const double* Qj0 = Q + fr.small_off;
-    for (int e = threadIdx.x; e < n * n; e += WG)
+    for (int e = threadIdx.x; e < n * n; e += RRW)
       Pm[(e / n) * SLD + e % n] = Qj0[e];
     __syncthreads();
     // U = A P, then A = P^T U (symmetrised)
-    for (int e = threadIdx.x; e < n * n; e += WG) {
+    for (int e = threadIdx.x; e < n * n; e += RRW) {
       const int r = e / n, c = e % n;
       double acc = 0;
       for (int k = 0; k < n; ++k) acc += A[r * SLD + k] * Pm[k * SLD + c];
       U[r * SLD + c] = acc;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += WG) {
+    for (int e = threadIdx.x; e < n * n; e += RRW) {
       const int r = e / n, c = e % n;
       double acc = 0;
       for (int k = 0; k < n; ++k) acc += Pm[k * SLD + r] * U[k * SLD + c];
       A[r * SLD + c] = acc;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += WG) {
+    for (int e = threadIdx.x; e < n * n; e += RRW) {
       const int r = e / n, c = e % n;
       if (c > r) {
         const double m = 0.5 * (A[r * SLD + c] + A[c * SLD + r]);
@@ -483,7 +537,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < n * n; e += WG)
+  for (int e = threadIdx.x; e < n * n; e += RRW)
     U[(e / n) * SLD + e % n] = (e / n == e % n) ? 1.0 : 0.0;
   const int n2 = n + (n & 1);       // round-robin over an even count
   const int npair = n2 / 2;
@@ -491,7 +545,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
   for (int sweep = 0; sweep < 40; ++sweep) {
     // off-diagonal and total Frobenius norms
     double so = 0, st = 0;
-    for (int e = threadIdx.x; e < n * n; e += WG) {
+    for (int e = threadIdx.x; e < n * n; e += RRW) {
       const double a = A[(e / n) * SLD + e % n];
       st += a * a;
       if (e / n != e % n) so += a * a;
@@ -504,7 +558,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0;
-      for (int w = 0; w < WG / 64; ++w) t += red[w];
+      for (int w = 0; w < RRW / 64; ++w) t += red[w];
       offn = t;
     }
     __syncthreads();
@@ -512,7 +566,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0;
-      for (int w = 0; w < WG / 64; ++w) t += red[w];
+      for (int w = 0; w < RRW / 64; ++w) t += red[w];
       totn = t;
     }
     __syncthreads();
@@ -539,7 +593,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int e = threadIdx.x; e < npair * n; e += WG) {
+      for (int e = threadIdx.x; e < npair * n; e += RRW) {
         const int i = e / n, m = e % n;
         const int p = pp[i], q = qq[i];
         if (q >= n || sn[i] == 0.0) continue;
@@ -550,7 +604,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
       }
       __syncthreads();
       // columns: A <- A J, U <- U J
-      for (int e = threadIdx.x; e < npair * n; e += WG) {
+      for (int e = threadIdx.x; e < npair * n; e += RRW) {
         const int i = e / n, m = e % n;
         const int p = pp[i], q = qq[i];
         if (q >= n || sn[i] == 0.0) continue;
@@ -567,7 +621,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
   }
   // ascending order (stable by index), Q[k][rank] = U[k][i]
   double* Qj = Q + fr.small_off;
-  for (int i = threadIdx.x; i < n; i += WG) {
+  for (int i = threadIdx.x; i < n; i += RRW) {
     const double d = A[i * SLD + i];
     int rank = 0;
     for (int m = 0; m < n; ++m) {
@@ -589,7 +643,7 @@ __global__ __launch_bounds__(WG) void k_rr_eig(
 
 void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
             double* theta, const int* active, int pre) {
-  hipLaunchKernelGGL(k_rr_eig, dim3(f->n_frag), dim3(WG), 0, s, f->d_frag,
+  hipLaunchKernelGGL(k_rr_eig, dim3(f->n_frag), dim3(RRW), 0, s, f->d_frag,
                      f->n_frag, G, Q, theta, active, pre);
   OFM_HIP(hipGetLastError());
 }
@@ -597,24 +651,54 @@ void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
 // ---------------------------------------------------------------------------
 // rotation X <- X Q (and HX <- HX Q with residual partial sums)
 // ---------------------------------------------------------------------------
+// Sum of v over a wave: butterflies inside each 16-lane row (DPP quad
+// permutations and row rotations), then the four row sums.  Every lane of
+// the wave must be active.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1,
+                                                  0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e,
+                                                  0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124,
+                                                  0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128,
+                                                  0xf, 0xf, true));
+  const int b = __float_as_int(v);
+  return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) +
+          __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(b, 32)) +
+          __int_as_float(__builtin_amdgcn_readlane(b, 48)));
+}
+
+// One thread per point of a 256-point chunk.  Q sits in LDS transposed and
+// zero-padded to BMAX x BMAX (column i of Q is a contiguous row), so a
+// thread reads four coefficients per LDS load; the products accumulate in
+// the storage type over k in ascending order.  With `upper` (a triangular
+// CholQR factor) only k <= i contributes.  The squared residuals
+// |HX'_i - theta_i X'_i|^2 of the stored values are summed per wave in FP32
+// (a convergence test needs only a few digits) and per chunk in FP64.
 template <typename T, int BMAX>
 __global__ __launch_bounds__(RCH) void k_rotate(
     const FragDev* __restrict__ F, const int2* __restrict__ rt, int nrt,
     T* __restrict__ X, T* __restrict__ HX, const double* __restrict__ Q,
     const double* __restrict__ theta, double* __restrict__ res_partial,
     const int* __restrict__ active, int upper) {
+  static_assert(BMAX % 4 == 0, "BMAX must be a multiple of 4");
   const int t = blockIdx.x;
   if (t >= nrt) return;
   const int j = rt[t].x;
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
   const int bw = fr.bw;
-  // products accumulate in the storage type (FP32 in the mixed form)
-  __shared__ T q[SMAX * SMAX];
-  __shared__ double th[SMAX];
-  __shared__ double red[RCH / 64][SMAX];
+  __shared__ __align__(16) T qt[BMAX * BMAX];
+  __shared__ double th[BMAX];
+  __shared__ float red[RCH / 64][BMAX];
   const double* Qj = Q + fr.small_off;
-  for (int e = threadIdx.x; e < bw * bw; e += RCH) q[e] = (T)Qj[e];
+  for (int e = threadIdx.x; e < BMAX * BMAX; e += RCH) {
+    const int i = e / BMAX, k = e % BMAX;
+    qt[e] = (i < bw && k < bw && (!upper || k <= i)) ? (T)Qj[k * bw + i]
+                                                    : T(0);
+  }
   if (HX)
     for (int i = threadIdx.x; i < bw; i += RCH) th[i] = theta[fr.th_off + i];
   __syncthreads();
@@ -636,21 +720,32 @@ __global__ __launch_bounds__(RCH) void k_rotate(
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = 0; i < bw; ++i) {
     T a = 0, h = 0;
+    const T* qi = qt + i * BMAX;
 #pragma unroll
-    for (int k = 0; k < BMAX; ++k) {
+    for (int k = 0; k < BMAX; k += 4) {
       if (k < bw && (!upper || k <= i)) {
-        const T qk = q[k * bw + i];
-        a += x[k] * qk;
-        if (HX) h += hx[k] * qk;
+        T q4[4];
+        if constexpr (sizeof(T) == 4) {
+          typedef float f4 __attribute__((ext_vector_type(4)));
+          const f4 v = *reinterpret_cast<const f4*>(qi + k);
+          q4[0] = v[0]; q4[1] = v[1]; q4[2] = v[2]; q4[3] = v[3];
+        } else {
+          const d4 v = *reinterpret_cast<const d4*>(qi + k);
+          q4[0] = v[0]; q4[1] = v[1]; q4[2] = v[2]; q4[3] = v[3];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a = fma(x[k + u], q4[u], a);
+          if (HX) h = fma(hx[k + u], q4[u], h);
+        }
       }
     }
-    if (ok) xp[(long long)i * fr.ld] = (T)a;
+    if (ok) xp[(long long)i * fr.ld] = a;
     if (HX) {
-      if (ok) hp[(long long)i * fr.ld] = (T)h;
-      double r = ok ? (double)((T)h) - th[i] * (double)((T)a) : 0.0;
-      r *= r;
-      for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
-      if (lane == 0) red[wave][i] = r;
+      if (ok) hp[(long long)i * fr.ld] = h;
+      const double r = ok ? (double)h - th[i] * (double)a : 0.0;
+      const float ws = wave_sum((float)(r * r));
+      if (lane == 0) red[wave][i] = ws;
     }
   }
   if (HX) {

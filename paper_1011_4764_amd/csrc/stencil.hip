@@ -33,45 +33,68 @@ namespace k {
 // variant gives bit-identical results.
 constexpr int HALO_NX_MAX = 128;   // boxes may span at most 128 points in x
 
-// Coefficients (alpha, gamma, beta) of Chebyshev step `step`:
-// out = alpha H y_{k-1} + gamma y_{k-1} + beta y_{k-2}.  A degenerate
+// Per-step coefficients of out = a1 s1 + a2 s2 + (alpha u + gamma) c
+// + beta pn, where c is the point's value, s1 / s2 the sums of its +-1 /
+// +-2 neighbours along the three axes, u = nh (3 W0 - W2 nfaces) + V its
+// diagonal (nh = -1/(2 h^2); each box face the point touches adds the odd
+// image of the second ghost) and pn the point's value two steps back.
+// mode 0 (out = H_j y): a1 = nh W1, a2 = nh W2, alpha = 1, gamma = beta = 0.
+// mode 1, Chebyshev step k: out = alpha H y_{k-1} + gamma y_{k-1}
+// + beta y_{k-2}, so a1 = alpha nh W1 and a2 = alpha nh W2.  A degenerate
 // interval gives the identity.
 template <typename T>
-__device__ __forceinline__ void cheb_coefs(const FilterState& st, int step,
-                                           T& alpha, T& gamma, T& beta) {
+struct StepCoef {
+  T a1, a2, alpha, gamma, beta;
+};
+
+template <typename T>
+__device__ __forceinline__ StepCoef<T> step_coefs(const FilterState* fs,
+                                                  int step, int mode,
+                                                  double nh) {
+  StepCoef<T> k;
+  if (mode == 0) {
+    k.a1 = (T)(nh * W1); k.a2 = (T)(nh * W2);
+    k.alpha = 1; k.gamma = 0; k.beta = 0;
+    return k;
+  }
+  const FilterState& st = *fs;
   const double e = 0.5 * (st.upper - st.lower);
   if (!(e > 1e-12 * fabs(st.upper))) {
-    alpha = 0; gamma = 1; beta = 0;
-    return;
+    k.a1 = 0; k.a2 = 0; k.alpha = 0; k.gamma = 1; k.beta = 0;
+    return k;
   }
   const double c = 0.5 * (st.upper + st.lower);
   const double s1 = e / (st.scale - c);
   double sp = s1, sc = s1;
   const double tau = 2.0 / s1;
-  for (int k = 2; k <= step; ++k) {
+  for (int i = 2; i <= step; ++i) {
     sp = sc;
     sc = 1.0 / (tau - sp);
   }
   const double a = (step == 1 ? sc : 2.0 * sc) / e;
-  alpha = (T)a;
-  gamma = (T)(-c * a);
-  beta = (T)(step == 1 ? 0.0 : -sp * sc);
+  k.a1 = (T)(a * nh * W1);
+  k.a2 = (T)(a * nh * W2);
+  k.alpha = (T)a;
+  k.gamma = (T)(-c * a);
+  k.beta = (T)(step == 1 ? 0.0 : -sp * sc);
+  return k;
 }
 
-// One output point: H_j y at a point whose value is c, from its +-1 and +-2
-// neighbours along each axis (0 beyond the box faces) and the number of box
-// faces it touches (each adds the odd image of the second ghost), then the
-// Chebyshev update (mode 1) or H_j y itself (mode 0).  Every stencil kernel
-// evaluates points through this function with explicit fused multiply-adds,
-// so they all produce the same bits.
+// diagonal of H_j at a point touching `nfaces` box faces with potential v
 template <typename T>
-__device__ __forceinline__ T stencil_point(T c, T s1, T s2, int nfaces, T v,
-                                           T pn, T nh, T alpha, T gamma,
-                                           T beta, int mode) {
+__device__ __forceinline__ T point_diag(T nh, int nfaces, T v) {
   const T dg = fma(-(T)W2, T(nfaces), (T)W0 * T(3));
-  const T lap = fma((T)W1, s1, fma((T)W2, s2, dg * c));
-  const T hval = fma(nh, lap, v * c);
-  return mode == 0 ? hval : fma(alpha, hval, fma(gamma, c, beta * pn));
+  return fma(nh, dg, v);
+}
+
+// One output point.  Every stencil kernel evaluates points through this
+// function with explicit fused multiply-adds, so they all produce the same
+// bits.
+template <typename T>
+__device__ __forceinline__ T stencil_point(T c, T s1, T s2, T u, T pn,
+                                           const StepCoef<T>& k) {
+  const T d = fma(k.alpha, u, k.gamma);
+  return fma(k.a1, s1, fma(k.a2, s2, fma(d, c, k.beta * pn)));
 }
 
 template <typename T, int PPT>
@@ -105,8 +128,7 @@ __global__ __launch_bounds__(WG) void k_apply_h(
   T* dst = out + base;
   const T* __restrict__ vv = Vj + fr.v_off;
 
-  T alpha = 1, gamma = 0, beta = 0;
-  if (mode == 1) cheb_coefs<T>(fs[j], step, alpha, gamma, beta);
+  const StepCoef<T> kc = step_coefs<T>(fs + j, step, mode, nh);
   const bool use_prev = (mode == 1 && step > 1);
 
   __shared__ T lds[2][LW];
@@ -186,8 +208,8 @@ __global__ __launch_bounds__(WG) void k_apply_h(
                          (z == 0) + (z == nz - 1);
       const T s1 = (xm1 + xp1) + (ym1 + yp1) + (q1[k] + q3[k]);
       const T s2 = (xm2 + xp2) + (ym2 + yp2) + (q0[k] + q4[k]);
-      const T o = stencil_point<T>(c, s1, s2, nfaces, vn[k], pn[k], tnh,
-                                   alpha, gamma, beta, mode);
+      const T o = stencil_point<T>(c, s1, s2, point_diag<T>(tnh, nfaces, vn[k]),
+                                   pn[k], kc);
       __builtin_nontemporal_store(o, &dst[zoff + pp[k]]);
     }
 #pragma unroll
@@ -208,81 +230,82 @@ __global__ __launch_bounds__(WG) void k_apply_h(
 // most 32 x 32 x 32 points)
 // ---------------------------------------------------------------------------
 // One workgroup of 1024 threads per (fragment, vector) runs every filter
-// step: y_{k-1} of the whole box (128 KB) sits in LDS, thread (x, y) owns
-// the z column at that plane point and keeps y_{k-2} and V_j of its column
-// in registers.  After each step's barrier a thread swaps
-// its own column: LDS takes y_k, the registers take y_{k-1}.  HBM is touched
-// once per filter (read y_0 and V, write y_d) instead of once per step.
-// Points are evaluated by stencil_point in the same order as the strip
-// kernel, so the filtered vectors are bit-identical to `degree` strip
-// launches.
+// step.  y_{k-1} of the whole box sits in LDS in a zero-padded layout (two
+// zero columns between rows, two zero rows between planes, zero planes
+// beyond the box), so every +-1, +-2 neighbour beyond a box face reads 0
+// without a test.  Thread (x, y) owns the z column at that plane point and
+// keeps y_{k-2} and the point diagonals u of its column in registers.  After
+// each step's barrier a thread swaps its own column: LDS takes y_k, the
+// registers take y_{k-1}.  HBM is touched once per filter (read y_0 and V,
+// write y_d) instead of once per step.  Points are evaluated by
+// stencil_point exactly as in the strip kernel, so the filtered vectors are
+// bit-identical to `degree` strip launches.
 constexpr int RN = 32;
-constexpr int RP = RN * RN;        // LDS plane pitch
-constexpr int RPAD = 2 * RN + 2;   // LDS pad below and above the box: every
-                                   // neighbour address stays in the array
-#ifndef OFM_RZG
-#define OFM_RZG 1
-#endif
-constexpr int RZG = OFM_RZG;       // planes per scheduling group
+constexpr int RX = RN + 2;          // LDS row pitch
+constexpr int RPL = RX * (RN + 2);  // LDS plane pitch
+constexpr int RLDS = RN * RPL + 2 * RX;
 
-__device__ __forceinline__ void resident_step(
-    float (&old)[RN], float* L, int li0, bool own, int nz, int nfxy,
-    bool xm1ok, bool xm2ok, bool xp1ok, bool xp2ok, bool ym1ok, bool ym2ok,
-    bool yp1ok, bool yp2ok, const float (&vr)[RN], float nh, float alpha,
-    float gamma, float beta) {
-  // Neighbour values are loaded unconditionally (all addresses lie inside
-  // the padded array) and selected to 0 beyond the box faces; lanes outside
-  // the box and planes z >= nz compute values nobody reads (the planes
-  // beyond the box are only ever selected away), so the whole step is one
-  // straight-line block.
-  // 5-deep window of the own column of y_{k-1}, streamed from LDS
+// LDS index of box point (x, y, z)
+__device__ __forceinline__ int rl(int x, int y, int z) {
+  return z * RPL + (y + 2) * RX + (x + 2);
+}
+
+// one filter step over the own column; FULLZ: the box spans all RN planes
+template <bool FULLZ>
+__device__ __forceinline__ void resident_step(float (&old)[RN],
+                                              const float (&u)[RN], float* L,
+                                              int a0, bool own, int nz,
+                                              const StepCoef<float>& kc) {
+  // 5-deep window of the own column of y_{k-1}, streamed from LDS (planes
+  // beyond the box are zero)
   float q0 = 0.f, q1 = 0.f;
-  const float r3 = L[li0 + RP], r4 = L[li0 + 2 * RP];
-  float q2 = L[li0];
-  float q3 = nz > 1 ? r3 : 0.f;
-  float q4 = nz > 2 ? r4 : 0.f;
+  float q2 = L[a0], q3 = L[a0 + RPL], q4 = L[a0 + 2 * RPL];
 #pragma unroll
   for (int z = 0; z < RN; ++z) {
-    {
-      const int li = li0 + z * RP;
-      float nxt = 0.f;
-      if (z + 3 < RN) {
-        const float r = L[li0 + (z + 3 < RN ? z + 3 : 0) * RP];
-        nxt = z + 3 < nz ? r : 0.f;
-      }
-      const float rxm1 = L[li - 1], rxm2 = L[li - 2];
-      const float rxp1 = L[li + 1], rxp2 = L[li + 2];
-      const float rym1 = L[li - RN], rym2 = L[li - 2 * RN];
-      const float ryp1 = L[li + RN], ryp2 = L[li + 2 * RN];
-      const float xm1 = xm1ok ? rxm1 : 0.f, xm2 = xm2ok ? rxm2 : 0.f;
-      const float xp1 = xp1ok ? rxp1 : 0.f, xp2 = xp2ok ? rxp2 : 0.f;
-      const float ym1 = ym1ok ? rym1 : 0.f, ym2 = ym2ok ? rym2 : 0.f;
-      const float yp1 = yp1ok ? ryp1 : 0.f, yp2 = yp2ok ? ryp2 : 0.f;
-      const int nfaces = nfxy + (z == 0) + (z == nz - 1);
-      const float s1 = (xm1 + xp1) + (ym1 + yp1) + (q1 + q3);
-      const float s2 = (xm2 + xp2) + (ym2 + yp2) + (q0 + q4);
-      old[z] = stencil_point<float>(q2, s1, s2, nfaces, vr[z], old[z], nh,
-                                    alpha, gamma, beta, 1);
+    if (FULLZ || z < nz) {
+      const int a = a0 + z * RPL;
+      const float nxt = z + 3 < RN ? L[a0 + (z + 3 < RN ? z + 3 : 0) * RPL]
+                                   : 0.f;
+      const float s1 = (L[a - 1] + L[a + 1]) + (L[a - RX] + L[a + RX]) +
+                       (q1 + q3);
+      const float s2 = (L[a - 2] + L[a + 2]) +
+                       (L[a - 2 * RX] + L[a + 2 * RX]) + (q0 + q4);
+      old[z] = stencil_point<float>(q2, s1, s2, u[z], old[z], kc);
       q0 = q1;
       q1 = q2;
       q2 = q3;
       q3 = q4;
       q4 = nxt;
     }
-    // keep the scheduler from hoisting loads of later planes (registers)
-    if ((z & (RZG - 1)) == RZG - 1) __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();   // every read of y_{k-1} in LDS is done
+  if (own) {
 #pragma unroll
-  for (int z = 0; z < RN; ++z) {
-      const float prev = L[li0 + z * RP];
-      L[li0 + z * RP] = old[z];
-      old[z] = prev;
-    }
+    for (int z = 0; z < RN; ++z)
+      if (FULLZ || z < nz) {
+        const float prev = L[a0 + z * RPL];
+        L[a0 + z * RPL] = old[z];
+        old[z] = prev;
+      }
+  }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(RP) void k_filter_resident(
+template <bool FULLZ>
+__device__ __forceinline__ void resident_filter(float* L, float (&old)[RN],
+                                                const float (&u)[RN], int a0,
+                                                bool own, int nz,
+                                                const FilterState* fs,
+                                                int degree, double nh) {
+  for (int step = 1; step <= degree; ++step) {
+    const StepCoef<float> kc = step_coefs<float>(fs, step, 1, nh);
+    int nzs = nz;
+    asm volatile("" : "+s"(nzs));   // keep per-plane tests inside the step
+    resident_step<FULLZ>(old, u, L, a0, own, nzs, kc);
+  }
+}
+
+__global__ __launch_bounds__(RN * RN) void k_filter_resident(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
     int nblk_pad, const float* __restrict__ Vj, float* X,
     const FilterState* __restrict__ fs, const int* __restrict__ active,
@@ -291,8 +314,7 @@ __global__ __launch_bounds__(RP) void k_filter_resident(
   if (t >= ntiles) return;
   const int j = tiles[t].x, v = tiles[t].y;
   if (active && !active[j]) return;
-  const FilterState st = fs[j];
-  if (v < st.lock) return;   // locked Ritz vectors are left as they are
+  if (v < fs[j].lock) return;   // locked Ritz vectors are left as they are
   const FragDev& fr = F[j];
   const int nx = fr.dims[0], ny = fr.dims[1], nz = fr.dims[2];
   const int plane = nx * ny;
@@ -302,37 +324,32 @@ __global__ __launch_bounds__(RP) void k_filter_resident(
   const int p = own ? x + nx * y : 0;
   float* col = X + fr.x_off + (long long)v * fr.ld + p;
   const float* vc = Vj + fr.v_off + p;
-  __shared__ float Lbuf[RPAD + RN * RP + RPAD];
-  float* L = Lbuf + RPAD;
-  const int li0 = y * RN + x;
-  float old[RN], vr[RN];   // y_{k-2} (zero before the first step), V_j
+  __shared__ float L[RLDS];
+  for (int i = tid; i < RLDS; i += RN * RN) L[i] = 0.f;
+  __syncthreads();
+  const int a0 = rl(x, y, 0);
+  const int nfxy = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1);
+  const float tnh = (float)nh;
+  float old[RN], u[RN];   // y_{k-2} (zero before the first step), diagonals
 #pragma unroll
   for (int z = 0; z < RN; ++z) {
     old[z] = 0.f;
-    vr[z] = (own && z < nz) ? vc[z * plane] : 0.f;
-    if (own && z < nz) L[li0 + z * RP] = col[z * plane];
+    u[z] = 0.f;
+    if (own && z < nz) {
+      u[z] = point_diag<float>(tnh, nfxy + (z == 0) + (z == nz - 1),
+                               vc[z * plane]);
+      L[a0 + z * RPL] = col[z * plane];
+    }
   }
   __syncthreads();
-  const int nfxy = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1);
-  const bool xm1ok = x >= 1, xm2ok = x >= 2, xp1ok = x + 1 < nx,
-             xp2ok = x + 2 < nx;
-  const bool ym1ok = y >= 1, ym2ok = y >= 2, yp1ok = y + 1 < ny,
-             yp2ok = y + 2 < ny;
-  const float tnh = (float)nh;
-  for (int step = 1; step <= degree; ++step) {
-    float al, ga, be;
-    cheb_coefs<float>(st, step, al, ga, be);
-    // the per-plane tests on nz are recomputed inside each step rather than
-    // hoisted out of the step loop as 32 lane masks (register pressure)
-    int nzs = nz;
-    asm volatile("" : "+s"(nzs));
-    resident_step(old, L, li0, own, nzs, nfxy, xm1ok, xm2ok, xp1ok, xp2ok,
-                  ym1ok, ym2ok, yp1ok, yp2ok, vr, tnh, al, ga, be);
-  }
+  if (nz == RN)
+    resident_filter<true>(L, old, u, a0, own, nz, fs + j, degree, nh);
+  else
+    resident_filter<false>(L, old, u, a0, own, nz, fs + j, degree, nh);
 #pragma unroll
   for (int z = 0; z < RN; ++z)
     if (own && z < nz)
-      __builtin_nontemporal_store(L[li0 + z * RP], &col[z * plane]);
+      __builtin_nontemporal_store(L[a0 + z * RPL], &col[z * plane]);
 }
 
 bool resident_eligible(int elem_bytes, const FragDev& d) {
@@ -346,7 +363,7 @@ void filter_resident(ofm_ctx* c, const ofm_frags* f, float* X,
                      double flops) {
   const int nblk = pad8(ntiles);
   Timed tm(c, "filter", alg_bytes, flops);
-  hipLaunchKernelGGL(k_filter_resident, dim3(nblk), dim3(RP), 0,
+  hipLaunchKernelGGL(k_filter_resident, dim3(nblk), dim3(RN * RN), 0,
                      f->ctx->stream, f->d_frag, tiles, ntiles, nblk,
                      (const float*)f->d_vf32, X, fs, active, degree,
                      -0.5 / (f->grid.h * f->grid.h));
