@@ -51,7 +51,8 @@ __all__ = [
     "hamiltonian_box", "fragment_states", "canonical_sign", "dilated_box",
     "apply_whole_H", "pair_list", "pair_blocks", "assemble", "global_solve",
     "full_grid_eigs", "line_spectrum", "box_spectrum", "OracleResult",
-    "run", "window_below_cutoff", "own_wells",
+    "run", "window_below_cutoff", "own_wells", "select_top",
+    "select_by_gap", "subset", "homo_energies", "homo_lumo_gap",
 ]
 
 #: stencil reach (points) of the 4th-order central second difference
@@ -354,6 +355,68 @@ def global_solve(H, S, tau=1e-6, e_lo=-np.inf, e_hi=np.inf,
     return {"E": E, "window": E[sel], "n_kept": int(keep.sum()),
             "s_min_kept": float(s[keep].min()), "s": s,
             "C": None if C is None else C[:, sel]}
+
+
+# --------------------------------------------------------------------------
+# basis selection near the top of the occupied fragment states and the
+# HOMO-LUMO gap of the whole system (Sec. III-B)
+# --------------------------------------------------------------------------
+# The fragment states computed for fragment j, eps_j[0] <= ... <= eps_j[s-1],
+# play the role of its occupied states; the last one is its HOMO.
+
+def select_top(eps, n_top):
+    """Keep mask over the basis (fragment by fragment): the n_top highest
+    computed states of every fragment (all of them where s_j <= n_top)."""
+    keep = []
+    for e in eps:
+        s = len(e)
+        keep.append(np.arange(s) >= s - min(n_top, s))
+    return np.concatenate(keep)
+
+
+def select_by_gap(eps, gap_min, n_max):
+    """Keep mask: for each fragment, walk down from its HOMO and cut at the
+    first substantial gap, eps_j[k] - eps_j[k-1] >= gap_min, keeping the
+    states k..s-1; with no such gap among the top n_max states keep those
+    n_max (the paper's rule: cut where the fragment levels have a gap)."""
+    keep = []
+    for e in eps:
+        s = len(e)
+        n = min(n_max, s)
+        for k in range(s - 1, max(s - n_max, 0), -1):
+            if e[k] - e[k - 1] >= gap_min:
+                n = s - k
+                break
+        keep.append(np.arange(s) >= s - n)
+    return np.concatenate(keep)
+
+
+def subset(H, S, keep):
+    """The pencil restricted to the kept basis functions (principal
+    submatrices)."""
+    idx = np.flatnonzero(keep)
+    return H[np.ix_(idx, idx)], S[np.ix_(idx, idx)]
+
+
+def homo_energies(H, n_states):
+    """e_j = <HOMO_j|H|HOMO_j> with the whole-system H, from the diagonal of
+    each fragment's diagonal block (the HOMO is its last basis state)."""
+    off = np.concatenate([[0], np.cumsum(n_states)])
+    return np.array([H[off[j + 1] - 1, off[j + 1] - 1]
+                     for j in range(len(n_states))])
+
+
+def homo_lumo_gap(E, e_ref, gap_min):
+    """First gap in the spectrum E above e_ref: scanning upward from the
+    first eigenvalue at or above e_ref, the first spacing
+    E[k+1] - E[k] >= gap_min; the states up to k are occupied.  Returns
+    (n_occ, E_homo, E_lumo), or (-1, nan, nan) when there is no such gap."""
+    E = np.sort(np.asarray(E, dtype=float))
+    start = int(np.searchsorted(E, e_ref, side="left"))
+    for k in range(max(start, 0), len(E) - 1):
+        if E[k + 1] - E[k] >= gap_min:
+            return k + 1, float(E[k]), float(E[k + 1])
+    return -1, math.nan, math.nan
 
 
 # --------------------------------------------------------------------------

@@ -315,3 +315,66 @@ def test_own_atoms_fragments(tiny0):
     B = np.hstack(B)
     Hb = B.T @ (Hg @ B)
     assert np.abs(r.H - 0.5 * (Hb + Hb.T)).max() < 1e-12
+
+
+# ------------------------------------------- basis near the HOMO (Sec. III-B)
+
+def test_select_top_and_by_gap_worked_examples():
+    """Hand-worked masks: the top-n rule and the cut at the first
+    substantial gap below each fragment's HOMO."""
+    eps = [np.array([-3.0, -2.0, -1.0]), np.array([-5.0, -4.0])]
+    assert O.select_top(eps, 2).tolist() == [False, True, True, True, True]
+    assert O.select_top(eps, 1).tolist() == [False, False, True, False, True]
+    e = [np.array([-3.0, -2.9, -1.0, -0.95])]
+    # walking down: 0.05 (no gap), then 1.9 >= 0.5: keep the top two
+    assert O.select_by_gap(e, 0.5, 4).tolist() == [False, False, True, True]
+    # no gap within the top three: keep three
+    assert O.select_by_gap(e, 5.0, 3).tolist() == [False, True, True, True]
+    # the gap lies deeper than n_max allows: keep n_max
+    assert O.select_by_gap(e, 0.5, 1).tolist() == [False, False, False, True]
+
+
+def test_homo_lumo_gap_worked_examples():
+    E = [-5.0, -4.9, -4.8, -2.0, -1.9]
+    assert O.homo_lumo_gap(E, -4.95, 0.5) == (3, -4.8, -2.0)
+    # the scan starts at the first level at or above e_ref: above -1.95
+    # only -1.9 remains, so there is no gap
+    n, lo, hi = O.homo_lumo_gap(E, -1.95, 0.05)
+    assert n == -1 and np.isnan(lo) and np.isnan(hi)
+    assert O.homo_lumo_gap(E, -10.0, 0.05) == (1, -5.0, -4.9)
+
+
+def test_homo_energies_and_subset_pencil_brute_force(tiny0, tiny0_oracle):
+    """e_j equals the HOMO's expectation value with the whole-grid H (brute
+    force on the zero-extended state), and the pencil restricted to a
+    selected basis equals the projection of the whole-grid H and identity
+    onto those states."""
+    s, r = tiny0, tiny0_oracle
+    V = s.potential()
+    Hg = O.hamiltonian_box(V, 0.5, (0, 0, 0), (24, 12, 12))
+    cols = []
+    for j in range(3):
+        z = np.zeros((12, 12, 24, 6))
+        lo, d = s.frag_lo[j], s.frag_dims[j]
+        z[:, :, lo[0]:lo[0] + d[0]] = r.phi[j].reshape(d[2], d[1], d[0], 6)
+        cols.append(z.reshape(-1, 6))
+    B = np.hstack(cols)
+    e = O.homo_energies(r.H, s.frag_states)
+    for j in range(3):
+        b = cols[j][:, -1]
+        assert abs(e[j] - b @ (Hg @ b)) < 1e-12
+    keep = O.select_top(r.eps, 3)
+    Hs, Ss = O.subset(r.H, r.S, keep)
+    Bs = B[:, keep]
+    assert np.abs(Ss - Bs.T @ Bs).max() < 1e-12
+    Hb = Bs.T @ (Hg @ Bs)
+    assert np.abs(Hs - 0.5 * (Hb + Hb.T)).max() < 1e-12
+    # keeping everything gives the full pencil
+    Ha, Sa = O.subset(r.H, r.S, np.ones(len(keep), bool))
+    assert np.array_equal(Ha, r.H) and np.array_equal(Sa, r.S)
+    # the subset pencil solved directly (Cholesky) agrees with the
+    # thresholded solve when nothing is dropped
+    g = O.global_solve(Hs, Ss, 1e-6)
+    assert g["n_kept"] == int(keep.sum())
+    ref = sla.eigh(Hs, Ss, eigvals_only=True)
+    assert np.abs(g["E"] - ref).max() < 1e-10
