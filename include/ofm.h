@@ -250,6 +250,46 @@ ofm_status ofm_solve_global(ofm_ctx* ctx, const ofm_mats* m, double s_thresh,
                             double e_lo, double e_hi, int* n_kept, int* n_eig,
                             double* E, double* C, double* s_min);
 
+/* ---- basis near the fragment HOMOs and the HOMO-LUMO gap (Sec. III-B) --- */
+/* The computed states of a fragment play the role of its occupied states;
+   the highest one is its HOMO. */
+
+/* Keep mask over the basis (fragment by fragment in basis order, n_basis
+   bytes, host) from the fragment eigenvalues of the last
+   ofm_solve_fragments (or imported states).  For each fragment, walk down
+   from its HOMO and keep the states above the first gap
+   eps[k] - eps[k-1] >= gap_min found among its top n_max states; with no
+   such gap, or gap_min <= 0, keep its top n_max states (all of them where
+   s_j <= n_max).  Errors: OFM_E_INVALID for n_max < 1; OFM_E_STATE without
+   states. */
+ofm_status ofm_select_homo(const ofm_frags* f, int n_max, double gap_min,
+                           unsigned char* keep);
+
+/* ofm_solve_global on the pencil restricted to the basis functions with
+   keep[i] != 0 (n_basis bytes, host; NULL keeps every function).  Rows of C
+   follow the kept functions in basis order (n_sel rows, column stride
+   n_sel).  Errors as ofm_solve_global, and OFM_E_INVALID when nothing is
+   kept. */
+ofm_status ofm_solve_global_subset(ofm_ctx* ctx, const ofm_mats* m,
+                                   const unsigned char* keep,
+                                   double s_thresh, double e_lo, double e_hi,
+                                   int* n_kept, int* n_eig, double* E,
+                                   double* C, double* s_min);
+
+/* e_j = <HOMO_j|H|HOMO_j> with the whole-system H for every fragment, read
+   from the diagonal blocks of m (n_frag doubles, host). */
+ofm_status ofm_homo_energies(const ofm_mats* m, double* e);
+
+/* First gap above e_ref in the spectrum E[0..n) (ascending, host): scanning
+   upward from the first eigenvalue >= e_ref, the first spacing
+   E[k+1] - E[k] >= gap_min.  Writes n_occ = k + 1 (states up to the gap are
+   occupied), e_homo = E[k], e_lumo = E[k+1]; n_occ = -1 and NaN energies
+   when there is no such gap.  Errors: OFM_E_INVALID for n < 0, a NULL
+   output, non-finite e_ref or gap_min < 0, or E not ascending. */
+ofm_status ofm_homo_lumo_gap(const double* E, int n, double e_ref,
+                             double gap_min, int* n_occ, double* e_homo,
+                             double* e_lumo);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Turn per-launch HIP-event timing of the library's kernels on or off.  When

@@ -1018,6 +1018,84 @@ ofm_status ofm_solve_global(ofm_ctx* c, const ofm_mats* m, double s_thresh,
   });
 }
 
+ofm_status ofm_solve_global_subset(ofm_ctx* c, const ofm_mats* m,
+                                   const unsigned char* keep, double s_thresh,
+                                   double e_lo, double e_hi, int* n_kept,
+                                   int* n_eig, double* E, double* C,
+                                   double* s_min) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(m && m->ctx == c && n_eig && E, OFM_E_INVALID, "bad arguments");
+    OFM_REQUIRE(std::isfinite(s_thresh) && s_thresh >= 0, OFM_E_INVALID,
+                "s_thresh must be finite and >= 0");
+    use_device(c);
+    const double t0 = now_ms();
+    global_solve(c, m, s_thresh, e_lo, e_hi, n_kept, n_eig, E, C, s_min, keep);
+    c->t_global = now_ms() - t0;
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_select_homo(const ofm_frags* f, int n_max, double gap_min,
+                           unsigned char* keep) {
+  if (!f) return OFM_E_INVALID;
+  ofm_ctx* c = f->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(keep && n_max >= 1, OFM_E_INVALID,
+                "keep is required and n_max must be >= 1");
+    OFM_REQUIRE(std::isfinite(gap_min), OFM_E_INVALID, "gap_min must be finite");
+    OFM_REQUIRE(f->have_states && (long long)f->eps_host.size() == f->n_basis,
+                OFM_E_STATE, "no states yet");
+    for (int j = 0; j < f->n_frag; ++j) {
+      const FragDev& d = f->host[j];
+      const double* e = f->eps_host.data() + d.basis_off;
+      const int s = d.n_states;
+      int n = std::min(n_max, s);
+      if (gap_min > 0)
+        for (int k = s - 1; k > std::max(s - n_max, 0); --k)
+          if (e[k] - e[k - 1] >= gap_min) {
+            n = s - k;
+            break;
+          }
+      for (int i = 0; i < s; ++i) keep[d.basis_off + i] = i >= s - n ? 1 : 0;
+    }
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_homo_energies(const ofm_mats* m, double* e) {
+  if (!m) return OFM_E_INVALID;
+  ofm_ctx* c = m->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(e, OFM_E_INVALID, "e is required");
+    use_device(c);
+    homo_energies(m, e);
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_homo_lumo_gap(const double* E, int n, double e_ref,
+                             double gap_min, int* n_occ, double* e_homo,
+                             double* e_lumo) {
+  if (n < 0 || (n > 0 && !E) || !n_occ || !e_homo || !e_lumo ||
+      !std::isfinite(e_ref) || !(gap_min >= 0) || !std::isfinite(gap_min))
+    return OFM_E_INVALID;
+  for (int k = 0; k + 1 < n; ++k)
+    if (!(E[k + 1] >= E[k])) return OFM_E_INVALID;
+  *n_occ = -1;
+  *e_homo = *e_lumo = std::nan("");
+  int k = 0;
+  while (k < n && !(E[k] >= e_ref)) ++k;
+  for (; k + 1 < n; ++k)
+    if (E[k + 1] - E[k] >= gap_min) {
+      *n_occ = k + 1;
+      *e_homo = E[k];
+      *e_lumo = E[k + 1];
+      break;
+    }
+  return OFM_OK;
+}
+
 ofm_status ofm_set_profiling(ofm_ctx* c, int on) {
   if (!c) return OFM_E_INVALID;
   c->profiling = on != 0;

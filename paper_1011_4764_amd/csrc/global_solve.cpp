@@ -30,11 +30,14 @@ namespace {
                                     rocblas_status_to_string(s_)};          \
   } while (0)
 
-// scatter the packed upper blocks (and their transposes) into dense N x N
+// scatter the packed upper blocks (and their transposes) into dense N x N;
+// sel maps a basis function to its row in the (possibly restricted) pencil,
+// -1 for a function left out
 __global__ void k_assemble(const int* __restrict__ pj, const int* __restrict__ pn,
                            const long long* __restrict__ boff,
                            const int* __restrict__ st,
-                           const long long* __restrict__ bas, int npair,
+                           const long long* __restrict__ bas,
+                           const long long* __restrict__ sel, int npair,
                            const double* __restrict__ Hb,
                            const double* __restrict__ Sb, double* __restrict__ H,
                            double* __restrict__ S, long long N) {
@@ -45,13 +48,23 @@ __global__ void k_assemble(const int* __restrict__ pj, const int* __restrict__ p
   const long long r0 = bas[j], c0 = bas[n];
   for (int e = threadIdx.x; e < sj * sn; e += blockDim.x) {
     const int i = e / sn, m = e % sn;
+    const long long r = sel[r0 + i], c = sel[c0 + m];
+    if (r < 0 || c < 0) continue;
     const double h = Hb[boff[p] + e], s = Sb[boff[p] + e];
     // symmetric: column-major and row-major storage coincide
-    H[(r0 + i) * N + (c0 + m)] = h;
-    S[(r0 + i) * N + (c0 + m)] = s;
-    H[(c0 + m) * N + (r0 + i)] = h;
-    S[(c0 + m) * N + (r0 + i)] = s;
+    H[r * N + c] = h;
+    S[r * N + c] = s;
+    H[c * N + r] = h;
+    S[c * N + r] = s;
   }
+}
+
+// out[i] = v[idx[i]]
+__global__ void k_gather(const double* __restrict__ v,
+                         const long long* __restrict__ idx, int n,
+                         double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v[idx[i]];
 }
 
 // X[:, k] = U[:, first + k] / sqrt(s[first + k])   (column-major N x K)
@@ -97,11 +110,42 @@ void destroy_blas(ofm_ctx* c) {
   }
 }
 
+void homo_energies(const ofm_mats* m, double* e) {
+  ofm_ctx* c = m->ctx;
+  const int nf = (int)m->states.size();
+  // offset of the last diagonal element of every diagonal block
+  std::vector<long long> idx(nf, -1);
+  for (size_t p = 0; p < m->pair_j.size(); ++p)
+    if (m->pair_j[p] == m->pair_n[p]) {
+      const int j = m->pair_j[p];
+      const long long sj = m->states[j];
+      idx[j] = m->block_off[p] + (sj - 1) * sj + (sj - 1);
+    }
+  for (int j = 0; j < nf; ++j)
+    OFM_REQUIRE(idx[j] >= 0, OFM_E_STATE, "a fragment has no diagonal block");
+  hipStream_t st = c->stream;
+  DevBuf<long long> di(nf);
+  DevBuf<double> out(nf);
+  OFM_HIP(hipMemcpyAsync(di.p, idx.data(), sizeof(long long) * nf,
+                         hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_gather, dim3((nf + 255) / 256), dim3(256), 0, st,
+                     m->d_H, di.p, nf, out.p);
+  OFM_HIP(hipGetLastError());
+  OFM_HIP(hipMemcpyAsync(e, out.p, sizeof(double) * nf, hipMemcpyDeviceToHost,
+                         st));
+  OFM_HIP(hipStreamSynchronize(st));
+}
+
 void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
                   double e_hi, int* n_kept, int* n_eig, double* E, double* C,
-                  double* s_min) {
-  const long long N = m->n_basis;
-  OFM_REQUIRE(N >= 1 && N <= 200000, OFM_E_INVALID,
+                  double* s_min, const unsigned char* keep) {
+  // rows of the pencil: every basis function, or the kept ones in order
+  std::vector<long long> selh(m->n_basis);
+  long long N = 0;
+  for (long long i = 0; i < m->n_basis; ++i)
+    selh[i] = (!keep || keep[i]) ? N++ : -1;
+  OFM_REQUIRE(N >= 1, OFM_E_INVALID, "no basis function is kept");
+  OFM_REQUIRE(N <= 200000, OFM_E_INVALID,
               "basis size outside the dense solver's range");
   hipStream_t st = c->stream;
   rocblas_handle h = blas(c);
@@ -109,7 +153,9 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
   const int nf = (int)m->states.size();
   DevBuf<double> H(N * N), S(N * N), s(N), work(N);
   DevBuf<int> pj(np), pn(np), sts(nf), info(1);
-  DevBuf<long long> boff(np), bas(nf);
+  DevBuf<long long> boff(np), bas(nf), sel(m->n_basis);
+  OFM_HIP(hipMemcpyAsync(sel.p, selh.data(), sizeof(long long) * m->n_basis,
+                         hipMemcpyHostToDevice, st));
   OFM_HIP(hipMemsetAsync(H.p, 0, sizeof(double) * N * N, st));
   OFM_HIP(hipMemsetAsync(S.p, 0, sizeof(double) * N * N, st));
   OFM_HIP(hipMemcpyAsync(pj.p, m->pair_j.data(), sizeof(int) * np,
@@ -123,7 +169,8 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
   OFM_HIP(hipMemcpyAsync(bas.p, m->basis_off.data(), sizeof(long long) * nf,
                          hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_assemble, dim3(np), dim3(256), 0, st, pj.p, pn.p,
-                     boff.p, sts.p, bas.p, np, m->d_H, m->d_S, H.p, S.p, N);
+                     boff.p, sts.p, bas.p, sel.p, np, m->d_H, m->d_S, H.p, S.p,
+                     N);
   OFM_HIP(hipGetLastError());
   // eig(S), ascending
   OFM_BLAS(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper,

@@ -1022,10 +1022,10 @@ __device__ __forceinline__ int box_index(const int* org, const int* dims,
 // has work; the slices are summed in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_pair(
-    const PairTask* __restrict__ tasks, int ntask, int nblk_pad,
+    const PairTask* __restrict__ tasks, int ntask,
     const T* __restrict__ PHI, const T* __restrict__ HPHI,
     double* __restrict__ Hout, double* __restrict__ Sout) {
-  const int ti = xcd_tile(blockIdx.x, nblk_pad);
+  const int ti = blockIdx.x;
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
   const T* A = PHI + tk.a_off;
@@ -1109,10 +1109,10 @@ __global__ __launch_bounds__(WG) void k_pair(
 // states are orthonormalised in FP64, and the dropped a_lo b_lo term would
 // bias their diagonal by ~2^-18)
 __global__ __launch_bounds__(WG) void k_pair_x3(
-    const PairTask* __restrict__ tasks, int ntask, int nblk_pad,
+    const PairTask* __restrict__ tasks, int ntask,
     const float* __restrict__ PHI, const float* __restrict__ HPHI,
     double* __restrict__ Hout, double* __restrict__ Sout) {
-  const int ti = xcd_tile(blockIdx.x, nblk_pad);
+  const int ti = blockIdx.x;
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
   double* C = (tk.which ? Hout : Sout) + tk.c_off;
@@ -1205,13 +1205,12 @@ void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
                    int n_tasks, const T* phi, const T* hphi, double* H,
                    double* S, double flops, double bytes) {
   Timed tm(c, "elements", bytes, flops);
-  const int nblk = pad8(n_tasks);
   if constexpr (sizeof(T) == 8)
-    hipLaunchKernelGGL(k_pair<T>, dim3(nblk), dim3(WG), 0, c->stream, tasks,
-                       n_tasks, nblk, phi, hphi, H, S);
+    hipLaunchKernelGGL(k_pair<T>, dim3(n_tasks), dim3(WG), 0, c->stream,
+                       tasks, n_tasks, phi, hphi, H, S);
   else
-    hipLaunchKernelGGL(k_pair_x3, dim3(nblk), dim3(WG), 0, c->stream, tasks,
-                       n_tasks, nblk, phi, hphi, H, S);
+    hipLaunchKernelGGL(k_pair_x3, dim3(n_tasks), dim3(WG), 0, c->stream,
+                       tasks, n_tasks, phi, hphi, H, S);
   OFM_HIP(hipGetLastError());
 }
 template void pair_elements<double>(ofm_ctx*, const ofm_frags*,

@@ -230,7 +230,8 @@ std::vector<PairTask> plan_pair_tasks(const ofm_frags* f);
 // global solve (global_solve.cpp)
 void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
                   double e_hi, int* n_kept, int* n_eig, double* E, double* C,
-                  double* s_min);
+                  double* s_min, const unsigned char* keep = nullptr);
+void homo_energies(const ofm_mats* m, double* e);
 void destroy_blas(ofm_ctx* c);
 
 // kernel launchers (kernels.hip)

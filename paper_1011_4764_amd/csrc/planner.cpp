@@ -226,9 +226,17 @@ std::vector<PairTask> plan_pair_tasks(const ofm_frags* f) {
       tasks.push_back(t);
     }
   }
-  // tasks stay grouped by their row fragment j (pair order), so the blocks
-  // that read the same states run close together and, with the XCD-aware
-  // launch mapping, on the same XCD (its L2 serves the repeated reads)
+  // longest contraction first: better load balance across workgroups
+  // (grouping the tasks by row fragment for L2 reuse measured no faster:
+  // the gathers, not the HBM misses, bound this kernel)
+  std::stable_sort(tasks.begin(), tasks.end(),
+                   [](const PairTask& x, const PairTask& y) {
+                     const long long kx = (long long)x.om[0] * x.om[1] *
+                                          x.om[2] * x.ma * x.mb;
+                     const long long ky = (long long)y.om[0] * y.om[1] *
+                                          y.om[2] * y.ma * y.mb;
+                     return kx > ky;
+                   });
   return tasks;
 }
 

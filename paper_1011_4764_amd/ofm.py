@@ -32,7 +32,8 @@ EXPORTS = [
     "ofm_matrix_elements", "ofm_mats_info", "ofm_mats_copy",
     "ofm_mats_destroy", "ofm_solve_global", "ofm_set_profiling",
     "ofm_kernel_stats", "ofm_reset_stats", "ofm_stage_times",
-    "ofm_set_stencil_variant", "ofm_set_fragment_wells",
+    "ofm_set_stencil_variant", "ofm_set_fragment_wells", "ofm_select_homo",
+    "ofm_solve_global_subset", "ofm_homo_energies", "ofm_homo_lumo_gap",
 ]
 
 
@@ -64,6 +65,7 @@ _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int)
 _LL = C.POINTER(C.c_longlong)
+_UB = C.POINTER(C.c_ubyte)
 
 
 def lib():
@@ -108,6 +110,13 @@ def lib():
             "ofm_set_stencil_variant": ([_P, C.c_int], C.c_int),
             "ofm_set_fragment_wells": ([_P, C.c_int, _D, _D, C.c_double,
                                         C.c_double, _LL, _I], C.c_int),
+            "ofm_select_homo": ([_P, C.c_int, C.c_double, _UB], C.c_int),
+            "ofm_solve_global_subset": ([_P, _P, _UB, C.c_double, C.c_double,
+                                         C.c_double, _I, _I, _D, _D, _D],
+                                        C.c_int),
+            "ofm_homo_energies": ([_P, _D], C.c_int),
+            "ofm_homo_lumo_gap": ([_D, C.c_int, C.c_double, C.c_double, _I,
+                                   _D, _D], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -398,6 +407,59 @@ def ofm_solve_global(ctx: Context, m: Mats, s_thresh=1e-6, e_lo=-np.inf,
     if want_vectors:
         out["C"] = Cm[:nb * ne.value].reshape(ne.value, nb).T.copy()
     return out
+
+
+def ofm_select_homo(frags: Fragments, n_max, gap_min=0.0):
+    """Keep mask (n_basis bools) near every fragment's HOMO."""
+    keep = np.zeros(frags.n_basis, np.uint8)
+    _check(lib().ofm_select_homo(frags.handle, int(n_max), float(gap_min),
+                                 keep.ctypes.data_as(_UB)), frags.ctx.handle)
+    return keep.astype(bool)
+
+
+def ofm_solve_global_subset(ctx: Context, m: Mats, keep, s_thresh=1e-6,
+                            e_lo=-np.inf, e_hi=np.inf, want_vectors=False):
+    """ofm_solve_global on the pencil restricted to keep (None: all).
+    Returns dict(E, n_kept, s_min[, C with n_sel rows])."""
+    nb = m.frags.n_basis
+    kp = None if keep is None else np.ascontiguousarray(keep, np.uint8)
+    if kp is not None and kp.size != nb:
+        raise ValueError("keep needs one entry per basis function")
+    nsel = nb if kp is None else int(np.count_nonzero(kp))
+    E = np.zeros(nb)
+    Cm = np.zeros(max(nsel, 1) * nb) if want_vectors else None
+    nk, ne = C.c_int(), C.c_int()
+    smin = C.c_double()
+    st = lib().ofm_solve_global_subset(
+        ctx.handle, m.handle, None if kp is None else kp.ctypes.data_as(_UB),
+        float(s_thresh), float(e_lo), float(e_hi), C.byref(nk), C.byref(ne),
+        _dp(E), _dp(Cm), C.byref(smin))
+    _check(st, ctx.handle)
+    out = {"E": E[:ne.value].copy(), "n_kept": nk.value, "s_min": smin.value}
+    if want_vectors:
+        out["C"] = Cm[:nsel * ne.value].reshape(ne.value, nsel).T.copy()
+    return out
+
+
+def ofm_homo_energies(m: Mats):
+    """e_j = <HOMO_j|H|HOMO_j> per fragment (whole-system H)."""
+    e = np.zeros(m.frags.n_frag)
+    _check(lib().ofm_homo_energies(m.handle, _dp(e)), m.ctx.handle)
+    return e
+
+
+def ofm_homo_lumo_gap(E, e_ref, gap_min):
+    """(n_occ, e_homo, e_lumo) of the first gap above e_ref; n_occ = -1
+    when there is none."""
+    Ea = np.ascontiguousarray(E, np.float64)
+    n = C.c_int()
+    lo, hi = C.c_double(), C.c_double()
+    st = lib().ofm_homo_lumo_gap(_dp(Ea), int(Ea.size), float(e_ref),
+                                 float(gap_min), C.byref(n), C.byref(lo),
+                                 C.byref(hi))
+    if st != OFM_OK:
+        raise OfmError(st, "invalid arguments to ofm_homo_lumo_gap")
+    return n.value, lo.value, hi.value
 
 
 def unpack_blocks(frags: Fragments, H_blocks, S_blocks):

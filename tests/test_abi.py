@@ -37,3 +37,31 @@ def test_library_loads_without_gpu():
     for name in _declared():
         assert hasattr(L, name)
     assert "gfx950" in P.ofm_version()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libofm.so not built")
+def test_homo_lumo_gap_host_matches_oracle():
+    """ofm_homo_lumo_gap is host arithmetic in the library: it needs no GPU
+    and gives the oracle's gap on seeded random spectra, including the
+    no-gap and empty cases."""
+    import numpy as np
+
+    import oracle as O
+    import paper_1011_4764_amd as P
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        n = int(rng.integers(0, 40))
+        E = np.sort(rng.normal(size=n) * rng.uniform(0.1, 3.0))
+        e_ref = float(rng.normal())
+        gmin = float(rng.uniform(0, 1.0))
+        got = P.ofm_homo_lumo_gap(E, e_ref, gmin)
+        ref = O.homo_lumo_gap(E, e_ref, gmin)
+        assert got[0] == ref[0]
+        if ref[0] >= 0:
+            assert got[1:] == ref[1:]
+        else:
+            assert np.isnan(got[1]) and np.isnan(got[2])
+    with pytest.raises(P.OfmError):
+        P.ofm_homo_lumo_gap([1.0, 0.0], 0.0, 0.1)   # not ascending
+    with pytest.raises(P.OfmError):
+        P.ofm_homo_lumo_gap([0.0, 1.0], 0.0, -1.0)  # negative gap

@@ -168,3 +168,23 @@ def test_resident_filter_bit_identical(mctx, seed):
     err = np.abs(out[0][0] - np.concatenate(r.eps)).max()
     _say("  eps err vs oracle", err)
     assert err < 1e-5
+
+
+def test_mixed_homo_basis_subset(mctx, tiny0, tiny0_oracle):
+    """Mixed form: the top-2 HOMO basis gives the oracle's subset-pencil
+    eigenvalues within 1e-5 Ha."""
+    s, r = tiny0, tiny0_oracle
+    f = _build(mctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(mctx, f)
+    assert st == 0
+    keep = P.ofm_select_homo(f, 2)
+    ref_keep = O.select_top(r.eps, 2)
+    assert np.array_equal(keep, ref_keep)
+    m = P.ofm_matrix_elements(mctx, f)
+    g = P.ofm_solve_global_subset(mctx, m, keep, 1e-6)
+    ref = O.global_solve(*O.subset(r.H, r.S, ref_keep), 1e-6)
+    err = np.abs(g["E"] - ref["E"]).max()
+    _say("mixed HOMO subset err", err)
+    assert err < 1e-5
+    m.close()
+    f.close()

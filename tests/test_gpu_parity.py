@@ -421,3 +421,65 @@ def test_own_atoms_invalid(ctx, tiny0):
         P.ofm_set_fragment_wells(f, s.atoms, s.Z, s.frag_atom_ptr,
                                  s.frag_atom_idx, sigma=0.0)
     f.close()
+
+
+# ------------------------------------------- basis near the HOMO (Sec. III-B)
+
+@pytest.mark.parametrize("rule", ["top3", "gap"])
+def test_homo_basis_subset(ctx, tiny0, tiny0_oracle, rule):
+    """Keep masks from the GPU's fragment eigenvalues equal the oracle's;
+    with the oracle's states imported, the HOMO energies match to 1e-12 of
+    max|H| and the subset pencil's eigenvalues to 1e-10; the gap above the
+    HOMO energies is the oracle's."""
+    s, r = tiny0, tiny0_oracle
+    f = _build(ctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0
+    if rule == "top3":
+        keep = P.ofm_select_homo(f, 3)
+        ref_keep = O.select_top(r.eps, 3)
+    else:
+        gap = 0.05
+        keep = P.ofm_select_homo(f, 6, gap)
+        ref_keep = O.select_by_gap(r.eps, gap, 6)
+    _say("keep", rule, int(keep.sum()), "of", keep.size)
+    assert np.array_equal(keep, ref_keep)
+    for j in range(s.n_frag):
+        P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+    m = P.ofm_matrix_elements(ctx, f)
+    e = P.ofm_homo_energies(m)
+    e_ref = O.homo_energies(r.H, s.frag_states)
+    assert np.abs(e - e_ref).max() < 1e-12 * np.abs(r.H).max()
+    g = P.ofm_solve_global_subset(ctx, m, keep, 1e-6)
+    Hs, Ss = O.subset(r.H, r.S, ref_keep)
+    ref = O.global_solve(Hs, Ss, 1e-6)
+    assert g["n_kept"] == ref["n_kept"]
+    assert np.abs(g["E"] - ref["E"]).max() < 1e-10
+    got_gap = P.ofm_homo_lumo_gap(g["E"], float(e.max()), 0.02)
+    ref_gap = O.homo_lumo_gap(ref["E"], float(e_ref.max()), 0.02)
+    _say("gap", got_gap, ref_gap)
+    assert got_gap[0] == ref_gap[0]
+    if ref_gap[0] >= 0:
+        assert abs(got_gap[1] - ref_gap[1]) < 1e-10
+        assert abs(got_gap[2] - ref_gap[2]) < 1e-10
+    # keeping everything is the plain solve
+    ga = P.ofm_solve_global_subset(ctx, m, np.ones(keep.size, bool), 1e-6)
+    gb = P.ofm_solve_global(ctx, m, 1e-6)
+    assert np.array_equal(ga["E"], gb["E"])
+    m.close()
+    f.close()
+
+
+def test_homo_subset_errors(ctx, tiny0):
+    s = tiny0
+    f = _build(ctx, s)
+    with pytest.raises(P.OfmError, match="OFM_E_STATE"):
+        P.ofm_select_homo(f, 3)           # no states yet
+    P.ofm_solve_fragments(ctx, f)
+    with pytest.raises(P.OfmError, match="OFM_E_INVALID"):
+        P.ofm_select_homo(f, 0)
+    m = P.ofm_matrix_elements(ctx, f)
+    with pytest.raises(P.OfmError, match="OFM_E_INVALID"):
+        P.ofm_solve_global_subset(ctx, m, np.zeros(f.n_basis, bool))
+    m.close()
+    f.close()
