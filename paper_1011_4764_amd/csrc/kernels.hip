@@ -980,108 +980,140 @@ template void whole_h<float>(ofm_ctx*, const ofm_frags*, const float*, float*,
 // ---------------------------------------------------------------------------
 // grouped pair contraction: one workgroup per (pair, S|H) block
 // ---------------------------------------------------------------------------
-// Position of a lane inside the overlap cuboid, advanced point by point
-// (x fastest) instead of recomputed with divisions.
-struct Cursor {
-  int x, y, z;
+// The overlap Omega of a block is walked row by row (x fastest), each row
+// padded to a multiple of 4 points, in stages of KST padded points.  A stage
+// is loaded into LDS with one thread per (state, point) -- a wave reads
+// consecutive points of one state row -- and the MFMA tiles read their
+// operands from LDS.  Work split of a block over the 4 waves: blocks with
+// fewer than four 16x16 tiles split every stage's points instead (k-slices),
+// summed in a fixed order at the end.
+struct StagePos {   // a thread's point inside the current stage
+  int xg, yy, zz;   // 4-point group along x, row y, plane z of Omega
 };
-__device__ __forceinline__ Cursor cursor_at(int k, int ox, int oy) {
-  Cursor c;
-  c.x = k % ox;
-  const int r = k / ox;
-  c.y = r % oy;
-  c.z = r / oy;
-  return c;
-}
-__device__ __forceinline__ void step1(Cursor& c, int ox, int oy) {
-  if (++c.x == ox) {
-    c.x = 0;
-    if (++c.y == oy) {
-      c.y = 0;
-      ++c.z;
-    }
-  }
-}
-__device__ __forceinline__ void stepn(Cursor& c, int d, int ox, int oy) {
-  c.x += d;
-  while (c.x >= ox) {
-    c.x -= ox;
-    if (++c.y == oy) {
-      c.y = 0;
-      ++c.z;
-    }
-  }
-}
-__device__ __forceinline__ int box_index(const int* org, const int* dims,
-                                         const Cursor& c) {
-  return (org[0] + c.x) + dims[0] * ((org[1] + c.y) + dims[1] * (org[2] + c.z));
+
+__device__ __forceinline__ StagePos stage_start(int q, int gx, int oy) {
+  StagePos s;
+  s.xg = q % gx;
+  const int row = q / gx;
+  s.yy = row % oy;
+  s.zz = row / oy;
+  return s;
 }
 
-// Work split of one block over the 4 waves: blocks with fewer than four
-// 16x16 tiles split the contraction length instead (k-slices), so every wave
-// has work; the slices are summed in a fixed order.
-template <typename T>
+__device__ __forceinline__ void stage_advance(StagePos& s, int by, int gx,
+                                              int oy) {
+  s.xg += by;
+  while (s.xg >= gx) {
+    s.xg -= gx;
+    if (++s.yy == oy) {
+      s.yy = 0;
+      ++s.zz;
+    }
+  }
+}
+
+// box offsets of the thread's point in A's and B's boxes (valid: inside
+// Omega, not padding)
+__device__ __forceinline__ bool stage_point(const PairTask& tk,
+                                            const StagePos& s, int x,
+                                            long long& ia, long long& ib) {
+  if (s.zz >= tk.om[2] || x >= tk.om[0]) return false;
+  ia = (tk.a_org[0] + x) +
+       (long long)tk.a_dims[0] *
+           ((tk.a_org[1] + s.yy) + (long long)tk.a_dims[1] * (tk.a_org[2] + s.zz));
+  ib = (tk.b_org[0] + x) +
+       (long long)tk.b_dims[0] *
+           ((tk.b_org[1] + s.yy) + (long long)tk.b_dims[1] * (tk.b_org[2] + s.zz));
+  return true;
+}
+
+// write the block (symmetrised on diagonal blocks) from LDS
+__device__ __forceinline__ void pair_store(const PairTask& tk,
+                                           const double* blk, int ldb,
+                                           double* C) {
+  for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
+    const int i = e / tk.mb, m = e % tk.mb;
+    double v = blk[i * ldb + m];
+    if (tk.sym) v = 0.5 * (v + blk[m * ldb + i]);
+    C[e] = v;
+  }
+}
+
+// FP64 MFMA 16x16x4; RMAX >= the largest state count, a multiple of 16
+template <int RMAX>
 __global__ __launch_bounds__(WG) void k_pair(
     const PairTask* __restrict__ tasks, int ntask,
-    const T* __restrict__ PHI, const T* __restrict__ HPHI,
+    const double* __restrict__ PHI, const double* __restrict__ HPHI,
     double* __restrict__ Hout, double* __restrict__ Sout) {
+  constexpr int KST = 64, LP = KST + 1;
+  constexpr int UMAX = (RMAX / 16) * (RMAX / 16) > 4
+                           ? ((RMAX / 16) * (RMAX / 16) + 3) / 4 : 1;
   const int ti = blockIdx.x;
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
-  const T* A = PHI + tk.a_off;
-  const T* B = (tk.which ? HPHI : PHI) + tk.b_off;
+  const double* A = PHI + tk.a_off;
+  const double* B = (tk.which ? HPHI : PHI) + tk.b_off;
   double* C = (tk.which ? Hout : Sout) + tk.c_off;
-  const int ox = tk.om[0], oy = tk.om[1];
-  const int K = ox * oy * tk.om[2];
+  const int gx = (tk.om[0] + 3) >> 2;
+  const long long ngrp = (long long)gx * tk.om[1] * tk.om[2];
+  const int nst = (int)((4 * ngrp + KST - 1) / KST);
   const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
   const int ntiles = nta * ntb;
   const int ks = ntiles >= 4 ? 1 : 4 / ntiles;
-  const int nch = (K + 15) / 16;
-  __shared__ double blk[SMAX * SLD];
+  const int kw = KST / ks;
+  __shared__ double As[RMAX * LP];
+  __shared__ double Bs[RMAX * LP];
   __shared__ double part[4][256];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  for (int unit = wave; unit < ntiles * ks; unit += WG / 64) {
-    const int tile = unit / ks, slice = unit % ks;
-    const int ta = tile / ntb, tb = tile % ntb;
-    const int ra = ta * 16 + r, rb = tb * 16 + r;
-    const bool va = ra < tk.ma, vb = rb < tk.mb;
-    const T* pa = A + (long long)(va ? ra : 0) * tk.lda;
-    const T* pb = B + (long long)(vb ? rb : 0) * tk.ldb;
-    const int c0 = (int)((long long)slice * nch / ks);
-    const int c1 = (int)((long long)(slice + 1) * nch / ks);
-    int k = 16 * c0 + 4 * g;
-    Cursor cur = cursor_at(min(k, max(K - 1, 0)), ox, oy);
-    d4 acc = {0, 0, 0, 0};
-    // the trip count is uniform across the wave: an MFMA reads every lane's
-    // operands, so lanes may not leave the loop early
-    for (int kb = 16 * c0; kb < 16 * c1; kb += 16) {
-      double a[4], b[4];
+  const int pt = threadIdx.x & (KST - 1), i0 = threadIdx.x / KST;
+  StagePos sp = stage_start(pt >> 2, gx, tk.om[1]);
+  d4 acc[UMAX];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = 0;
-        b[u] = 0;
-        if (k + u < K) {
-          if (va) a[u] = (double)pa[box_index(tk.a_org, tk.a_dims, cur)];
-          if (vb) b[u] = (double)pb[box_index(tk.b_org, tk.b_dims, cur)];
-          step1(cur, ox, oy);
-        }
-      }
-      acc = mfma_f64(a[0], b[0], acc);
-      acc = mfma_f64(a[1], b[1], acc);
-      acc = mfma_f64(a[2], b[2], acc);
-      acc = mfma_f64(a[3], b[3], acc);
-      k += 16;
-      if (k < K) stepn(cur, 12, ox, oy);
+  for (int u = 0; u < UMAX; ++u) acc[u] = d4{0, 0, 0, 0};
+  for (int st = 0; st < nst; ++st) {
+    long long ia = 0, ib = 0;
+    const bool valid = stage_point(tk, sp, 4 * sp.xg + (pt & 3), ia, ib);
+#pragma unroll
+    for (int m = 0; m < RMAX / (WG / KST); ++m) {
+      const int i = i0 + (WG / KST) * m;
+      As[i * LP + pt] = (valid && i < tk.ma) ? A[(long long)i * tk.lda + ia] : 0.0;
+      Bs[i * LP + pt] = (valid && i < tk.mb) ? B[(long long)i * tk.ldb + ib] : 0.0;
     }
+    stage_advance(sp, KST / 4, gx, tk.om[1]);
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int rl = g + 4 * i;
-      if (ks == 1) {
-        const int row = ta * 16 + rl, col = tb * 16 + r;
-        if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = acc[i];
-      } else {
-        part[unit][rl * 16 + r] = acc[i];
+    for (int u = 0; u < UMAX; ++u) {
+      const int unit = wave + 4 * u;
+      if (unit < ntiles * ks) {   // wave-uniform
+        const int tile = unit / ks, slice = unit % ks;
+        const int ta = tile / ntb, tb = tile % ntb;
+        const double* pa = As + (ta * 16 + r) * LP + slice * kw + 4 * g;
+        const double* pb = Bs + (tb * 16 + r) * LP + slice * kw + 4 * g;
+        for (int kk = 0; kk < kw; kk += 16)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[u] = mfma_f64(pa[kk + v], pb[kk + v], acc[u]);
+      }
+    }
+    __syncthreads();
+  }
+  double* blk = As;   // the staging area is free now
+#pragma unroll
+  for (int u = 0; u < UMAX; ++u) {
+    const int unit = wave + 4 * u;
+    if (unit < ntiles * ks) {
+      const int tile = unit / ks;
+      const int ta = tile / ntb, tb = tile % ntb;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rl = g + 4 * i;
+        if (ks == 1) {
+          const int row = ta * 16 + rl, col = tb * 16 + r;
+          if (row < tk.ma && col < tk.mb) blk[row * LP + col] = acc[u][i];
+        } else {
+          part[unit][rl * 16 + r] = acc[u][i];
+        }
       }
     }
   }
@@ -1092,26 +1124,25 @@ __global__ __launch_bounds__(WG) void k_pair(
       double v = 0;
       for (int sl = 0; sl < ks; ++sl) v += part[tile * ks + sl][rl * 16 + cl];
       const int row = (tile / ntb) * 16 + rl, col = (tile % ntb) * 16 + cl;
-      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = v;
+      if (row < tk.ma && col < tk.mb) blk[row * LP + col] = v;
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
-    const int i = e / tk.mb, m = e % tk.mb;
-    double v = blk[i * SLD + m];
-    if (tk.sym) v = 0.5 * (v + blk[m * SLD + i]);
-    C[e] = v;
-  }
+  pair_store(tk, blk, LP, C);
 }
 
-// mixed form of the pair contraction: split-BF16 x3 MFMA, FP32 sums flushed
-// into FP64 every 1024 points; diagonal S blocks are the identity (the
-// states are orthonormalised in FP64, and the dropped a_lo b_lo term would
-// bias their diagonal by ~2^-18)
+// mixed form of the pair contraction: split-BF16 x3 MFMA 16x16x32 on FP32
+// states, FP32 sums of a stage flushed into FP64; diagonal S blocks are the
+// identity (the states are orthonormalised in FP64, and the dropped
+// a_lo b_lo term would bias their diagonal by ~2^-18)
+template <int RMAX>
 __global__ __launch_bounds__(WG) void k_pair_x3(
     const PairTask* __restrict__ tasks, int ntask,
     const float* __restrict__ PHI, const float* __restrict__ HPHI,
     double* __restrict__ Hout, double* __restrict__ Sout) {
+  constexpr int KST = 128, LP = KST + 4;
+  constexpr int UMAX = (RMAX / 16) * (RMAX / 16) > 4
+                           ? ((RMAX / 16) * (RMAX / 16) + 3) / 4 : 1;
   const int ti = blockIdx.x;
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
@@ -1123,61 +1154,85 @@ __global__ __launch_bounds__(WG) void k_pair_x3(
   }
   const float* A = PHI + tk.a_off;
   const float* B = (tk.which ? HPHI : PHI) + tk.b_off;
-  const int ox = tk.om[0], oy = tk.om[1];
-  const int K = ox * oy * tk.om[2];
+  const int gx = (tk.om[0] + 3) >> 2;
+  const long long ngrp = (long long)gx * tk.om[1] * tk.om[2];
+  const int nst = (int)((4 * ngrp + KST - 1) / KST);
   const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
   const int ntiles = nta * ntb;
   const int ks = ntiles >= 4 ? 1 : 4 / ntiles;
-  const int nch = (K + 31) / 32;
-  __shared__ double blk[SMAX * SLD];
+  const int kw = KST / ks;
+  __shared__ float As[RMAX * LP];
+  __shared__ float Bs[RMAX * LP];
   __shared__ double part[4][256];
+  __shared__ double blk[RMAX * (RMAX + 1)];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  for (int unit = wave; unit < ntiles * ks; unit += WG / 64) {
-    const int tile = unit / ks, slice = unit % ks;
-    const int ta = tile / ntb, tb = tile % ntb;
-    const int ra = ta * 16 + r, rb = tb * 16 + r;
-    const bool va = ra < tk.ma, vb = rb < tk.mb;
-    const float* pa = A + (long long)(va ? ra : 0) * tk.lda;
-    const float* pb = B + (long long)(vb ? rb : 0) * tk.ldb;
-    const int c0 = (int)((long long)slice * nch / ks);
-    const int c1 = (int)((long long)(slice + 1) * nch / ks);
-    int k = 32 * c0 + 8 * g;
-    Cursor cur = cursor_at(min(k, max(K - 1, 0)), ox, oy);
-    f4v acc = {0, 0, 0, 0};
-    double tot[4] = {0, 0, 0, 0};
-    int since = 0;
-    for (int kb = 32 * c0; kb < 32 * c1; kb += 32) {   // uniform trip count
-      float a[8], b[8];
+  // a thread loads two consecutive groups' worth of points: 2 x 64 = KST
+  const int pt = threadIdx.x & 63, i0 = threadIdx.x >> 6;
+  StagePos sp0 = stage_start(pt >> 2, gx, tk.om[1]);
+  StagePos sp1 = stage_start((pt >> 2) + 16, gx, tk.om[1]);
+  f4v acc[UMAX];
+  double tot[UMAX][4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a[u] = 0.f;
-        b[u] = 0.f;
-        if (k + u < K) {
-          if (va) a[u] = pa[box_index(tk.a_org, tk.a_dims, cur)];
-          if (vb) b[u] = pb[box_index(tk.b_org, tk.b_dims, cur)];
-          step1(cur, ox, oy);
-        }
-      }
-      acc = mfma_x3(a, b, acc);
-      if (++since == 32) {
+  for (int u = 0; u < UMAX; ++u) {
+    acc[u] = f4v{0, 0, 0, 0};
+    tot[u][0] = tot[u][1] = tot[u][2] = tot[u][3] = 0;
+  }
+  for (int st = 0; st < nst; ++st) {
+    long long ia0 = 0, ib0 = 0, ia1 = 0, ib1 = 0;
+    const bool v0 = stage_point(tk, sp0, 4 * sp0.xg + (pt & 3), ia0, ib0);
+    const bool v1 = stage_point(tk, sp1, 4 * sp1.xg + (pt & 3), ia1, ib1);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) tot[i] += (double)acc[i];
-        acc = f4v{0, 0, 0, 0};
-        since = 0;
-      }
-      k += 32;
-      if (k < K) stepn(cur, 24, ox, oy);
+    for (int m = 0; m < RMAX / 4; ++m) {
+      const int i = i0 + 4 * m;
+      const bool ra = i < tk.ma, rb = i < tk.mb;
+      As[i * LP + pt] = (v0 && ra) ? A[(long long)i * tk.lda + ia0] : 0.f;
+      As[i * LP + 64 + pt] = (v1 && ra) ? A[(long long)i * tk.lda + ia1] : 0.f;
+      Bs[i * LP + pt] = (v0 && rb) ? B[(long long)i * tk.ldb + ib0] : 0.f;
+      Bs[i * LP + 64 + pt] = (v1 && rb) ? B[(long long)i * tk.ldb + ib1] : 0.f;
     }
+    stage_advance(sp0, KST / 4, gx, tk.om[1]);
+    stage_advance(sp1, KST / 4, gx, tk.om[1]);
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      tot[i] += (double)acc[i];
-      const int rl = 4 * g + i;
-      if (ks == 1) {
-        const int row = ta * 16 + rl, col = tb * 16 + r;
-        if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = tot[i];
-      } else {
-        part[unit][rl * 16 + r] = tot[i];
+    for (int u = 0; u < UMAX; ++u) {
+      const int unit = wave + 4 * u;
+      if (unit < ntiles * ks) {   // wave-uniform
+        const int tile = unit / ks, slice = unit % ks;
+        const int ta = tile / ntb, tb = tile % ntb;
+        const float* pa = As + (ta * 16 + r) * LP + slice * kw + 8 * g;
+        const float* pb = Bs + (tb * 16 + r) * LP + slice * kw + 8 * g;
+        for (int kk = 0; kk < kw; kk += 32) {
+          float a[8], b[8];
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            a[v] = pa[kk + v];
+            b[v] = pb[kk + v];
+          }
+          acc[u] = mfma_x3(a, b, acc[u]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tot[u][i] += (double)acc[u][i];
+        acc[u] = f4v{0, 0, 0, 0};
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < UMAX; ++u) {
+    const int unit = wave + 4 * u;
+    if (unit < ntiles * ks) {
+      const int tile = unit / ks;
+      const int ta = tile / ntb, tb = tile % ntb;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rl = 4 * g + i;
+        if (ks == 1) {
+          const int row = ta * 16 + rl, col = tb * 16 + r;
+          if (row < tk.ma && col < tk.mb) blk[row * (RMAX + 1) + col] = tot[u][i];
+        } else {
+          part[unit][rl * 16 + r] = tot[u][i];
+        }
       }
     }
   }
@@ -1188,16 +1243,11 @@ __global__ __launch_bounds__(WG) void k_pair_x3(
       double v = 0;
       for (int sl = 0; sl < ks; ++sl) v += part[tile * ks + sl][rl * 16 + cl];
       const int row = (tile / ntb) * 16 + rl, col = (tile % ntb) * 16 + cl;
-      if (row < tk.ma && col < tk.mb) blk[row * SLD + col] = v;
+      if (row < tk.ma && col < tk.mb) blk[row * (RMAX + 1) + col] = v;
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
-    const int i = e / tk.mb, m = e % tk.mb;
-    double v = blk[i * SLD + m];
-    if (tk.sym) v = 0.5 * (v + blk[m * SLD + i]);
-    C[e] = v;
-  }
+  pair_store(tk, blk, RMAX + 1, C);
 }
 
 template <typename T>
@@ -1205,12 +1255,24 @@ void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
                    int n_tasks, const T* phi, const T* hphi, double* H,
                    double* S, double flops, double bytes) {
   Timed tm(c, "elements", bytes, flops);
-  if constexpr (sizeof(T) == 8)
-    hipLaunchKernelGGL(k_pair<T>, dim3(n_tasks), dim3(WG), 0, c->stream,
-                       tasks, n_tasks, phi, hphi, H, S);
-  else
-    hipLaunchKernelGGL(k_pair_x3, dim3(n_tasks), dim3(WG), 0, c->stream,
-                       tasks, n_tasks, phi, hphi, H, S);
+  const int rm = f->max_states <= 16 ? 16 : f->max_states <= 32 ? 32
+               : f->max_states <= 48 ? 48 : 64;
+#define PAIR(R)                                                              \
+  do {                                                                       \
+    if constexpr (sizeof(T) == 8)                                            \
+      hipLaunchKernelGGL(k_pair<R>, dim3(n_tasks), dim3(WG), 0, c->stream,   \
+                         tasks, n_tasks, (const double*)phi,                 \
+                         (const double*)hphi, H, S);                         \
+    else                                                                     \
+      hipLaunchKernelGGL(k_pair_x3<R>, dim3(n_tasks), dim3(WG), 0,           \
+                         c->stream, tasks, n_tasks, (const float*)phi,       \
+                         (const float*)hphi, H, S);                          \
+  } while (0)
+  if (rm == 16) PAIR(16);
+  else if (rm == 32) PAIR(32);
+  else if (rm == 48) PAIR(48);
+  else PAIR(64);
+#undef PAIR
   OFM_HIP(hipGetLastError());
 }
 template void pair_elements<double>(ofm_ctx*, const ofm_frags*,

@@ -483,3 +483,31 @@ def test_homo_subset_errors(ctx, tiny0):
         P.ofm_solve_global_subset(ctx, m, np.zeros(f.n_basis, bool))
     m.close()
     f.close()
+
+
+def test_widest_block_end_to_end(ctx):
+    """The widest supported block (56 states + 8 guard vectors = 64: 4x4
+    Gram tiles, 64-wide rotations, 64x64 Jacobi, 4x4 pair tiles) on two
+    overlapping ragged boxes: eigenvalues within 1e-8 Ha and the window of
+    the global solve within 1e-8 Ha of the oracle."""
+    rng = np.random.default_rng(64)
+    shape = (17, 11, 12)
+    V = -np.abs(rng.standard_normal(shape[::-1])) * 0.5
+    lo = [(0, 0, 0), (6, 1, 1)]
+    dims = [(11, 10, 11), (11, 10, 10)]
+    states = [56, 56]
+    s = box_system(shape, 0.5, lo, dims, states, V=V)
+    r = O.run(V, 0.5, lo, dims, states)
+    f = _build(ctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    _say("widest block: iterations", it, "status", st)
+    assert st == 0 and cv.all()
+    err = np.abs(eps - np.concatenate(r.eps)).max()
+    _say("  eps err", err)
+    assert err < 1e-8
+    m = P.ofm_matrix_elements(ctx, f)
+    g = P.ofm_solve_global(ctx, m, 1e-6, -1e30, O.window_below_cutoff(r.eps)[1])
+    assert len(g["E"]) == len(r.solve["window"])
+    assert np.abs(g["E"] - r.solve["window"]).max() < 1e-8
+    m.close()
+    f.close()
