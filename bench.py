@@ -264,6 +264,7 @@ def main():
                      "TFLOPs": (gr["flops"] / gr["ms"] / 1e9) if gr["ms"] else 0},
             "elements": {"launches": el["launches"],
                          "avg_ms": el["ms"] / max(el["launches"], 1),
+                         "GBps": (el["bytes"] / el["ms"] / 1e6) if el["ms"] else 0,
                          "TFLOPs": (el["flops"] / el["ms"] / 1e9) if el["ms"] else 0,
                          "frac_fp64_peak": ((el["flops"] / el["ms"] / 1e9)
                                             / FP64_PEAK_TFS) if el["ms"] else 0},

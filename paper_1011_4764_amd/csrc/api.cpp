@@ -936,13 +936,16 @@ ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {
       OFM_HIP(hipMemsetAsync(m->d_S, 0, sizeof(double) * f->n_values, s));
       OFM_HIP(hipMemcpyAsync(dt, tasks.data(), sizeof(PairTask) * tasks.size(),
                              hipMemcpyHostToDevice, s));
-      double flops = 0, bytes = 0;
-      for (auto& t : tasks)
-        flops += 2.0 * t.ma * t.mb * (double)t.om[0] * t.om[1] * t.om[2];
+      // algorithmic bytes of the pair-centric contraction: every block reads
+      // its two operands over its overlap once (each fragment's states and
+      // H|phi> are read once per block that touches them), plus the blocks
       const double w = (double)wsize(c);
-      for (auto& d : f->host)
-        bytes += (double)(d.npts + d.ndil) * d.n_states * w;
-      bytes += 2.0 * 8.0 * f->n_values;
+      double flops = 0, bytes = 2.0 * 8.0 * f->n_values;
+      for (auto& t : tasks) {
+        const double K = (double)t.om[0] * t.om[1] * t.om[2];
+        flops += 2.0 * t.ma * t.mb * K;
+        bytes += (double)(t.ma + t.mb) * K * w;
+      }
       if (c->precision == OFM_FP64)
         k::pair_elements<double>(c, f, dt, (int)tasks.size(),
                                  arena<double>(f->d_x), arena<double>(f->d_hphi),
