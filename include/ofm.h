@@ -105,6 +105,11 @@ typedef struct {
                             launch with the vector held on chip (same bits
                             as the per-step launches) [on]; -1: per-step
                             launches for every box                         */
+  int fused;             /* >= 0: when every box's xy plane fits one
+                            workgroup (at most 2048 points in FP64, 4096 in
+                            FP32), each launch runs two filter steps (same
+                            bits as single steps) [on]; -1: one step per
+                            launch                                         */
 } ofm_solve_opts;
 
 typedef struct ofm_ctx ofm_ctx;

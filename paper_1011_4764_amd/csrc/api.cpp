@@ -164,7 +164,7 @@ void free_frags(ofm_frags* f) {
   void* ptrs[] = {f->d_frag, f->d_v, f->d_v32, f->d_x, f->d_p, f->d_hx,
                   f->d_hphi, f->d_tiles[0], f->d_tiles[1], f->d_tiles[2],
                   f->d_ftiles, f->d_tiles_nr[0], f->d_tiles_nr[1],
-                  f->d_tiles_nr[2],
+                  f->d_tiles_nr[2], f->d_vt[0], f->d_vt[1],
                   f->d_stiles, f->d_rtiles, f->d_G,
                   f->d_Q, f->d_theta, f->d_res, f->d_res_partial, f->d_fs,
                   f->d_active, f->d_iters, f->d_conv, f->d_flags,
@@ -182,6 +182,7 @@ struct SolveCfg {
   bool autotune;
   bool use_graph;
   bool resident;
+  bool fused;
 };
 
 template <typename T>
@@ -293,6 +294,11 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   int2* const* sweep_tiles = res ? f->d_tiles_nr : f->d_tiles;
   const int* sweep_n = res ? f->n_tiles_nr : f->n_tiles;
   if (res && sweep_n[var] == 0) tuning = false;   // nothing left to tune
+  // two filter steps per launch when every box of the sweep fits one
+  // workgroup's plane
+  const int vset = res ? 1 : 0;
+  const int ppt2 = cfg.fused && f->n_vt[vset] > 0
+                       ? k::stencil2_ppt((int)w, f->vt_plane[vset]) : 0;
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
     // filter work: unlocked vectors of the active fragments (strip launches
     // and on-chip filter separately)
@@ -317,6 +323,17 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                            32.0 * rnb * cfg.degree);
     }
     auto sweep = [&](bool timed_each) {
+      if (ppt2 > 0 && !tuning) {
+        for (int step = 1; step < cfg.degree; step += 2) {
+          // y_{k-1}, y_{k-2} read (no y_{k-2} on the first pair), y_k and
+          // y_{k+1} written, V_j once per box
+          const double by = (step == 1 ? 3 * nb : 4 * nb) * w + npt * w;
+          k::apply_h2<T>(timed_each ? c : nullptr, f, X, P, f->d_vt[vset],
+                         f->n_vt[vset], ppt2, f->d_active, step, f->d_fs, by,
+                         64.0 * nb);
+        }
+        return;
+      }
       for (int step = 1; step <= cfg.degree; ++step) {
         const bool odd = step & 1;
         const T* in = odd ? X : P;
@@ -359,9 +376,16 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         OFM_HIP(ie);
       }
       double by = 0;
-      for (int step = 1; step <= cfg.degree; ++step)
-        by += (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
-      Timed tm(c, "stencil", by, 32.0 * nb * cfg.degree, cfg.degree);
+      int launches = cfg.degree;
+      if (ppt2 > 0) {
+        launches = cfg.degree / 2;
+        for (int step = 1; step < cfg.degree; step += 2)
+          by += (step == 1 ? 3 * nb : 4 * nb) * w + npt * w;
+      } else {
+        for (int step = 1; step <= cfg.degree; ++step)
+          by += (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
+      }
+      Timed tm(c, "stencil", by, 32.0 * nb * cfg.degree, launches);
       OFM_HIP(hipGraphLaunch(sweep_exec, s));
     }
     cholqr();
@@ -535,6 +559,23 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
                                  hipMemcpyHostToDevice, s));
         OFM_HIP(hipStreamSynchronize(s));
       }
+      for (int set = 0; set < 2; ++set) {
+        std::vector<int2> vt;
+        int mp = 0;
+        for (int j = 0; j < n_frag; ++j) {
+          const FragDev& d = f->host[j];
+          if (set == 1 && k::resident_eligible((int)w, d)) continue;
+          mp = std::max(mp, d.dims[0] * d.dims[1]);
+          for (int v = 0; v < d.bw; ++v) vt.push_back(make_int2(j, v));
+        }
+        f->n_vt[set] = (int)vt.size();
+        f->vt_plane[set] = mp;
+        f->d_vt[set] = dev_alloc<int2>(vt.size());
+        if (!vt.empty())
+          OFM_HIP(hipMemcpyAsync(f->d_vt[set], vt.data(), sizeof(int2) * vt.size(),
+                                 hipMemcpyHostToDevice, s));
+        OFM_HIP(hipStreamSynchronize(s));
+      }
       {
         std::vector<int2> ft;
         for (int j = 0; j < n_frag; ++j)
@@ -681,6 +722,7 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.autotune = !opts || opts->autotune >= 0;
     cfg.use_graph = !opts || opts->use_graph >= 0;
     cfg.resident = !opts || opts->resident >= 0;
+    cfg.fused = !opts || opts->fused >= 0;
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,
                 "guard vectors are fixed when the fragments are built");

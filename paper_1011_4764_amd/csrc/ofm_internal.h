@@ -133,6 +133,11 @@ struct ofm_frags {
   int n_ftiles = 0;
   int2* d_tiles_nr[3] = {nullptr, nullptr, nullptr};
   int n_tiles_nr[3] = {0, 0, 0};
+  // (fragment, vector) tiles of the two-step kernel: every fragment [0], the
+  // fragments the on-chip filter does not take [1]; largest plane of each
+  int2* d_vt[2] = {nullptr, nullptr};
+  int n_vt[2] = {0, 0};
+  int vt_plane[2] = {0, 0};
   int variant = -1;            // stencil variant in use (-1: not chosen)
   int2* d_stiles = nullptr;
   int n_stiles = 0;
@@ -249,6 +254,12 @@ int stencil_ppt(int elem_bytes, int variant);
 std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
                                 int variant, int nvec_only, int only,
                                 bool skip_resident = false);
+// two Chebyshev steps per launch for boxes whose plane fits one workgroup
+int stencil2_ppt(int elem_bytes, int max_plane);
+template <typename T>
+void apply_h2(ofm_ctx* c, const ofm_frags* f, T* X, T* P, const int2* tiles,
+              int ntiles, int ppt, const int* active, int step,
+              const FilterState* fs, double alg_bytes, double flops);
 // whole Chebyshev filter with the vector on chip (FP32, boxes <= 32^3)
 bool resident_eligible(int elem_bytes, const FragDev& d);
 void filter_resident(ofm_ctx* c, const ofm_frags* f, float* X,

@@ -51,7 +51,8 @@ class OfmSolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int),
                 ("guard", C.c_int), ("degree", C.c_int),
                 ("seed", C.c_ulonglong), ("use_graph", C.c_int),
-                ("autotune", C.c_int), ("resident", C.c_int)]
+                ("autotune", C.c_int), ("resident", C.c_int),
+                ("fused", C.c_int)]
 
 
 class OfmError(RuntimeError):
@@ -291,11 +292,12 @@ def ofm_build_fragments(ctx: Context, shape_xyz, h, V, frag_lo, frag_dims,
 
 def ofm_solve_fragments(ctx: Context, frags: Fragments, tol=0.0, max_iter=0,
                         degree=0, seed=0, use_graph=0, autotune=0,
-                        resident=0, raise_on_noconv=False):
+                        resident=0, fused=0, raise_on_noconv=False):
     """Returns (status, eps (sum s_j,), iters (n_frag,), converged (n_frag,)).
-    use_graph / autotune / resident: 0 = library default (on), -1 = off."""
+    use_graph / autotune / resident / fused: 0 = library default (on),
+    -1 = off."""
     o = OfmSolveOpts(float(tol), int(max_iter), 0, int(degree), int(seed),
-                     int(use_graph), int(autotune), int(resident))
+                     int(use_graph), int(autotune), int(resident), int(fused))
     eps = np.zeros(frags.n_basis)
     it = np.zeros(frags.n_frag, np.int32)
     cv = np.zeros(frags.n_frag, np.uint8)

@@ -511,3 +511,37 @@ def test_widest_block_end_to_end(ctx):
     assert np.abs(g["E"] - r.solve["window"]).max() < 1e-8
     m.close()
     f.close()
+
+
+@pytest.mark.parametrize("case", ["tiny", "wide"])
+def test_fused_two_step_bit_identical(ctx, tiny0, case):
+    """Two filter steps per launch give the same bits as one step per
+    launch (eigenvalues, iteration counts, states), graph on and off; planes
+    of 144 points (one point per thread) and up to 1024 (four)."""
+    if case == "tiny":
+        s = tiny0
+    else:
+        rng = np.random.default_rng(7)
+        shape = (40, 34, 14)
+        V = -np.abs(rng.standard_normal(shape[::-1])) * 0.3
+        s = box_system(shape, 0.5, [(0, 0, 0), (16, 17, 1)],
+                       [(32, 32, 10), (20, 15, 12)], [5, 4], V=V)
+    out = []
+    for fused, graph in ((0, 0), (-1, 0), (0, -1)):
+        _say("fused", fused, "graph", graph, case)
+        f = _build(ctx, s)
+        st, eps, it, cv = P.ofm_solve_fragments(ctx, f, fused=fused,
+                                                use_graph=graph)
+        assert st == 0 and cv.all()
+        out.append((eps, it, [P.ofm_get_states(f, j)[1]
+                              for j in range(s.n_frag)]))
+        f.close()
+    for eps, it, phis in out[1:]:
+        assert np.array_equal(eps, out[0][0])
+        assert np.array_equal(it, out[0][1])
+        for a, b in zip(phis, out[0][2]):
+            assert np.array_equal(a, b)
+    if case == "wide":
+        r = O.run(s.potential(), 0.5, s.frag_lo, s.frag_dims, s.frag_states,
+                  solve=False)
+        assert np.abs(out[0][0] - np.concatenate(r.eps)).max() < 1e-8
