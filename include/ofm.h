@@ -302,8 +302,9 @@ ofm_status ofm_homo_lumo_gap(const double* E, int n, double e_ref,
    kernels on the context stream. */
 ofm_status ofm_set_profiling(ofm_ctx* ctx, int on);
 /* Accumulated timing of one kernel family since the last reset: "stencil"
-   (fragment-Hamiltonian filter steps), "gram" (subspace contractions),
-   "elements" (pair contractions), "rotate", "small".  total_ms is the sum of
+   (one fragment-Hamiltonian step per launch), "stencil2" (two filter steps
+   per launch), "filter" (whole filter with the vector on chip), "gram"
+   (subspace contractions), "elements" (pair contractions), "rotate".  total_ms is the sum of
    launch durations, alg_bytes the algorithmic HBM bytes of those launches
    (inputs read once, outputs written once), flops their useful flops. */
 ofm_status ofm_kernel_stats(ofm_ctx* ctx, const char* family,

@@ -385,7 +385,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         for (int step = 1; step <= cfg.degree; ++step)
           by += (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
       }
-      Timed tm(c, "stencil", by, 32.0 * nb * cfg.degree, launches);
+      Timed tm(c, ppt2 > 0 ? "stencil2" : "stencil", by,
+               32.0 * nb * cfg.degree, launches);
       OFM_HIP(hipGraphLaunch(sweep_exec, s));
     }
     cholqr();

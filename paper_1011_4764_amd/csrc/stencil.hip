@@ -400,7 +400,7 @@ void apply_h2(ofm_ctx* c, const ofm_frags* f, T* X, T* P, const int2* tiles,
     Vj = (const T*)f->d_vf32;
   const double nh = -0.5 / (f->grid.h * f->grid.h);
   const int nblk = pad8(ntiles);
-  Timed tm(c, "stencil", alg_bytes, flops);
+  Timed tm(c, "stencil2", alg_bytes, flops);
   hipStream_t stream = f->ctx->stream;
 #define LAUNCH2(PP)                                                          \
   hipLaunchKernelGGL((k_apply_h2<T, PP>), dim3(nblk), dim3(H2T), 0, stream,  \
