@@ -33,7 +33,8 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 LDS_BYTES_PER_POINT_STEP = 11 * 4   # on-chip filter, FP32
 STENCIL_KERNELS = {
     "stencil": "k_apply_h (one Chebyshev filter step of H_j per launch)",
-    "stencil2": "k_apply_h2 (two Chebyshev filter steps of H_j per launch)",
+    "multistep": "k_apply_hm (two or three Chebyshev filter steps of H_j "
+                 "per launch)",
 }
 
 
@@ -203,7 +204,7 @@ def main():
         for key in stage_sum:
             res[key] = stage_sum[key] / steps
         res["stencil"] = ctx.kernel_stats("stencil")
-        res["stencil2"] = ctx.kernel_stats("stencil2")
+        res["multistep"] = ctx.kernel_stats("multistep")
         res["elements"] = ctx.kernel_stats("elements")
         res["gram"] = ctx.kernel_stats("gram")
         res["filter"] = ctx.kernel_stats("filter")
@@ -217,9 +218,9 @@ def main():
     el, gr = main_form["elements"], main_form["gram"]
     # the dominant stencil kernel: two filter steps per launch where every
     # plane fits one workgroup, else one step per launch
-    two = main_form["stencil2"]["ms"] > main_form["stencil"]["ms"]
-    st = main_form["stencil2" if two else "stencil"]
-    kname = STENCIL_KERNELS["stencil2" if two else "stencil"]
+    two = main_form["multistep"]["ms"] > main_form["stencil"]["ms"]
+    st = main_form["multistep" if two else "stencil"]
+    kname = STENCIL_KERNELS["multistep" if two else "stencil"]
     avg_ms = st["ms"] / max(st["launches"], 1)
     bytes_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -262,7 +263,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(
-                f"{'stencil2' if two else 'stencil'}_{args.config}_{args.precision}"),
+                f"{'multistep' if two else 'stencil'}_{args.config}_{args.precision}"),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + "
                             "WRITE_SIZE, copy-calibrated)",
             "launches": st["launches"], "avg_launch_ms": avg_ms,
@@ -307,12 +308,12 @@ def main():
             "whole_step_speedup_vs_fp64": ms_step / mx["ms_step"],
             "fp64_at_2e-5_solve_ms": eq["solve_ms"],
         }
-        ms2 = mx["stencil2"]
+        ms2 = mx["multistep"]
         if ms2["launches"]:
             a_ms = ms2["ms"] / ms2["launches"]
             ach = ms2["bytes"] / ms2["launches"] / (a_ms * 1e-3) / 1e9
-            out["mixed"]["stencil2_roofline"] = {
-                "kernel": "k_apply_h2<float>", "bound": "hbm", "achieved": ach,
+            out["mixed"]["multistep_roofline"] = {
+                "kernel": "k_apply_hm<float>", "bound": "hbm", "achieved": ach,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": a_ms,
                 "launches": ms2["launches"]}

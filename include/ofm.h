@@ -105,11 +105,11 @@ typedef struct {
                             launch with the vector held on chip (same bits
                             as the per-step launches) [on]; -1: per-step
                             launches for every box                         */
-  int fused;             /* >= 0: when every box's xy plane fits one
-                            workgroup (at most 2048 points in FP64, 4096 in
-                            FP32), each launch runs two filter steps (same
-                            bits as single steps) [on]; -1: one step per
-                            launch                                         */
+  int fused;             /* when every box's xy plane fits one workgroup
+                            (at most 2048 points in FP64, 4096 in FP32),
+                            filter steps per launch: 0 or 2: two [default];
+                            3: three; -1 (or 1): one.  Same bits in every
+                            case.                                          */
 } ofm_solve_opts;
 
 typedef struct ofm_ctx ofm_ctx;
@@ -302,8 +302,8 @@ ofm_status ofm_homo_lumo_gap(const double* E, int n, double e_ref,
    kernels on the context stream. */
 ofm_status ofm_set_profiling(ofm_ctx* ctx, int on);
 /* Accumulated timing of one kernel family since the last reset: "stencil"
-   (one fragment-Hamiltonian step per launch), "stencil2" (two filter steps
-   per launch), "filter" (whole filter with the vector on chip), "gram"
+   (one fragment-Hamiltonian step per launch), "multistep" (two or three
+   filter steps per launch), "filter" (whole filter with the vector on chip), "gram"
    (subspace contractions), "elements" (pair contractions), "rotate".  total_ms is the sum of
    launch durations, alg_bytes the algorithmic HBM bytes of those launches
    (inputs read once, outputs written once), flops their useful flops. */

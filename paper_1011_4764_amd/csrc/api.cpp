@@ -175,6 +175,16 @@ void free_frags(ofm_frags* f) {
 // ---------------------------------------------------------------------------
 // the batched eigensolver
 // ---------------------------------------------------------------------------
+// Steps per launch of the multi-step filter kernel for an even degree:
+// (3, n3) then (2, n2) with n3 even, so the filtered block ends in X.  Two
+// steps per launch is the default: three hold more registers and measured
+// slower on the 32^3 FP64 boxes (lower occupancy outweighs the bytes).
+static std::vector<std::pair<int, int>> multistep_plan(int degree,
+                                                       int max_steps) {
+  const int n3 = max_steps >= 3 ? 2 * (degree / 6) : 0;
+  return {{3, n3}, {2, (degree - 3 * n3) / 2}};
+}
+
 struct SolveCfg {
   double tol;
   int max_iter, degree;
@@ -182,7 +192,7 @@ struct SolveCfg {
   bool autotune;
   bool use_graph;
   bool resident;
-  bool fused;
+  int fused;   // 0: one step per launch, else the most steps per launch
 };
 
 template <typename T>
@@ -297,8 +307,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   // two filter steps per launch when every box of the sweep fits one
   // workgroup's plane
   const int vset = res ? 1 : 0;
-  const int ppt2 = cfg.fused && f->n_vt[vset] > 0
-                       ? k::stencil2_ppt((int)w, f->vt_plane[vset]) : 0;
+  const int ppt2 = cfg.fused >= 2 && f->n_vt[vset] > 0
+                       ? k::multistep_ppt((int)w, f->vt_plane[vset]) : 0;
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
     // filter work: unlocked vectors of the active fragments (strip launches
     // and on-chip filter separately)
@@ -324,14 +334,22 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
     }
     auto sweep = [&](bool timed_each) {
       if (ppt2 > 0 && !tuning) {
-        for (int step = 1; step < cfg.degree; step += 2) {
-          // y_{k-1}, y_{k-2} read (no y_{k-2} on the first pair), y_k and
-          // y_{k+1} written, V_j once per box
-          const double by = (step == 1 ? 3 * nb : 4 * nb) * w + npt * w;
-          k::apply_h2<T>(timed_each ? c : nullptr, f, X, P, f->d_vt[vset],
-                         f->n_vt[vset], ppt2, f->d_active, step, f->d_fs, by,
-                         64.0 * nb);
-        }
+        // y_{k-1}, y_{k-2} read (no y_{k-2} on the first launch), the last
+        // two iterates written, V_j once per box; a three-step launch leaves
+        // its last iterate in the other buffer, so they come in pairs and
+        // the filtered block ends in X
+        T* in = X;
+        T* pv = P;
+        int step = 1;
+        for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused))
+          for (int i = 0; i < count; ++i) {
+            const double by = (step == 1 ? 3 * nb : 4 * nb) * w + npt * w;
+            k::apply_hm<T>(timed_each ? c : nullptr, f, in, pv, f->d_vt[vset],
+                           f->n_vt[vset], ppt2, ns, f->d_active, step, f->d_fs,
+                           by, 32.0 * nb * ns);
+            if (ns % 2) std::swap(in, pv);
+            step += ns;
+          }
         return;
       }
       for (int step = 1; step <= cfg.degree; ++step) {
@@ -378,14 +396,17 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       double by = 0;
       int launches = cfg.degree;
       if (ppt2 > 0) {
-        launches = cfg.degree / 2;
-        for (int step = 1; step < cfg.degree; step += 2)
-          by += (step == 1 ? 3 * nb : 4 * nb) * w + npt * w;
+        launches = 0;
+        for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused)) {
+          (void)ns;
+          launches += count;
+        }
+        by = (3 * nb + npt) * w + (launches - 1) * (4 * nb + npt) * w;
       } else {
         for (int step = 1; step <= cfg.degree; ++step)
           by += (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
       }
-      Timed tm(c, ppt2 > 0 ? "stencil2" : "stencil", by,
+      Timed tm(c, ppt2 > 0 ? "multistep" : "stencil", by,
                32.0 * nb * cfg.degree, launches);
       OFM_HIP(hipGraphLaunch(sweep_exec, s));
     }
@@ -723,7 +744,8 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.autotune = !opts || opts->autotune >= 0;
     cfg.use_graph = !opts || opts->use_graph >= 0;
     cfg.resident = !opts || opts->resident >= 0;
-    cfg.fused = !opts || opts->fused >= 0;
+    cfg.fused = !opts || opts->fused == 0 ? 2
+                : opts->fused < 0 ? 0 : std::min(opts->fused, 3);
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,
                 "guard vectors are fixed when the fragments are built");

@@ -254,11 +254,12 @@ int stencil_ppt(int elem_bytes, int variant);
 std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
                                 int variant, int nvec_only, int only,
                                 bool skip_resident = false);
-// two Chebyshev steps per launch for boxes whose plane fits one workgroup
-int stencil2_ppt(int elem_bytes, int max_plane);
+// two or three Chebyshev steps per launch for boxes whose plane fits one
+// workgroup
+int multistep_ppt(int elem_bytes, int max_plane);
 template <typename T>
-void apply_h2(ofm_ctx* c, const ofm_frags* f, T* X, T* P, const int2* tiles,
-              int ntiles, int ppt, const int* active, int step,
+void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
+              int ntiles, int ppt, int ns, const int* active, int step,
               const FilterState* fs, double alg_bytes, double flops);
 // whole Chebyshev filter with the vector on chip (FP32, boxes <= 32^3)
 bool resident_eligible(int elem_bytes, const FragDev& d);

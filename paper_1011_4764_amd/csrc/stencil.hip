@@ -226,31 +226,35 @@ __global__ __launch_bounds__(WG) void k_apply_h(
 }
 
 // ---------------------------------------------------------------------------
-// two Chebyshev steps per launch (boxes whose xy plane fits one workgroup)
+// NS Chebyshev steps per launch (boxes whose xy plane fits one workgroup)
 // ---------------------------------------------------------------------------
 // One workgroup per (fragment, vector) owns the whole box and marches along
-// z computing y_k at plane t and y_{k+1} at plane t - 2 in the same pass:
-// y_{k-1} rides in a register window of planes t-2..t+2 (plus the prefetch
-// of t+3), its plane t is staged in LDS for the x/y neighbours; y_k is kept
-// in a register window of planes t-4..t and a ring of its last three planes
-// in LDS.  HBM sees y_{k-1} and y_{k-2} read once and y_k, y_{k+1} written
-// once per two steps (4 passes instead of 6).  y_k is written over y_{k-2}
-// (P) and y_{k+1} over y_{k-1} (X) after each point's last read, exactly as
-// the two single-step launches leave them.  Points are evaluated by
-// stencil_point in the same order as k_apply_h, so the results are
-// bit-identical to two single-step launches.
+// z.  At iteration t, stage s = 1..NS computes y_{k+s-1} at plane
+// t - 2(s-1) from the outputs of stage s-1: their z neighbours ride in a
+// register window of four planes plus the plane stage s-1 produced this
+// iteration, their x/y neighbours come from LDS (the input plane t for
+// stage 1, a ring of the last three planes of stage s-1 otherwise), and the
+// point two steps back is the oldest plane of stage s-2's window (the y_{k-2}
+// stream for stage 1).  HBM sees y_{k-1} and y_{k-2} read once and only the
+// last two iterates written, per NS steps: 4 passes instead of 3 NS.  An
+// iterate goes to the buffer of its parity (IN holds y_{k-1}, PV y_{k-2}),
+// after each point's last read there, exactly as single-step launches leave
+// it.  Points are evaluated by stencil_point in the same order as k_apply_h,
+// so the results are bit-identical to NS single-step launches.
 #ifndef OFM_H2_THREADS
 #define OFM_H2_THREADS 512
 #endif
-constexpr int H2T = OFM_H2_THREADS;   // threads of a two-step workgroup
+constexpr int H2T = OFM_H2_THREADS;   // threads of a multi-step workgroup
 
-template <typename T, int PPT>
-__global__ __launch_bounds__(H2T) void k_apply_h2(
+template <typename T, int PPT, int NS>
+__global__ __launch_bounds__(H2T) void k_apply_hm(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
-    int nblk_pad, const T* __restrict__ Vj, T* X, T* P,
+    int nblk_pad, const T* __restrict__ Vj, T* IN, T* PV,
     const FilterState* __restrict__ fs, const int* __restrict__ active,
     int step, double nh) {
+  static_assert(NS >= 2 && NS <= 3, "two or three steps per launch");
   constexpr int SP = PPT * H2T;
+  constexpr int NV = 2 * (NS - 1) + 1;   // V planes t - 2(NS-1) .. t
   const int t0 = xcd_tile(blockIdx.x, nblk_pad);
   if (t0 >= ntiles) return;
   const int j = tiles[t0].x, v = tiles[t0].y;
@@ -261,22 +265,24 @@ __global__ __launch_bounds__(H2T) void k_apply_h2(
   const int plane = nx * ny;
   if (plane > SP) return;       // the host launches only boxes that fit
   const long long base = fr.x_off + (long long)v * fr.ld;
-  T* xs = X + base;
-  T* ps = P + base;
+  T* in = IN + base;
+  T* pv = PV + base;
   const T* __restrict__ vv = Vj + fr.v_off;
-  const StepCoef<T> ka = step_coefs<T>(fs + j, step, 1, nh);
-  const StepCoef<T> kb = step_coefs<T>(fs + j, step + 1, 1, nh);
+  StepCoef<T> kc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) kc[s] = step_coefs<T>(fs + j, step + s, 1, nh);
   const bool use_prev = step > 1;
   const T tnh = (T)nh;
-  __shared__ T L1[2][SP];   // y_{k-1}, plane t (double-buffered)
-  __shared__ T L2[3][SP];   // y_k, planes t, t-1, t-2 (ring)
+  __shared__ T L0[2][SP];          // y_{k-1}, plane t (double-buffered)
+  __shared__ T R[NS - 1][3][SP];   // stage outputs, last three planes
   const int tid = threadIdx.x;
   int pp[PPT], px[PPT], py[PPT];
   bool ok[PPT];
-  T a0[PPT], a1[PPT], a2[PPT], a3[PPT], a4[PPT];   // y_{k-1}, t-2..t+2
-  T b0[PPT], b1[PPT], b2[PPT], b3[PPT];            // y_k, t-4..t-1
-  T w0[PPT], w1[PPT], w2[PPT];                     // V, t-2..t
-  T q[PPT];                                        // y_{k-2}, plane t
+  T W[NS][4][PPT];   // stage s outputs at planes n_s-4..n_s-1, n_s = t-2(s-1)
+                     // (stage 0: the input y_{k-1} at planes t-2..t+1)
+  T nw0[PPT];        // input plane t+2
+  T vq[NV][PPT];     // V at planes t-2(NS-1) .. t
+  T q[PPT];          // y_{k-2} at plane t
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int p = tid + k * H2T;
@@ -284,64 +290,43 @@ __global__ __launch_bounds__(H2T) void k_apply_h2(
     pp[k] = ok[k] ? p : 0;
     px[k] = pp[k] % nx;
     py[k] = pp[k] / nx;
-    a0[k] = a1[k] = 0;
-    a2[k] = ok[k] ? xs[pp[k]] : T(0);
-    a3[k] = (ok[k] && nz > 1) ? xs[plane + pp[k]] : T(0);
-    a4[k] = (ok[k] && nz > 2) ? xs[2 * plane + pp[k]] : T(0);
-    b0[k] = b1[k] = b2[k] = b3[k] = 0;
-    w0[k] = w1[k] = 0;
-    w2[k] = ok[k] ? vv[pp[k]] : T(0);
-    q[k] = (ok[k] && use_prev) ? ps[pp[k]] : T(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) W[s][i][k] = 0;
+    W[0][2][k] = ok[k] ? in[pp[k]] : T(0);
+    W[0][3][k] = (ok[k] && nz > 1) ? in[plane + pp[k]] : T(0);
+    nw0[k] = (ok[k] && nz > 2) ? in[2 * plane + pp[k]] : T(0);
+#pragma unroll
+    for (int i = 0; i < NV - 1; ++i) vq[i][k] = 0;
+    vq[NV - 1][k] = ok[k] ? vv[pp[k]] : T(0);
+    q[k] = (ok[k] && use_prev) ? pv[pp[k]] : T(0);
   }
-  for (int t = 0; t < nz + 2; ++t) {
+  for (int t = 0; t < nz + 2 * (NS - 1); ++t) {
     const int zoff = t * plane;
-    T an[PPT], wn[PPT], qn[PPT], b4[PPT];
+    T an[PPT], vn[PPT], qn[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      an[k] = (ok[k] && t + 3 < nz) ? xs[zoff + 3 * plane + pp[k]] : T(0);
-      wn[k] = (ok[k] && t + 1 < nz) ? vv[zoff + plane + pp[k]] : T(0);
+      an[k] = (ok[k] && t + 3 < nz) ? in[zoff + 3 * plane + pp[k]] : T(0);
+      vn[k] = (ok[k] && t + 1 < nz) ? vv[zoff + plane + pp[k]] : T(0);
       qn[k] = (ok[k] && use_prev && t + 1 < nz)
-                  ? __builtin_nontemporal_load(&ps[zoff + plane + pp[k]])
+                  ? __builtin_nontemporal_load(&pv[zoff + plane + pp[k]])
                   : T(0);
-      if (t < nz && ok[k]) L1[t & 1][pp[k]] = a2[k];
+      if (t < nz && ok[k]) L0[t & 1][pp[k]] = W[0][2][k];
     }
     __syncthreads();
-    // y_k at plane t
-    T* R = L2[t % 3];
+    T nw[NS + 1][PPT];   // nw[s]: stage s output at plane n_s
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      b4[k] = 0;
-      if (t < nz && ok[k]) {
-        const T* L = L1[t & 1];
-        const int li = pp[k], x = px[k], y = py[k];
-        const T xm1 = x >= 1 ? L[li - 1] : T(0);
-        const T xm2 = x >= 2 ? L[li - 2] : T(0);
-        const T xp1 = x + 1 < nx ? L[li + 1] : T(0);
-        const T xp2 = x + 2 < nx ? L[li + 2] : T(0);
-        const T ym1 = y >= 1 ? L[li - nx] : T(0);
-        const T ym2 = y >= 2 ? L[li - 2 * nx] : T(0);
-        const T yp1 = y + 1 < ny ? L[li + nx] : T(0);
-        const T yp2 = y + 2 < ny ? L[li + 2 * nx] : T(0);
-        const int nfaces = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) +
-                           (t == 0) + (t == nz - 1);
-        const T s1 = (xm1 + xp1) + (ym1 + yp1) + (a1[k] + a3[k]);
-        const T s2 = (xm2 + xp2) + (ym2 + yp2) + (a0[k] + a4[k]);
-        const T o = stencil_point<T>(a2[k], s1, s2,
-                                     point_diag<T>(tnh, nfaces, w2[k]), q[k],
-                                     ka);
-        __builtin_nontemporal_store(o, &ps[zoff + li]);
-        R[li] = o;
-        b4[k] = o;
-      }
-    }
-    // y_{k+1} at plane t - 2 (its y_k plane went to LDS two iterations ago,
-    // before the last two barriers)
-    if (t >= 2) {
-      const int z = t - 2;
-      const T* L = L2[z % 3];
+    for (int k = 0; k < PPT; ++k) nw[0][k] = nw0[k];
+#pragma unroll
+    for (int s = 1; s <= NS; ++s) {
+      const int z = t - 2 * (s - 1);
+      const bool live = z >= 0 && z < nz;
+      const T* L = s == 1 ? L0[t & 1] : R[s - 2][live ? z % 3 : 0];
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        if (!ok[k]) continue;
+        nw[s][k] = 0;
+        if (!live || !ok[k]) continue;
         const int li = pp[k], x = px[k], y = py[k];
         const T xm1 = x >= 1 ? L[li - 1] : T(0);
         const T xm2 = x >= 2 ? L[li - 2] : T(0);
@@ -353,35 +338,40 @@ __global__ __launch_bounds__(H2T) void k_apply_h2(
         const T yp2 = y + 2 < ny ? L[li + 2 * nx] : T(0);
         const int nfaces = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) +
                            (z == 0) + (z == nz - 1);
-        const T s1 = (xm1 + xp1) + (ym1 + yp1) + (b1[k] + b3[k]);
-        const T s2 = (xm2 + xp2) + (ym2 + yp2) + (b0[k] + b4[k]);
-        const T o = stencil_point<T>(b2[k], s1, s2,
-                                     point_diag<T>(tnh, nfaces, w0[k]), a0[k],
-                                     kb);
-        __builtin_nontemporal_store(o, &xs[z * plane + li]);
+        const T s1 = (xm1 + xp1) + (ym1 + yp1) + (W[s - 1][1][k] + W[s - 1][3][k]);
+        const T s2 = (xm2 + xp2) + (ym2 + yp2) + (W[s - 1][0][k] + nw[s - 1][k]);
+        const T pn = s == 1 ? q[k] : W[s >= 2 ? s - 2 : 0][0][k];
+        const T o = stencil_point<T>(
+            W[s - 1][2][k], s1, s2,
+            point_diag<T>(tnh, nfaces, vq[NV - 1 - 2 * (s - 1)][k]), pn,
+            kc[s - 1]);
+        if (s >= NS - 1)   // the last two iterates go to HBM
+          __builtin_nontemporal_store(o, &((s % 2 == 0) ? in : pv)[z * plane + li]);
+        if (s <= NS - 1) R[s - 1][z % 3][li] = o;
+        nw[s][k] = o;
       }
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      a0[k] = a1[k];
-      a1[k] = a2[k];
-      a2[k] = a3[k];
-      a3[k] = a4[k];
-      a4[k] = an[k];
-      b0[k] = b1[k];
-      b1[k] = b2[k];
-      b2[k] = b3[k];
-      b3[k] = b4[k];
-      w0[k] = w1[k];
-      w1[k] = w2[k];
-      w2[k] = wn[k];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        W[s][0][k] = W[s][1][k];
+        W[s][1][k] = W[s][2][k];
+        W[s][2][k] = W[s][3][k];
+        W[s][3][k] = nw[s][k];
+      }
+      nw0[k] = an[k];
+#pragma unroll
+      for (int i = 0; i < NV - 1; ++i) vq[i][k] = vq[i + 1][k];
+      vq[NV - 1][k] = vn[k];
       q[k] = qn[k];
     }
   }
 }
 
-// points per thread of the two-step kernel for a largest plane, 0 if none fits
-int stencil2_ppt(int elem_bytes, int max_plane) {
+// points per thread of the multi-step kernel for a largest plane, 0 if none
+// fits
+int multistep_ppt(int elem_bytes, int max_plane) {
   if (elem_bytes == 8)
     return max_plane <= H2T ? 1 : max_plane <= 2 * H2T ? 2
            : max_plane <= 4 * H2T ? 4 : 0;
@@ -390,8 +380,8 @@ int stencil2_ppt(int elem_bytes, int max_plane) {
 }
 
 template <typename T>
-void apply_h2(ofm_ctx* c, const ofm_frags* f, T* X, T* P, const int2* tiles,
-              int ntiles, int ppt, const int* active, int step,
+void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
+              int ntiles, int ppt, int ns, const int* active, int step,
               const FilterState* fs, double alg_bytes, double flops) {
   const T* Vj;
   if constexpr (sizeof(T) == 8)
@@ -400,29 +390,35 @@ void apply_h2(ofm_ctx* c, const ofm_frags* f, T* X, T* P, const int2* tiles,
     Vj = (const T*)f->d_vf32;
   const double nh = -0.5 / (f->grid.h * f->grid.h);
   const int nblk = pad8(ntiles);
-  Timed tm(c, "stencil2", alg_bytes, flops);
+  Timed tm(c, "multistep", alg_bytes, flops);
   hipStream_t stream = f->ctx->stream;
-#define LAUNCH2(PP)                                                          \
-  hipLaunchKernelGGL((k_apply_h2<T, PP>), dim3(nblk), dim3(H2T), 0, stream,  \
-                     f->d_frag, tiles, ntiles, nblk, Vj, X, P, fs, active,   \
-                     step, nh)
+#define LAUNCHM(PP, NSS)                                                     \
+  hipLaunchKernelGGL((k_apply_hm<T, PP, NSS>), dim3(nblk), dim3(H2T), 0,     \
+                     stream, f->d_frag, tiles, ntiles, nblk, Vj, IN, PV, fs, \
+                     active, step, nh)
+#define LAUNCHP(PP)                                                          \
+  do {                                                                       \
+    if (ns == 3) LAUNCHM(PP, 3);                                             \
+    else LAUNCHM(PP, 2);                                                     \
+  } while (0)
   if (ppt == 1) {
-    LAUNCH2(1);
+    LAUNCHP(1);
   } else if (ppt == 2) {
-    LAUNCH2(2);
+    LAUNCHP(2);
   } else if (ppt == 4) {
-    LAUNCH2(4);
+    LAUNCHP(4);
   } else {
-    if constexpr (sizeof(T) == 4) LAUNCH2(8);   // FP64 stops at 4
+    if constexpr (sizeof(T) == 4) LAUNCHP(8);   // FP64 stops at 4
   }
-#undef LAUNCH2
+#undef LAUNCHP
+#undef LAUNCHM
   OFM_HIP(hipGetLastError());
 }
-template void apply_h2<double>(ofm_ctx*, const ofm_frags*, double*, double*,
-                               const int2*, int, int, const int*, int,
+template void apply_hm<double>(ofm_ctx*, const ofm_frags*, double*, double*,
+                               const int2*, int, int, int, const int*, int,
                                const FilterState*, double, double);
-template void apply_h2<float>(ofm_ctx*, const ofm_frags*, float*, float*,
-                              const int2*, int, int, const int*, int,
+template void apply_hm<float>(ofm_ctx*, const ofm_frags*, float*, float*,
+                              const int2*, int, int, int, const int*, int,
                               const FilterState*, double, double);
 
 // ---------------------------------------------------------------------------

@@ -144,13 +144,13 @@ def _wells_system(seed):
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_resident_filter_bit_identical(mctx, seed):
-    """The on-chip whole-filter kernel and the two-steps-per-launch kernel
-    give the same bits as the one-step strip launches: eigenvalues,
-    iteration counts and states."""
+    """The on-chip whole-filter kernel and the multi-step kernel (two or
+    three steps per launch) give the same bits as the one-step strip
+    launches: eigenvalues, iteration counts and states."""
     s = _wells_system(seed)
     out = []
     for res, graph, fused in ((0, 0, 0), (-1, 0, 0), (-1, -1, 0),
-                              (-1, 0, -1), (0, 0, -1)):
+                              (-1, 0, -1), (0, 0, -1), (-1, 0, 3)):
         _say("resident", res, "graph", graph, "fused", fused, "seed", seed)
         f = _build(mctx, s)
         st, eps, it, cv = P.ofm_solve_fragments(mctx, f, resident=res,

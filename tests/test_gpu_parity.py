@@ -514,10 +514,10 @@ def test_widest_block_end_to_end(ctx):
 
 
 @pytest.mark.parametrize("case", ["tiny", "wide"])
-def test_fused_two_step_bit_identical(ctx, tiny0, case):
-    """Two filter steps per launch give the same bits as one step per
-    launch (eigenvalues, iteration counts, states), graph on and off; planes
-    of 144 points (one point per thread) and up to 1024 (four)."""
+def test_multistep_bit_identical(ctx, tiny0, case):
+    """Two or three filter steps per launch give the same bits as one step
+    per launch (eigenvalues, iteration counts, states), graph on and off;
+    planes of 144 points and up to 1024."""
     if case == "tiny":
         s = tiny0
     else:
@@ -527,7 +527,7 @@ def test_fused_two_step_bit_identical(ctx, tiny0, case):
         s = box_system(shape, 0.5, [(0, 0, 0), (16, 17, 1)],
                        [(32, 32, 10), (20, 15, 12)], [5, 4], V=V)
     out = []
-    for fused, graph in ((0, 0), (-1, 0), (0, -1)):
+    for fused, graph in ((0, 0), (-1, 0), (0, -1), (3, 0), (3, -1)):
         _say("fused", fused, "graph", graph, case)
         f = _build(ctx, s)
         st, eps, it, cv = P.ofm_solve_fragments(ctx, f, fused=fused,
