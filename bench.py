@@ -35,6 +35,8 @@ STENCIL_KERNELS = {
     "stencil": "k_apply_h (one Chebyshev filter step of H_j per launch)",
     "multistep": "k_apply_hm (two or three Chebyshev filter steps of H_j "
                  "per launch)",
+    "sweep": "filter sweep replayed as one graph: k_apply_hm on the boxes "
+             "whose plane fits it, k_apply_h on the others",
 }
 
 
@@ -205,6 +207,7 @@ def main():
             res[key] = stage_sum[key] / steps
         res["stencil"] = ctx.kernel_stats("stencil")
         res["multistep"] = ctx.kernel_stats("multistep")
+        res["sweep"] = ctx.kernel_stats("sweep")
         res["elements"] = ctx.kernel_stats("elements")
         res["gram"] = ctx.kernel_stats("gram")
         res["filter"] = ctx.kernel_stats("filter")
@@ -218,9 +221,9 @@ def main():
     el, gr = main_form["elements"], main_form["gram"]
     # the dominant stencil kernel: two filter steps per launch where every
     # plane fits one workgroup, else one step per launch
-    two = main_form["multistep"]["ms"] > main_form["stencil"]["ms"]
-    st = main_form["multistep" if two else "stencil"]
-    kname = STENCIL_KERNELS["multistep" if two else "stencil"]
+    fam = max(("stencil", "multistep", "sweep"), key=lambda k: main_form[k]["ms"])
+    st = main_form[fam]
+    kname = STENCIL_KERNELS[fam]
     avg_ms = st["ms"] / max(st["launches"], 1)
     bytes_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -263,7 +266,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(
-                f"{'multistep' if two else 'stencil'}_{args.config}_{args.precision}"),
+                f"{fam}_{args.config}_{args.precision}"),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + "
                             "WRITE_SIZE, copy-calibrated)",
             "launches": st["launches"], "avg_launch_ms": avg_ms,

@@ -165,6 +165,9 @@ void free_frags(ofm_frags* f) {
                   f->d_hphi, f->d_tiles[0], f->d_tiles[1], f->d_tiles[2],
                   f->d_ftiles, f->d_tiles_nr[0], f->d_tiles_nr[1],
                   f->d_tiles_nr[2], f->d_vt[0], f->d_vt[1],
+                  f->d_tiles_rest[0][0], f->d_tiles_rest[0][1],
+                  f->d_tiles_rest[0][2], f->d_tiles_rest[1][0],
+                  f->d_tiles_rest[1][1], f->d_tiles_rest[1][2],
                   f->d_stiles, f->d_rtiles, f->d_G,
                   f->d_Q, f->d_theta, f->d_res, f->d_res_partial, f->d_fs,
                   f->d_active, f->d_iters, f->d_conv, f->d_flags,
@@ -299,29 +302,37 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   cholqr();
   apply_plain();
   rayleigh_ritz();
-  // mixed form: boxes of at most 32^3 run the whole filter on chip
+  // mixed form: boxes of at most 32^3 run the whole filter on chip; boxes
+  // whose plane fits the multi-step kernel run two steps per launch; the
+  // rest one step per launch in strips
   const bool res = sizeof(T) == 4 && cfg.resident && f->n_ftiles > 0;
-  int2* const* sweep_tiles = res ? f->d_tiles_nr : f->d_tiles;
-  const int* sweep_n = res ? f->n_tiles_nr : f->n_tiles;
-  if (res && sweep_n[var] == 0) tuning = false;   // nothing left to tune
-  // two filter steps per launch when every box of the sweep fits one
-  // workgroup's plane
   const int vset = res ? 1 : 0;
   const int ppt2 = cfg.fused >= 2 && f->n_vt[vset] > 0
                        ? k::multistep_ppt((int)w, f->vt_plane[vset]) : 0;
+  int2* const* strip_tiles = ppt2 > 0 ? f->d_tiles_rest[vset]
+                             : res ? f->d_tiles_nr : f->d_tiles;
+  const int* strip_n = ppt2 > 0 ? f->n_tiles_rest[vset]
+                       : res ? f->n_tiles_nr : f->n_tiles;
+  // the autotuning sweep runs every non-resident box in strips
+  int2* const* tune_tiles = res ? f->d_tiles_nr : f->d_tiles;
+  const int* tune_n = res ? f->n_tiles_nr : f->n_tiles;
+  if (tune_n[var] == 0) tuning = false;   // nothing left to tune
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
-    // filter work: unlocked vectors of the active fragments (strip launches
-    // and on-chip filter separately)
-    double nb = 0, npt = 0, rnb = 0, rnpt = 0;
+    // filter work: unlocked vectors of the active fragments, per class
+    double snb = 0, snpt = 0, mnb = 0, mnpt = 0, rnb = 0, rnpt = 0;
     for (int j = 0; j < nf; ++j)
       if (act[j] && fsh[j].lock < f->host[j].bw) {
-        const double u = (double)f->host[j].npts * (f->host[j].bw - fsh[j].lock);
-        if (res && k::resident_eligible((int)w, f->host[j])) {
+        const FragDev& d = f->host[j];
+        const double u = (double)d.npts * (d.bw - fsh[j].lock);
+        if (res && k::resident_eligible((int)w, d)) {
           rnb += u;
-          rnpt += f->host[j].npts;
+          rnpt += d.npts;
+        } else if (ppt2 > 0 && !tuning && k::multistep_eligible((int)w, d)) {
+          mnb += u;
+          mnpt += d.npts;
         } else {
-          nb += u;
-          npt += f->host[j].npts;
+          snb += u;
+          snpt += d.npts;
         }
       }
     if (res && rnb > 0) {
@@ -332,8 +343,11 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                            f->d_fs, cfg.degree, (2 * rnb + rnpt) * w,
                            32.0 * rnb * cfg.degree);
     }
+    const bool use_ms = ppt2 > 0 && !tuning;
+    int2* const* st_tiles = tuning ? tune_tiles : strip_tiles;
+    const int* st_n = tuning ? tune_n : strip_n;
     auto sweep = [&](bool timed_each) {
-      if (ppt2 > 0 && !tuning) {
+      if (use_ms) {
         // y_{k-1}, y_{k-2} read (no y_{k-2} on the first launch), the last
         // two iterates written, V_j once per box; a three-step launch leaves
         // its last iterate in the other buffer, so they come in pairs and
@@ -343,21 +357,21 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         int step = 1;
         for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused))
           for (int i = 0; i < count; ++i) {
-            const double by = (step == 1 ? 3 * nb : 4 * nb) * w + npt * w;
+            const double by = (step == 1 ? 3 * mnb : 4 * mnb) * w + mnpt * w;
             k::apply_hm<T>(timed_each ? c : nullptr, f, in, pv, f->d_vt[vset],
                            f->n_vt[vset], ppt2, ns, f->d_active, step, f->d_fs,
-                           by, 32.0 * nb * ns);
+                           by, 32.0 * mnb * ns);
             if (ns % 2) std::swap(in, pv);
             step += ns;
           }
-        return;
       }
+      if (st_n[var] == 0) return;
       for (int step = 1; step <= cfg.degree; ++step) {
         const bool odd = step & 1;
         const T* in = odd ? X : P;
         const T* prev = odd ? P : X;
         T* out = odd ? P : X;
-        const double by = (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
+        const double by = (step == 1 ? 2 * snb : 3 * snb) * w + snpt * w;
         int sv = var;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tuning && step >= 2 && step < 8) {
@@ -365,12 +379,12 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
           e0 = tev[step - 2][0];
           e1 = tev[step - 2][1];
         }
-        k::apply_h<T>(timed_each ? c : nullptr, f, in, prev, out,
-                      sweep_tiles[sv], sweep_n[sv], sv, f->d_active, step,
-                      f->d_fs, 1, -1, by, 32.0 * nb, e0, e1);
+        k::apply_h<T>(timed_each ? c : nullptr, f, in, prev, out, st_tiles[sv],
+                      st_n[sv], sv, f->d_active, step, f->d_fs, 1, -1, by,
+                      32.0 * snb, e0, e1);
       }
     };
-    if (sweep_n[var] == 0) {
+    if (!use_ms && st_n[var] == 0) {
       // every box took the on-chip filter
     } else if (tuning || !cfg.use_graph) {
       sweep(true);
@@ -393,21 +407,25 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         (void)hipGraphDestroy(g);
         OFM_HIP(ie);
       }
+      // one event pair brackets the replayed sweep: it is booked under the
+      // kernel family that carries its work (a mix of both, "sweep")
       double by = 0;
-      int launches = cfg.degree;
-      if (ppt2 > 0) {
-        launches = 0;
+      int launches = 0;
+      if (use_ms) {
         for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused)) {
           (void)ns;
           launches += count;
         }
-        by = (3 * nb + npt) * w + (launches - 1) * (4 * nb + npt) * w;
-      } else {
-        for (int step = 1; step <= cfg.degree; ++step)
-          by += (step == 1 ? 2 * nb : 3 * nb) * w + npt * w;
+        by += (3 * mnb + mnpt) * w + (launches - 1) * (4 * mnb + mnpt) * w;
       }
-      Timed tm(c, ppt2 > 0 ? "multistep" : "stencil", by,
-               32.0 * nb * cfg.degree, launches);
+      if (st_n[var] > 0) {
+        launches += cfg.degree;
+        for (int step = 1; step <= cfg.degree; ++step)
+          by += (step == 1 ? 2 * snb : 3 * snb) * w + snpt * w;
+      }
+      const char* fam = !use_ms ? "stencil"
+                        : st_n[var] == 0 ? "multistep" : "sweep";
+      Timed tm(c, fam, by, 32.0 * (mnb + snb) * cfg.degree, launches);
       OFM_HIP(hipGraphLaunch(sweep_exec, s));
     }
     cholqr();
@@ -565,21 +583,34 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
       hipStream_t s = c->stream;
       const size_t w = wsize(c);
       f->d_frag = dev_alloc<FragDev>(n_frag);
-      for (int v = 0; v < k::NVARIANT; ++v) {
-        auto tv = k::stencil_tiles(f, (int)w, v, 0, -1);
-        f->n_tiles[v] = (int)tv.size();
-        f->d_tiles[v] = dev_alloc<int2>(tv.size());
-        OFM_HIP(hipMemcpyAsync(f->d_tiles[v], tv.data(), sizeof(int2) * tv.size(),
-                               hipMemcpyHostToDevice, s));
-        OFM_HIP(hipStreamSynchronize(s));
-        auto tn = k::stencil_tiles(f, (int)w, v, 0, -1, true);
-        f->n_tiles_nr[v] = (int)tn.size();
-        f->d_tiles_nr[v] = dev_alloc<int2>(tn.size());
-        if (!tn.empty())
-          OFM_HIP(hipMemcpyAsync(f->d_tiles_nr[v], tn.data(),
-                                 sizeof(int2) * tn.size(),
+      // fragment classes: on-chip filter (FP32, <= 32^3), multi-step,
+      // strips; the tile lists below cover each combination a solve uses
+      std::vector<char> nres(n_frag), rest0(n_frag), rest1(n_frag);
+      for (int j = 0; j < n_frag; ++j) {
+        const FragDev& d = f->host[j];
+        const bool r = k::resident_eligible((int)w, d);
+        const bool m = k::multistep_eligible((int)w, d);
+        nres[j] = !r;
+        rest0[j] = !m;
+        rest1[j] = !r && !m;
+      }
+      auto upload = [&](const std::vector<int2>& tv, int2*& dst, int& n) {
+        n = (int)tv.size();
+        dst = dev_alloc<int2>(tv.size());
+        if (!tv.empty())
+          OFM_HIP(hipMemcpyAsync(dst, tv.data(), sizeof(int2) * tv.size(),
                                  hipMemcpyHostToDevice, s));
         OFM_HIP(hipStreamSynchronize(s));
+      };
+      for (int v = 0; v < k::NVARIANT; ++v) {
+        upload(k::stencil_tiles(f, (int)w, v, 0, -1), f->d_tiles[v],
+               f->n_tiles[v]);
+        upload(k::stencil_tiles(f, (int)w, v, 0, -1, &nres), f->d_tiles_nr[v],
+               f->n_tiles_nr[v]);
+        upload(k::stencil_tiles(f, (int)w, v, 0, -1, &rest0),
+               f->d_tiles_rest[0][v], f->n_tiles_rest[0][v]);
+        upload(k::stencil_tiles(f, (int)w, v, 0, -1, &rest1),
+               f->d_tiles_rest[1][v], f->n_tiles_rest[1][v]);
       }
       for (int set = 0; set < 2; ++set) {
         std::vector<int2> vt;
@@ -587,16 +618,12 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
         for (int j = 0; j < n_frag; ++j) {
           const FragDev& d = f->host[j];
           if (set == 1 && k::resident_eligible((int)w, d)) continue;
+          if (!k::multistep_eligible((int)w, d)) continue;
           mp = std::max(mp, d.dims[0] * d.dims[1]);
           for (int v = 0; v < d.bw; ++v) vt.push_back(make_int2(j, v));
         }
-        f->n_vt[set] = (int)vt.size();
         f->vt_plane[set] = mp;
-        f->d_vt[set] = dev_alloc<int2>(vt.size());
-        if (!vt.empty())
-          OFM_HIP(hipMemcpyAsync(f->d_vt[set], vt.data(), sizeof(int2) * vt.size(),
-                                 hipMemcpyHostToDevice, s));
-        OFM_HIP(hipStreamSynchronize(s));
+        upload(vt, f->d_vt[set], f->n_vt[set]);
       }
       {
         std::vector<int2> ft;

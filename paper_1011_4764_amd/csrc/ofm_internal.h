@@ -133,11 +133,16 @@ struct ofm_frags {
   int n_ftiles = 0;
   int2* d_tiles_nr[3] = {nullptr, nullptr, nullptr};
   int n_tiles_nr[3] = {0, 0, 0};
-  // (fragment, vector) tiles of the two-step kernel: every fragment [0], the
-  // fragments the on-chip filter does not take [1]; largest plane of each
+  // multi-step kernel: (fragment, vector) tiles of the boxes it takes, with
+  // the on-chip filter off [0] or on [1] (then it takes none of those), the
+  // largest plane of each set, and the strip tiles of the remaining boxes
+  // per stencil variant
   int2* d_vt[2] = {nullptr, nullptr};
   int n_vt[2] = {0, 0};
   int vt_plane[2] = {0, 0};
+  int2* d_tiles_rest[2][3] = {{nullptr, nullptr, nullptr},
+                              {nullptr, nullptr, nullptr}};
+  int n_tiles_rest[2][3] = {{0, 0, 0}, {0, 0, 0}};
   int variant = -1;            // stencil variant in use (-1: not chosen)
   int2* d_stiles = nullptr;
   int n_stiles = 0;
@@ -251,12 +256,14 @@ void init_random(hipStream_t s, const ofm_frags* f, T* X,
                  unsigned long long seed);
 constexpr int NVARIANT = 3;   // stencil variants (points per thread)
 int stencil_ppt(int elem_bytes, int variant);
+// strip tiles of the fragments with keep[j] (every fragment without keep)
 std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
                                 int variant, int nvec_only, int only,
-                                bool skip_resident = false);
+                                const std::vector<char>* keep = nullptr);
 // two or three Chebyshev steps per launch for boxes whose plane fits one
 // workgroup
 int multistep_ppt(int elem_bytes, int max_plane);
+bool multistep_eligible(int elem_bytes, const FragDev& d);
 template <typename T>
 void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
               int ntiles, int ppt, int ns, const int* active, int step,

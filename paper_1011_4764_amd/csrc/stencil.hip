@@ -369,6 +369,13 @@ __global__ __launch_bounds__(H2T) void k_apply_hm(
   }
 }
 
+// boxes the multi-step kernel takes: planes that fit at most 2 points per
+// thread in FP64 and 4 in FP32 (beyond that its register windows cost more
+// occupancy than the saved passes are worth, measured)
+bool multistep_eligible(int elem_bytes, const FragDev& d) {
+  return d.dims[0] * d.dims[1] <= (elem_bytes == 8 ? 2 : 4) * H2T;
+}
+
 // points per thread of the multi-step kernel for a largest plane, 0 if none
 // fits
 int multistep_ppt(int elem_bytes, int max_plane) {
@@ -577,13 +584,13 @@ int stencil_ppt(int elem_bytes, int variant) {
 // vectors v < nvec(j) of every fragment (or of fragment `only` alone)
 std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
                                 int variant, int nvec_only, int only,
-                                bool skip_resident) {
+                                const std::vector<char>* keep) {
   const int sp = stencil_ppt(elem_bytes, variant) * WG;
   std::vector<int2> t;
   for (int j = 0; j < f->n_frag; ++j) {
     if (only >= 0 && j != only) continue;
     const FragDev& d = f->host[j];
-    if (skip_resident && resident_eligible(elem_bytes, d)) continue;
+    if (keep && !(*keep)[j]) continue;
     const int ns = (d.dims[0] * d.dims[1] + sp - 1) / sp;
     const int nv = nvec_only > 0 ? nvec_only : d.bw;
     for (int v = 0; v < nv; ++v)

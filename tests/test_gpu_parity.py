@@ -513,13 +513,21 @@ def test_widest_block_end_to_end(ctx):
     f.close()
 
 
-@pytest.mark.parametrize("case", ["tiny", "wide"])
+@pytest.mark.parametrize("case", ["tiny", "wide", "split"])
 def test_multistep_bit_identical(ctx, tiny0, case):
     """Two or three filter steps per launch give the same bits as one step
     per launch (eigenvalues, iteration counts, states), graph on and off;
     planes of 144 points and up to 1024."""
     if case == "tiny":
         s = tiny0
+    elif case == "split":
+        # a 40x30 plane (over the FP64 multi-step limit: strips) beside a
+        # 12x12 one (multi-step) in the same sweep
+        rng = np.random.default_rng(8)
+        shape = (44, 34, 16)
+        V = -np.abs(rng.standard_normal(shape[::-1])) * 0.3
+        s = box_system(shape, 0.5, [(0, 0, 0), (30, 20, 2)],
+                       [(40, 30, 6), (12, 12, 12)], [4, 5], V=V)
     else:
         rng = np.random.default_rng(7)
         shape = (40, 34, 14)
@@ -541,7 +549,7 @@ def test_multistep_bit_identical(ctx, tiny0, case):
         assert np.array_equal(it, out[0][1])
         for a, b in zip(phis, out[0][2]):
             assert np.array_equal(a, b)
-    if case == "wide":
+    if case != "tiny":
         r = O.run(s.potential(), 0.5, s.frag_lo, s.frag_dims, s.frag_states,
                   solve=False)
         assert np.abs(out[0][0] - np.concatenate(r.eps)).max() < 1e-8
