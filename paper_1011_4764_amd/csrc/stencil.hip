@@ -380,10 +380,8 @@ bool multistep_eligible(int elem_bytes, const FragDev& d) {
 // fits
 int multistep_ppt(int elem_bytes, int max_plane) {
   if (elem_bytes == 8)
-    return max_plane <= H2T ? 1 : max_plane <= 2 * H2T ? 2
-           : max_plane <= 4 * H2T ? 4 : 0;
-  return max_plane <= 2 * H2T ? 2 : max_plane <= 4 * H2T ? 4
-         : max_plane <= 8 * H2T ? 8 : 0;
+    return max_plane <= H2T ? 1 : max_plane <= 2 * H2T ? 2 : 0;
+  return max_plane <= 2 * H2T ? 2 : max_plane <= 4 * H2T ? 4 : 0;
 }
 
 template <typename T>
@@ -408,14 +406,13 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
     if (ns == 3) LAUNCHM(PP, 3);                                             \
     else LAUNCHM(PP, 2);                                                     \
   } while (0)
+  // the boxes it takes need at most 2 points per thread in FP64, 4 in FP32
   if (ppt == 1) {
     LAUNCHP(1);
   } else if (ppt == 2) {
     LAUNCHP(2);
   } else if (ppt == 4) {
-    LAUNCHP(4);
-  } else {
-    if constexpr (sizeof(T) == 4) LAUNCHP(8);   // FP64 stops at 4
+    if constexpr (sizeof(T) == 4) LAUNCHP(4);
   }
 #undef LAUNCHP
 #undef LAUNCHM
