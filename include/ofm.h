@@ -12,9 +12,9 @@
  *                              restricted to every box;
  *   2. ofm_solve_fragments  -- the lowest s_j eigenpairs of every fragment
  *                              Hamiltonian (one batched eigensolver for all
- *                              fragments) and H|phi> with the whole-system H
- *                              (Sec. II: "H of the whole system, not just the
- *                              fragment");
+ *                              fragments) and H|phi> with the Hamiltonian of
+ *                              the entire system, as the matrix elements
+ *                              need (Sec. II);
  *   3. ofm_matrix_elements  -- H_{ij,mn} = <phi_i^(j)|H|phi_m^(n)> and
  *                              S_{ij,mn} = <phi_i^(j)|phi_m^(n)> for every
  *                              overlapping pair (Sec. II);
