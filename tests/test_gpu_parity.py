@@ -553,3 +553,44 @@ def test_multistep_bit_identical(ctx, tiny0, case):
         r = O.run(s.potential(), 0.5, s.frag_lo, s.frag_dims, s.frag_states,
                   solve=False)
         assert np.abs(out[0][0] - np.concatenate(r.eps)).max() < 1e-8
+
+
+def test_more_error_paths(ctx, tiny0):
+    """Rejected inputs and states: every one returns its status, and the
+    context stays usable afterwards."""
+    s = tiny0
+    V = s.potential()
+    bad = [
+        ([[0, 0, 0]], [[12, 12, 12]], [65]),     # more than 64 states
+        ([[0, 0, 0]], [[12, 12, 12]], [0]),      # no states
+        ([[0, 0, 0]], [[2, 2, 2]], [9]),         # more states than points
+        ([[0, 0, 0]], [[0, 12, 12]], [1]),       # empty box
+    ]
+    for lo, dims, st in bad:
+        with pytest.raises(P.OfmError) as e:
+            P.ofm_build_fragments(ctx, (24, 12, 12), 0.5, V, lo, dims, st)
+        assert e.value.status == P.OFM_E_INVALID
+    big = np.zeros((4, 4, 130))
+    with pytest.raises(P.OfmError) as e:            # x extent above 128
+        P.ofm_build_fragments(ctx, (130, 4, 4), 0.5, big, [[0, 0, 0]],
+                              [[130, 4, 4]], [1])
+    assert e.value.status == P.OFM_E_INVALID
+    f = _build(ctx, s)
+    # the context refuses to go away while its fragments live
+    assert P.lib().ofm_destroy(ctx.handle) == P.OFM_E_STATE
+    with pytest.raises(P.OfmError) as e:
+        P.ofm_get_states(f, 0)                      # no states yet
+    assert e.value.status == P.OFM_E_STATE
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0
+    with pytest.raises(P.OfmError) as e:
+        P.ofm_get_states(f, s.n_frag)               # fragment out of range
+    assert e.value.status == P.OFM_E_INVALID
+    m = P.ofm_matrix_elements(ctx, f)
+    with pytest.raises(P.OfmError) as e:            # nothing reaches tau
+        P.ofm_solve_global(ctx, m, 1e30)
+    assert e.value.status == P.OFM_E_SINGULAR
+    g = P.ofm_solve_global(ctx, m, 1e-6)            # still usable
+    assert len(g["E"]) == s.n_basis
+    m.close()
+    f.close()
