@@ -281,6 +281,18 @@ ofm_status ofm_solve_global_subset(ofm_ctx* ctx, const ofm_mats* m,
                                    int* n_kept, int* n_eig, double* E,
                                    double* C, double* s_min);
 
+/* The dense FP64 symmetric eigensolver behind ofm_solve_global (it
+   diagonalises S and H' of the canonical orthogonalisation that solves
+   Eq. 2), for callers with a pencil of their own.  A: n*n doubles, host,
+   column-major, symmetric (both triangles are read; they should agree).
+   w: n doubles, host, the eigenvalues in ascending order.  Z: NULL, or n*n
+   doubles, host, column k the unit eigenvector of w[k] (each column's sign
+   is arbitrary).  Errors: OFM_E_INVALID for n < 1, n > 65536 or a NULL A or
+   w; OFM_E_DEVICE when the tridiagonal solver does not converge;
+   OFM_E_NOMEM. */
+ofm_status ofm_dense_eigh(ofm_ctx* ctx, int n, const double* A, double* w,
+                          double* Z);
+
 /* e_j = <HOMO_j|H|HOMO_j> with the whole-system H for every fragment, read
    from the diagonal blocks of m (n_frag doubles, host). */
 ofm_status ofm_homo_energies(const ofm_mats* m, double* e);

@@ -1158,6 +1158,19 @@ ofm_status ofm_select_homo(const ofm_frags* f, int n_max, double gap_min,
   });
 }
 
+ofm_status ofm_dense_eigh(ofm_ctx* c, int n, const double* A, double* w,
+                          double* Z) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(A && w, OFM_E_INVALID, "A and w are required");
+    OFM_REQUIRE(n >= 1 && n <= 65536, OFM_E_INVALID,
+                "n outside the dense solver's range [1, 65536]");
+    use_device(c);
+    dense_eigh_host(c, n, A, w, Z);
+    return OFM_OK;
+  });
+}
+
 ofm_status ofm_homo_energies(const ofm_mats* m, double* e) {
   if (!m) return OFM_E_INVALID;
   ofm_ctx* c = m->ctx;

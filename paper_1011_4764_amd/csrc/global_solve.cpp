@@ -1,13 +1,15 @@
 // Generalised eigenproblem sum_mn (H - E S) C = 0 in the fragment basis
 // (method Eq. 2), FP64 on the GPU by thresholded canonical
 // orthogonalisation:
-//   S = U diag(s) U^T            (rocSOLVER dsyevd)
+//   S = U diag(s) U^T            (dense_eigh: own tridiagonal reduction,
+//                                 rocSOLVER stedc and ormtr)
 //   K = { k : s_k >= s_thresh }  (directions of S below the threshold are
 //                                 linearly dependent combinations of
 //                                 overlapping fragment states and are dropped)
 //   X = U_K diag(s_K^-1/2)       (own kernel)
 //   H' = X^T H X                 (two rocBLAS dgemm)
-//   H' = Y diag(E) Y^T           (rocSOLVER dsyevd), C = X Y
+//   H' = Y diag(E) Y^T           (dense_eigh; rocSOLVER sterf without
+//                                 vectors), C = X Y
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -79,6 +81,21 @@ __global__ void k_scale_cols(const double* __restrict__ U,
   }
 }
 
+// A = (A + A^T) / 2 for the K x K product X^T H X, whose two triangles
+// differ by rounding
+__global__ void k_symmetrize(double* __restrict__ A, int K) {
+  const long long total = (long long)K * K;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % K), c = (int)(e / K);
+    if (r < c) {
+      const double m = 0.5 * (A[e] + A[c + (long long)r * K]);
+      A[e] = m;
+      A[c + (long long)r * K] = m;
+    }
+  }
+}
+
 rocblas_handle blas(ofm_ctx* c) {
   if (!c->blas) {
     rocblas_handle h;
@@ -89,15 +106,6 @@ rocblas_handle blas(ofm_ctx* c) {
   OFM_BLAS(rocblas_set_stream(h, c->stream));
   return h;
 }
-
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  explicit DevBuf(size_t n) { p = dev_alloc<T>(n); }
-  ~DevBuf() { dev_free(p); }
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-};
 
 }  // namespace
 
@@ -136,6 +144,26 @@ void homo_energies(const ofm_mats* m, double* e) {
   OFM_HIP(hipStreamSynchronize(st));
 }
 
+void dense_eigh_host(ofm_ctx* c, int n, const double* A, double* w,
+                     double* Z) {
+  hipStream_t st = c->stream;
+  rocblas_handle h = blas(c);
+  const long long nn = (long long)n * n;
+  DevBuf<double> Ad(nn), wd(n), Zd(Z ? nn : 1);
+  DevBuf<int> info(1);
+  OFM_HIP(hipMemcpyAsync(Ad.p, A, sizeof(double) * nn, hipMemcpyHostToDevice,
+                         st));
+  dense_eigh(st, h, n, Ad.p, wd.p, Z ? Zd.p : nullptr, info.p);
+  int info_h = 0;
+  OFM_HIP(hipMemcpyAsync(&info_h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  OFM_HIP(hipMemcpyAsync(w, wd.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  if (Z)
+    OFM_HIP(hipMemcpyAsync(Z, Zd.p, sizeof(double) * nn, hipMemcpyDeviceToHost,
+                           st));
+  OFM_HIP(hipStreamSynchronize(st));
+  OFM_REQUIRE(info_h == 0, OFM_E_DEVICE, "the tridiagonal eigensolver did not converge");
+}
+
 void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
                   double e_hi, int* n_kept, int* n_eig, double* E, double* C,
                   double* s_min, const unsigned char* keep) {
@@ -151,7 +179,7 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
   rocblas_handle h = blas(c);
   const int np = (int)m->pair_j.size();
   const int nf = (int)m->states.size();
-  DevBuf<double> H(N * N), S(N * N), s(N), work(N);
+  DevBuf<double> H(N * N), S(N * N), U(N * N), s(N);
   DevBuf<int> pj(np), pn(np), sts(nf), info(1);
   DevBuf<long long> boff(np), bas(nf), sel(m->n_basis);
   OFM_HIP(hipMemcpyAsync(sel.p, selh.data(), sizeof(long long) * m->n_basis,
@@ -173,16 +201,14 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
                      N);
   OFM_HIP(hipGetLastError());
   // eig(S), ascending
-  OFM_BLAS(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper,
-                            (rocblas_int)N, S.p, (rocblas_int)N, s.p, work.p,
-                            info.p));
+  dense_eigh(st, h, (int)N, S.p, s.p, U.p, info.p);
   std::vector<double> sh(N);
   int info_h = 0;
   OFM_HIP(hipMemcpyAsync(sh.data(), s.p, sizeof(double) * N,
                          hipMemcpyDeviceToHost, st));
   OFM_HIP(hipMemcpyAsync(&info_h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   OFM_HIP(hipStreamSynchronize(st));
-  OFM_REQUIRE(info_h == 0, OFM_E_DEVICE, "dsyevd(S) did not converge");
+  OFM_REQUIRE(info_h == 0, OFM_E_DEVICE, "eig(S) did not converge");
   long long first = 0;
   while (first < N && !(sh[first] >= s_thresh)) ++first;
   const int K = (int)(N - first);
@@ -193,8 +219,8 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
   }
   if (s_min) *s_min = sh[first];
   DevBuf<double> X(N * (long long)K), T1(N * (long long)K), Hp((long long)K * K),
-      E_d(K), work2(K);
-  hipLaunchKernelGGL(k_scale_cols, dim3(1024), dim3(256), 0, st, S.p, s.p, X.p,
+      E_d(K);
+  hipLaunchKernelGGL(k_scale_cols, dim3(1024), dim3(256), 0, st, U.p, s.p, X.p,
                      N, (int)first, K);
   OFM_HIP(hipGetLastError());
   const double one = 1.0, zero = 0.0;
@@ -206,15 +232,17 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
   OFM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none,
                          K, K, (rocblas_int)N, &one, X.p, (rocblas_int)N, T1.p,
                          (rocblas_int)N, &zero, Hp.p, K));
-  OFM_BLAS(rocsolver_dsyevd(h, C ? rocblas_evect_original : rocblas_evect_none,
-                            rocblas_fill_upper, K, Hp.p, K, E_d.p, work2.p,
-                            info.p));
+  hipLaunchKernelGGL(k_symmetrize, dim3(1024), dim3(256), 0, st, Hp.p, K);
+  OFM_HIP(hipGetLastError());
+  // the eigenvectors of H' replace U (no longer needed) when asked for
+  double* Y = C ? U.p : nullptr;
+  dense_eigh(st, h, K, Hp.p, E_d.p, Y, info.p);
   std::vector<double> Eh(K);
   OFM_HIP(hipMemcpyAsync(Eh.data(), E_d.p, sizeof(double) * K,
                          hipMemcpyDeviceToHost, st));
   OFM_HIP(hipMemcpyAsync(&info_h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   OFM_HIP(hipStreamSynchronize(st));
-  OFM_REQUIRE(info_h == 0, OFM_E_DEVICE, "dsyevd(H') did not converge");
+  OFM_REQUIRE(info_h == 0, OFM_E_DEVICE, "eig(H') did not converge");
   int lo = 0;
   while (lo < K && !(Eh[lo] >= e_lo)) ++lo;
   int hi = lo;
@@ -227,7 +255,7 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
     DevBuf<double> Cd(N * (long long)ne);
     OFM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none,
                            (rocblas_int)N, ne, K, &one, X.p, (rocblas_int)N,
-                           Hp.p + (long long)lo * K, K, &zero, Cd.p,
+                           Y + (long long)lo * K, K, &zero, Cd.p,
                            (rocblas_int)N));
     OFM_HIP(hipMemcpyAsync(C, Cd.p, sizeof(double) * N * ne,
                            hipMemcpyDeviceToHost, st));

@@ -216,6 +216,16 @@ inline void dev_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// device buffer freed with its scope
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  explicit DevBuf(size_t n) { p = dev_alloc<T>(n); }
+  ~DevBuf() { dev_free(p); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
 // timed-launch bracket (no-op unless profiling is on)
 struct Timed {
   ofm_ctx* c;
@@ -242,6 +252,14 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
                   double e_hi, int* n_kept, int* n_eig, double* E, double* C,
                   double* s_min, const unsigned char* keep = nullptr);
 void homo_energies(const ofm_mats* m, double* e);
+// dense symmetric eigensolver (tridiag.hip): eigenvalues of the n x n
+// symmetric A (full storage, column-major, leading dimension n; destroyed)
+// in ascending order into w; with Z != nullptr the orthonormal eigenvectors
+// into Z (n x n, leading dimension n).  info (device) is 0 on success.
+void dense_eigh(hipStream_t s, void* blas_handle, int n, double* A, double* w,
+                double* Z, int* info);
+// the same on host arrays, on the context's stream
+void dense_eigh_host(ofm_ctx* c, int n, const double* A, double* w, double* Z);
 void destroy_blas(ofm_ctx* c);
 
 // kernel launchers (kernels.hip)

@@ -34,6 +34,7 @@ EXPORTS = [
     "ofm_kernel_stats", "ofm_reset_stats", "ofm_stage_times",
     "ofm_set_stencil_variant", "ofm_set_fragment_wells", "ofm_select_homo",
     "ofm_solve_global_subset", "ofm_homo_energies", "ofm_homo_lumo_gap",
+    "ofm_dense_eigh",
 ]
 
 
@@ -116,6 +117,7 @@ def lib():
                                          C.c_double, _I, _I, _D, _D, _D],
                                         C.c_int),
             "ofm_homo_energies": ([_P, _D], C.c_int),
+            "ofm_dense_eigh": ([_P, C.c_int, _D, _D, _D], C.c_int),
             "ofm_homo_lumo_gap": ([_D, C.c_int, C.c_double, C.c_double, _I,
                                    _D, _D], C.c_int),
         }
@@ -448,6 +450,20 @@ def ofm_homo_energies(m: Mats):
     e = np.zeros(m.frags.n_frag)
     _check(lib().ofm_homo_energies(m.handle, _dp(e)), m.ctx.handle)
     return e
+
+
+def ofm_dense_eigh(ctx: Context, A, want_vectors=False):
+    """Eigenvalues (ascending) of the symmetric A, and with want_vectors the
+    unit eigenvectors as the columns of Z: (w, Z or None)."""
+    Af = np.asfortranarray(A, dtype=np.float64)
+    if Af.ndim != 2 or Af.shape[0] != Af.shape[1]:
+        raise ValueError("A must be square")
+    n = Af.shape[0]
+    w = np.zeros(n)
+    Z = np.zeros((n, n), order="F") if want_vectors else None
+    _check(lib().ofm_dense_eigh(ctx.handle, n, _dp(Af), _dp(w),
+                                None if Z is None else _dp(Z)), ctx.handle)
+    return w, Z
 
 
 def ofm_homo_lumo_gap(E, e_ref, gap_min):
