@@ -34,9 +34,31 @@ namespace {
 constexpr int NB = 32;     // panel width
 constexpr int TPB = 1024;  // threads of the column kernels
 
+// one DPP step on both halves of a double
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf,
+                                             true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the wave, the same value (and the same rounding) in every lane:
+// quad swaps and row rotations by DPP, then the four rows' sums in order
 __device__ __forceinline__ double wave_sum_d(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_d<0xb1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4e>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);   // row_ror:4
+  v += dpp_d<0x128>(v);   // row_ror:8
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
 // sum over a workgroup of NW waves, returned to every thread
@@ -90,6 +112,10 @@ __global__ __launch_bounds__(MV) void k_mv(
   const double* c = A + (long long)i * lda;   // indexed by row
   const int wave = blockIdx.x * (MV / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  // the reflector's inputs, loaded with the columns
+  double ss = 0;
+  for (int k = threadIdx.x; k < np; k += MV) ss += part[k];
+  const double alpha = c[i + 1], cii = c[i];
   double s1 = 0, sr = 0, cy = 0;   // x(i+1), sum_{r>=i+2} x(r) c(r), c(ycol)
   int ycol = -1;
   if (wave < L + 2 * il) {
@@ -139,10 +165,7 @@ __global__ __launch_bounds__(MV) void k_mv(
     s1 = wave_sum_d(s1);
     sr = wave_sum_d(sr);
   }
-  double ss = 0;
-  for (int k = threadIdx.x; k < np; k += MV) ss += part[k];
   const double xn2 = block_sum<MV / 64>(ss, red);
-  const double alpha = c[i + 1];
   double t = 0, beta = alpha, scale = 1;
   if (xn2 > 0) {
     beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -150,7 +173,7 @@ __global__ __launch_bounds__(MV) void k_mv(
     scale = 1.0 / (alpha - beta);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    D[i] = c[i];
+    D[i] = cii;
     E[i] = beta;
     tau[i] = t;
     sc[i] = scale;
