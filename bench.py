@@ -211,6 +211,7 @@ def main():
         res["elements"] = ctx.kernel_stats("elements")
         res["gram"] = ctx.kernel_stats("gram")
         res["filter"] = ctx.kernel_stats("filter")
+        res["tridiag"] = ctx.kernel_stats("tridiag")
         ctx.close()
         return res
 
@@ -218,7 +219,7 @@ def main():
                          True)
     last = main_form["last"]
     ms_step = main_form["ms_step"]
-    el, gr = main_form["elements"], main_form["gram"]
+    el, gr, td = main_form["elements"], main_form["gram"], main_form["tridiag"]
     # the dominant stencil kernel: two filter steps per launch where every
     # plane fits one workgroup, else one step per launch
     fam = max(("stencil", "multistep", "sweep"), key=lambda k: main_form[k]["ms"])
@@ -277,6 +278,14 @@ def main():
                      "avg_ms": gr["ms"] / max(gr["launches"], 1),
                      "GBps": (gr["bytes"] / gr["ms"] / 1e6) if gr["ms"] else 0,
                      "TFLOPs": (gr["flops"] / gr["ms"] / 1e9) if gr["ms"] else 0},
+            "tridiag": {"kernel": "k_mv + k_fin (Householder tridiagonal "
+                                  "reduction of the global solve)",
+                        "reductions": td["launches"],
+                        "avg_ms": td["ms"] / max(td["launches"], 1),
+                        "alg_bytes": td["bytes"] / max(td["launches"], 1),
+                        "GBps": (td["bytes"] / td["ms"] / 1e6) if td["ms"] else 0,
+                        "frac_hbm": ((td["bytes"] / td["ms"] / 1e6) / HBM_PEAK_GBS)
+                                    if td["ms"] else 0},
             "elements": {"launches": el["launches"],
                          "avg_ms": el["ms"] / max(el["launches"], 1),
                          "GBps": (el["bytes"] / el["ms"] / 1e6) if el["ms"] else 0,

@@ -316,9 +316,12 @@ ofm_status ofm_set_profiling(ofm_ctx* ctx, int on);
 /* Accumulated timing of one kernel family since the last reset: "stencil"
    (one fragment-Hamiltonian step per launch), "multistep" (two or three
    filter steps per launch), "filter" (whole filter with the vector on chip), "gram"
-   (subspace contractions), "elements" (pair contractions), "rotate".  total_ms is the sum of
-   launch durations, alg_bytes the algorithmic HBM bytes of those launches
-   (inputs read once, outputs written once), flops their useful flops. */
+   (subspace contractions), "elements" (pair contractions), "rotate",
+   "tridiag" (one whole tridiagonal reduction of the dense eigensolver per
+   entry; its bytes are the trailing-matrix stream of its column products).
+   total_ms is the sum of launch durations, alg_bytes the algorithmic HBM
+   bytes of those launches (inputs read once, outputs written once), flops
+   their useful flops. */
 ofm_status ofm_kernel_stats(ofm_ctx* ctx, const char* family,
                             long long* launches, double* total_ms,
                             double* alg_bytes, double* flops);

@@ -153,7 +153,7 @@ void dense_eigh_host(ofm_ctx* c, int n, const double* A, double* w,
   DevBuf<int> info(1);
   OFM_HIP(hipMemcpyAsync(Ad.p, A, sizeof(double) * nn, hipMemcpyHostToDevice,
                          st));
-  dense_eigh(st, h, n, Ad.p, wd.p, Z ? Zd.p : nullptr, info.p);
+  dense_eigh(c, st, h, n, Ad.p, wd.p, Z ? Zd.p : nullptr, info.p);
   int info_h = 0;
   OFM_HIP(hipMemcpyAsync(&info_h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   OFM_HIP(hipMemcpyAsync(w, wd.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
@@ -201,7 +201,7 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
                      N);
   OFM_HIP(hipGetLastError());
   // eig(S), ascending
-  dense_eigh(st, h, (int)N, S.p, s.p, U.p, info.p);
+  dense_eigh(c, st, h, (int)N, S.p, s.p, U.p, info.p);
   std::vector<double> sh(N);
   int info_h = 0;
   OFM_HIP(hipMemcpyAsync(sh.data(), s.p, sizeof(double) * N,
@@ -236,7 +236,7 @@ void global_solve(ofm_ctx* c, const ofm_mats* m, double s_thresh, double e_lo,
   OFM_HIP(hipGetLastError());
   // the eigenvectors of H' replace U (no longer needed) when asked for
   double* Y = C ? U.p : nullptr;
-  dense_eigh(st, h, K, Hp.p, E_d.p, Y, info.p);
+  dense_eigh(c, st, h, K, Hp.p, E_d.p, Y, info.p);
   std::vector<double> Eh(K);
   OFM_HIP(hipMemcpyAsync(Eh.data(), E_d.p, sizeof(double) * K,
                          hipMemcpyDeviceToHost, st));

@@ -256,8 +256,9 @@ void homo_energies(const ofm_mats* m, double* e);
 // symmetric A (full storage, column-major, leading dimension n; destroyed)
 // in ascending order into w; with Z != nullptr the orthonormal eigenvectors
 // into Z (n x n, leading dimension n).  info (device) is 0 on success.
-void dense_eigh(hipStream_t s, void* blas_handle, int n, double* A, double* w,
-                double* Z, int* info);
+// c (may be null) receives the "tridiag" kernel statistics.
+void dense_eigh(ofm_ctx* c, hipStream_t s, void* blas_handle, int n, double* A,
+                double* w, double* Z, int* info);
 // the same on host arrays, on the context's stream
 void dense_eigh_host(ofm_ctx* c, int n, const double* A, double* w, double* Z);
 void destroy_blas(ofm_ctx* c);

@@ -473,8 +473,8 @@ void sytrd_lower(hipStream_t s, rocblas_handle h, int n, double* A,
 
 }  // namespace
 
-void dense_eigh(hipStream_t s, void* blas_handle, int n, double* A, double* w,
-                double* Z, int* info) {
+void dense_eigh(ofm_ctx* c, hipStream_t s, void* blas_handle, int n, double* A,
+                double* w, double* Z, int* info) {
   OFM_REQUIRE(n >= 1, OFM_E_INVALID, "empty matrix");
   rocblas_handle h = static_cast<rocblas_handle>(blas_handle);
   if (n == 1) {
@@ -494,7 +494,17 @@ void dense_eigh(hipStream_t s, void* blas_handle, int n, double* A, double* w,
   DevBuf<double> Ap((size_t)ldp * n), E(n), tau(n);
   hipLaunchKernelGGL(k_pad_copy, dim3(2048), dim3(256), 0, s, A, n, Ap.p, ldp);
   OFM_HIP(hipGetLastError());
-  sytrd_lower(s, h, n, Ap.p, ldp, w, E.p, tau.p);
+  {
+    // the reduction streams the trailing matrix once per column (k_mv):
+    // sum over columns of 8 L (L + 2 il) bytes, L = n - i - 1
+    double bytes = 0;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double L = n - i - 1;
+      bytes += 8.0 * L * (L + 2.0 * (i % NB));
+    }
+    Timed tm(c, "tridiag", bytes, bytes / 4.0);
+    sytrd_lower(s, h, n, Ap.p, ldp, w, E.p, tau.p);
+  }
   if (!Z) {
     DevBuf<double> D(n), E2(n), gb(3);
     OFM_HIP(hipMemcpyAsync(D.p, w, sizeof(double) * n, hipMemcpyDeviceToDevice,
