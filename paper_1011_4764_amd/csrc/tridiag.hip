@@ -96,7 +96,7 @@ constexpr int MU = 4;     // double2 loads in flight per lane in k_mv
 // 0..L-1 form y(k) = A22(:, k) . v, waves L..L+il-1 u1 = W(i+1:n, 0:il)^T v,
 // the next il waves u2 = V(i+1:n, 0:il)^T v, each as x(i+1) + scale
 // sum_{r>=i+2} x(r) c(r), so that the loads do not wait for the reflector.
-// Each workgroup then sums the np partial norms of c(i+2:n) and builds the
+// Each wave then sums the np partial norms of c(i+2:n) and builds the
 // reflector (beta, tau, scale = 1/(c(i+1) - beta)); pm gets each
 // workgroup's share of y . v.
 // Storage: lda and ldw even and at least n rounded up to even, rows n.. of
@@ -112,9 +112,11 @@ __global__ __launch_bounds__(MV) void k_mv(
   const double* c = A + (long long)i * lda;   // indexed by row
   const int wave = blockIdx.x * (MV / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // the reflector's inputs, loaded with the columns
+  // the reflector's inputs, loaded with the columns; every wave sums the
+  // partial norms itself (same order everywhere, so every wave of every
+  // workgroup gets the same value)
   double ss = 0;
-  for (int k = threadIdx.x; k < np; k += MV) ss += part[k];
+  for (int k = lane; k < np; k += 64) ss += part[k];
   const double alpha = c[i + 1], cii = c[i];
   double s1 = 0, sr = 0, cy = 0;   // x(i+1), sum_{r>=i+2} x(r) c(r), c(ycol)
   int ycol = -1;
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(MV) void k_mv(
     s1 = wave_sum_d(s1);
     sr = wave_sum_d(sr);
   }
-  const double xn2 = block_sum<MV / 64>(ss, red);
+  const double xn2 = wave_sum_d(ss);
   double t = 0, beta = alpha, scale = 1;
   if (xn2 > 0) {
     beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(256) void k_fin(
     double* A, long long lda, int n, int p, int il, int nb_panel, double* W,
     long long ldw, const double* tau, const double* sc, const double* y,
     const double* u, const double* pm, int gm, double* part) {
-  __shared__ double sw[4][64], scn[4][64], red[4];
+  __shared__ double sw[4][64], scn[4][64];
   const int i = p + il, piv = i + 1;
   const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool next = il + 1 < nb_panel;
@@ -274,9 +276,9 @@ __global__ __launch_bounds__(256) void k_fin(
       if (r >= i + 3) ssq = cr * cr;
     }
   }
-  if (next) {
-    const double bs = block_sum<4>(ssq, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+  if (next && g == 0) {   // only wave 0 holds rows
+    const double bs = wave_sum_d(ssq);
+    if (lane == 0) part[blockIdx.x] = bs;
   }
 }
 
