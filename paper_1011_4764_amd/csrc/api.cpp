@@ -563,7 +563,7 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
     auto* f = new ofm_frags;
     f->ctx = c;
     try {
-      plan_fragments(f, *grid, n_frag, frags, 8);
+      plan_fragments(f, *grid, n_frag, frags, OFM_GUARD_VECTORS);
       plan_pairs(f, atom_xyz, frag_atom_ptr, frag_atom_idx, d_cut);
       // tile lists
       std::vector<int2> stiles, rtiles;

@@ -12,6 +12,11 @@
 
 #include "ofm.h"
 
+// extra block vectors beyond s_j in the fragment eigensolver
+#ifndef OFM_GUARD_VECTORS
+#define OFM_GUARD_VECTORS 8
+#endif
+
 namespace ofm {
 
 // ---------------------------------------------------------------------------
@@ -104,7 +109,7 @@ struct ofm_frags {
   ofm_ctx* ctx = nullptr;
   ofm_grid grid{};
   int n_frag = 0;
-  int guard = 8;
+  int guard = OFM_GUARD_VECTORS;
   std::vector<ofm::FragDev> host;      // descriptors (host copy)
   std::vector<int> pair_j, pair_n;     // pair list j <= n
   std::vector<long long> block_off;    // packed block offsets
