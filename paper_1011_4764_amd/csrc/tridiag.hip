@@ -413,6 +413,44 @@ __global__ void k_restore(double* A, long long lda, int n, int p, int b,
 
 __global__ void k_zero_u32(unsigned int* x) { *x = 0; }
 
+constexpr int QB = 128;   // reflectors per block when Q is applied
+
+// Vb (m x nb, leading dimension m) = the reflectors j0 .. j0+nb-1 as
+// explicit columns over rows j0+1 .. n-1: zero above the unit element, 1 at
+// row i+1, A(r, i) below it; a reflector with tau = 0 (the identity) is a
+// zero column.
+__global__ void k_build_v(const double* __restrict__ A, long long lda, int n,
+                          int j0, int nb, const double* __restrict__ tau,
+                          double* __restrict__ Vb) {
+  const int m = n - 1 - j0;
+  const long long total = (long long)m * nb;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       e < total; e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % m), q = (int)(e / m);
+    const int row = j0 + 1 + r, i = j0 + q;
+    double v = 0.0;
+    if (tau[i] != 0.0)
+      v = row < i + 1 ? 0.0 : (row == i + 1 ? 1.0 : A[row + (long long)i * lda]);
+    Vb[e] = v;
+  }
+}
+
+// T^{-1} of the block's compact WY form H_j0 ... H_j0+nb-1 = I - V T V^T:
+// diag(1 / tau) + the strict upper triangle of G = V^T V (Joffrain et al.,
+// "Accumulating Householder transformations, revisited", the UT transform);
+// an identity reflector (tau = 0, zero column) takes 1 on the diagonal.
+__global__ void k_build_tinv(const double* __restrict__ G, int nb,
+                             const double* __restrict__ tau, int j0,
+                             double* __restrict__ Ti) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb * nb;
+       e += gridDim.x * blockDim.x) {
+    const int i = e % nb, j = e / nb;   // column-major (i, j)
+    const double t = tau[j0 + i];
+    Ti[e] = i < j ? G[e] : (i == j ? (t != 0.0 ? 1.0 / t : 1.0) : 0.0);
+  }
+}
+
+
 #define OFM_BLAS_TD(call)                                                   \
   do {                                                                      \
     rocblas_status s_ = (call);                                             \
@@ -473,6 +511,44 @@ void sytrd_lower(hipStream_t s, rocblas_handle h, int n, double* A,
   OFM_HIP(hipStreamSynchronize(s));
 }
 
+// Z = Q Z for the Q of sytrd_lower (n x n Z, leading dimension ldz), in
+// blocks of QB reflectors from the last block to the first: per block,
+// W = V^T Z(j0+1:n, :), W <- T W (a triangular solve with T^{-1}),
+// Z(j0+1:n, :) -= V W, all as rocBLAS GEMM / TRSM.
+void apply_q(hipStream_t s, rocblas_handle h, int n, const double* A,
+             long long lda, const double* tau, double* Z, int ldz) {
+  if (n < 2) return;
+  DevBuf<double> Vb((size_t)n * QB), G((size_t)QB * QB), Ti((size_t)QB * QB),
+      W((size_t)QB * n);
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  const int nref = n - 1;
+  for (int j0 = (nref - 1) / QB * QB; j0 >= 0; j0 -= QB) {
+    const int nb = std::min(QB, nref - j0);
+    const int m = n - 1 - j0;
+    hipLaunchKernelGGL(k_build_v, dim3(std::min(2048, (m * nb + 255) / 256)),
+                       dim3(256), 0, s, A, lda, n, j0, nb, tau, Vb.p);
+    OFM_HIP(hipGetLastError());
+    OFM_BLAS_TD(rocblas_dgemm(h, rocblas_operation_transpose,
+                              rocblas_operation_none, nb, nb, m, &one, Vb.p, m,
+                              Vb.p, m, &zero, G.p, nb));
+    hipLaunchKernelGGL(k_build_tinv, dim3((nb * nb + 255) / 256), dim3(256), 0,
+                       s, G.p, nb, tau, j0, Ti.p);
+    OFM_HIP(hipGetLastError());
+    double* Zs = Z + (j0 + 1);
+    OFM_BLAS_TD(rocblas_dgemm(h, rocblas_operation_transpose,
+                              rocblas_operation_none, nb, n, m, &one, Vb.p, m,
+                              Zs, ldz, &zero, W.p, nb));
+    OFM_BLAS_TD(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_upper,
+                              rocblas_operation_none,
+                              rocblas_diagonal_non_unit, nb, n, &one, Ti.p, nb,
+                              W.p, nb));
+    OFM_BLAS_TD(rocblas_dgemm(h, rocblas_operation_none,
+                              rocblas_operation_none, m, n, nb, &mone, Vb.p, m,
+                              W.p, nb, &one, Zs, ldz));
+  }
+  OFM_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
 void dense_eigh(ofm_ctx* c, hipStream_t s, void* blas_handle, int n, double* A,
@@ -526,10 +602,7 @@ void dense_eigh(ofm_ctx* c, hipStream_t s, void* blas_handle, int n, double* A,
   // eigenvectors of T, then Z = Q Z
   OFM_BLAS_TD(rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, w, E.p, Z, n,
                                info));
-  OFM_BLAS_TD(rocsolver_dormtr(h, rocblas_side_left, rocblas_fill_lower,
-                               rocblas_operation_none, n, n, Ap.p, (int)ldp,
-                               tau.p, Z, n));
-  OFM_HIP(hipStreamSynchronize(s));
+  apply_q(s, h, n, Ap.p, ldp, tau.p, Z, n);
 }
 
 }  // namespace ofm
