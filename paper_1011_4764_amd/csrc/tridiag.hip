@@ -284,15 +284,27 @@ __global__ __launch_bounds__(256) void k_fin(
 
 // Sturm count of T - x I: the number of negative pivots of its LDL^T
 // factorisation, pivots of magnitude below pivmin replaced by -pivmin (the
-// safeguard of LAPACK's stebz).
+// safeguard of LAPACK's stebz).  The quotient uses a reciprocal of about
+// 1 ulp, so the count is that of T with entries perturbed by a few ulps.
+// 1/d from the hardware reciprocal and two Newton steps (about 1 ulp; |d|
+// is at least pivmin, a normal number)
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ int sturm_count(int n, const double* __restrict__ D,
                                            const double* __restrict__ E2,
                                            double x, double pivmin) {
   double d = D[0] - x;
   if (fabs(d) < pivmin) d = -pivmin;
   int cnt = d < 0;
+#pragma unroll 8
   for (int j = 1; j < n; ++j) {
-    d = (D[j] - x) - E2[j - 1] / d;
+    d = (D[j] - x) - E2[j - 1] * rcp_nr(d);
     if (fabs(d) < pivmin) d = -pivmin;
     cnt += d < 0;
   }
