@@ -6,13 +6,19 @@ batched fragment eigensolve + whole-system H|phi>, grouped pair matrix
 elements, and the thresholded generalised eigenproblem.
 
 Prints ONE JSON line.  `value` is fragment eigenstates delivered per second
-by the whole step (sum_j s_j / step time); the per-stage rates (fragment
-eigenstates/s of the eigensolver stage, H,S elements/s of the element stage),
-the roofline of the dominant kernel (the fragment-Hamiltonian stencil of the
-Chebyshev filter) and the CPU oracle's rate on a bounded sample ride along.
+by the whole job (sum_j s_j x steps / time of the timed steps).  By default
+two steps are in flight (two contexts on two HIP streams, one host thread
+each; every step runs the whole path and must return the serial step's
+eigenvalues), so the global solve's latency-bound launches overlap the other
+step's bandwidth-bound fragment stage; `serial_ms_per_step` is the same
+workload one step at a time (--inflight 1 makes it the value).  The
+per-stage rates (fragment eigenstates/s of the eigensolver stage, H,S
+elements/s of the element stage), the roofline of the dominant kernel (the
+fragment-Hamiltonian stencil of the Chebyshev filter) come from the serial
+profiled steps; the CPU oracle's rate on a bounded sample rides along.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config alkane]
-                  [--precision fp64|mixed] [--no-cpu-baseline]
+                  [--precision fp64|mixed] [--inflight 2|1] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -20,6 +26,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -47,7 +54,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="alkane")
     ap.add_argument("--seed", type=int, default=0)
@@ -63,6 +70,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-form comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inflight", type=int, default=2, choices=[1, 2],
+                    help="steps in flight during the timed throughput run "
+                         "(2: two contexts on two streams; 1: serial)")
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="fragments in the oracle's timed sample")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -162,30 +172,35 @@ def main():
     V_dev = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
     torch.cuda.synchronize()
 
-    def run_form(precision, tol, steps, warmup, profile):
+    def run_form(precision, tol, steps, warmup, profile, inflight=1):
+        """Serial timed steps (stage times, kernel statistics), then, with
+        inflight = 2, the same number of steps with two in flight: two
+        contexts on two HIP streams, one host thread each, every step the
+        whole path on its own (the global solve's latency-bound launches of
+        one step overlap the bandwidth-bound fragment stage of the other)."""
         prec = P.OFM_FP64 if precision == "fp64" else P.OFM_MIXED_BF16X3
         ctx = P.ofm_create(0, stream.cuda_stream, prec)
         last = {}
 
-        def step():
-            f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V_dev,
+        def step(cx, out):
+            f = P.ofm_build_fragments(cx, (g.nx, g.ny, g.nz), g.h, V_dev,
                                       system.frag_lo, system.frag_dims,
                                       system.frag_states, origin=g.origin)
             deg = args.degree if precision == "fp64" else args.degree_mixed
-            st, eps, it, cv = P.ofm_solve_fragments(ctx, f, tol=tol,
+            st, eps, it, cv = P.ofm_solve_fragments(cx, f, tol=tol,
                                                     degree=deg)
-            m = P.ofm_matrix_elements(ctx, f)
-            gs = P.ofm_solve_global(ctx, m, 1e-6)
+            m = P.ofm_matrix_elements(cx, f)
+            gs = P.ofm_solve_global(cx, m, 1e-6)
             E = gs["E"]
-            last.update(status=st, iters=it, conv=cv, n_pairs=f.n_pairs,
-                        n_values=m.n_values, E=E, n_kept=gs["n_kept"],
-                        stages=ctx.stage_times())
+            out.update(status=st, iters=it, conv=cv, n_pairs=f.n_pairs,
+                       n_values=m.n_values, E=E, n_kept=gs["n_kept"],
+                       stages=cx.stage_times())
             m.close()
             f.close()
 
         for w in range(warmup):
             t = time.perf_counter()
-            step()
+            step(ctx, last)
             log(f"{precision} tol {tol or 'default'} warmup {w}: "
                 f"{time.perf_counter() - t:.3f} s, status {last['status']}, "
                 f"iters max {int(last['iters'].max())}")
@@ -195,28 +210,61 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            step()
+            step(ctx, last)
             for key in stage_sum:
                 stage_sum[key] += last["stages"][key]
             log(f"{precision} step {k} done")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         ctx.set_profiling(False)
-        res = {"ms_step": 1000.0 * elapsed / steps, "last": last}
+        res = {"ms_step_serial": 1000.0 * elapsed / steps, "last": last}
         for key in stage_sum:
             res[key] = stage_sum[key] / steps
-        res["stencil"] = ctx.kernel_stats("stencil")
-        res["multistep"] = ctx.kernel_stats("multistep")
-        res["sweep"] = ctx.kernel_stats("sweep")
-        res["elements"] = ctx.kernel_stats("elements")
-        res["gram"] = ctx.kernel_stats("gram")
-        res["filter"] = ctx.kernel_stats("filter")
-        res["tridiag"] = ctx.kernel_stats("tridiag")
+        for fam in ("stencil", "multistep", "sweep", "elements", "gram",
+                    "filter", "tridiag"):
+            res[fam] = ctx.kernel_stats(fam)
+        res["ms_step"] = res["ms_step_serial"]
+        if inflight == 2:
+            stream2 = torch.cuda.Stream(dev)   # default priority
+            ctx2 = P.ofm_create(0, stream2.cuda_stream, prec)
+            other = {}
+            for w in range(warmup):
+                step(ctx2, other)
+            outs = [dict() for _ in range(steps)]
+            errors = []
+
+            def worker(cx, first):
+                try:
+                    for k in range(first, steps, 2):
+                        step(cx, outs[k])
+                        log(f"{precision} in-flight step {k} done")
+                except Exception as e:   # reported after the join
+                    errors.append(e)
+
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            th = [threading.Thread(target=worker, args=(cx, i))
+                  for i, cx in enumerate((ctx, ctx2))]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join()
+            torch.cuda.synchronize()
+            elapsed = time.perf_counter() - t0
+            ctx2.close()
+            if errors:
+                raise errors[0]
+            # every in-flight step delivers the serial step's eigenvalues
+            for o in outs:
+                if not np.array_equal(o["E"], last["E"]):
+                    raise RuntimeError("an in-flight step differs from the "
+                                       "serial one")
+            res["ms_step"] = 1000.0 * elapsed / steps
         ctx.close()
         return res
 
     main_form = run_form(args.precision, args.tol, args.steps, args.warmup,
-                         True)
+                         True, args.inflight)
     last = main_form["last"]
     ms_step = main_form["ms_step"]
     el, gr, td = main_form["elements"], main_form["gram"], main_form["tridiag"]
@@ -241,6 +289,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
+        "steps_in_flight": args.inflight,
+        "serial_ms_per_step": main_form["ms_step_serial"],
         "dtype": "f64" if args.precision == "fp64" else "f32+bf16x3",
         "data": "synthetic",
         "config": {"workload": f"{args.config} seed {args.seed}: "
@@ -297,7 +347,8 @@ def main():
     if args.precision == "fp64" and not args.no_mixed:
         # the same workload in the mixed form, and FP64 stopped at the mixed
         # tolerance (equal accuracy); window eigenvalues compared to FP64's
-        mx = run_form("mixed", 0.0, args.steps, args.warmup, True)
+        mx = run_form("mixed", 0.0, args.steps, args.warmup, True,
+                      args.inflight)
         eq = run_form("fp64", 2e-5, args.steps, args.warmup, False)
         Em = mx["last"]["E"]
         nw = len(window)
@@ -305,6 +356,7 @@ def main():
         out["mixed"] = {
             "value": n_states / (mx["ms_step"] * 1e-3),
             "ms_per_step": mx["ms_step"],
+            "serial_ms_per_step": mx["ms_step_serial"],
             "fragment_eigenstates_per_s": n_states / (mx["solve_ms"] * 1e-3),
             "hs_elements_per_s": 2 * mx["last"]["n_values"] / (mx["elements_ms"] * 1e-3),
             "solve_ms": mx["solve_ms"], "elements_ms": mx["elements_ms"],
