@@ -1,17 +1,26 @@
-"""Full-size run of the polythiophene-like system (4096 overlapping trimer
-fragments, 32^3..48^3 boxes, 24 states each, 98,304 basis states) in the
-mixed form: every fragment converges; a sample of three overlapping
-fragments is checked against the oracle's own eigenpairs (1e-5 Ha); with the
-oracle's states imported for that sample, its blocks match the oracle's
-(1e-6 of max|H|); properties that hold at any size are checked on all
-blocks (S_jj = I exactly, |S| <= 1)."""
+"""Full-size runs.
+
+The bench workload (alkane chain, 256 fragments of 32^3, 4096 basis states)
+in FP64, in the launch configuration bench.py times: every fragment
+converges; three overlapping fragments are checked against the oracle's own
+eigenpairs (1e-8 Ha); with the oracle's states imported for them, their
+blocks match the oracle's (1e-10 of max|H|); the whole global spectrum
+matches a CPU dense solve of the same blocks (1e-8 Ha).
+
+The polythiophene-like system (4096 overlapping trimer fragments,
+32^3..48^3 boxes, 24 states each, 98,304 basis states) in the mixed form:
+every fragment converges; a sample of three overlapping fragments is checked
+against the oracle's own eigenpairs (1e-5 Ha); with the oracle's states
+imported for that sample, its blocks match the oracle's (1e-6 of max|H|);
+properties that hold at any size are checked on all blocks (S_jj = I
+exactly, |S| <= 1)."""
 import time
 
 import numpy as np
 import pytest
 
 import oracle as O
-from ofm_inputs import thiophene_polymer
+from ofm_inputs import make_system, thiophene_polymer
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -27,6 +36,86 @@ def _sample(s):
     vol = s.frag_dims.prod(1)
     best = min(range(0, 62), key=lambda k: vol[k:k + 3].sum())
     return [best, best + 1, best + 2]
+
+
+def _sampled_blocks(ctx, f, V, g, s, samp, tol_eps, tol_h, eps):
+    """Oracle eigenpairs of the sampled fragments against eps; then, with
+    the oracle's states imported for them, their pair blocks against the
+    oracle's.  Returns the number of blocks checked."""
+    st_ = s.frag_states
+    boff = np.concatenate([[0], np.cumsum(st_)])
+    ref_states = {}
+    for j in samp:
+        e_o, phi_o = O.fragment_states(V, g.h, s.frag_lo[j], s.frag_dims[j],
+                                       int(st_[j]))
+        ref_states[j] = (e_o, phi_o)
+        err = np.abs(eps[boff[j]:boff[j + 1]] - e_o).max()
+        _say(f"  fragment {j}: max |eps - oracle| {err:.2e} Ha")
+        assert err < tol_eps
+    for j in samp:
+        P.ofm_set_states(f, j, ref_states[j][1].T, ref_states[j][0])
+    m = P.ofm_matrix_elements(ctx, f)
+    H, S = P.ofm_mats_copy(m)
+    pj, pn, off = f.pairs()
+    hp, hbox = {}, {}
+    for j in samp:
+        dlo, dd, hpj = O.apply_whole_H(V, g.h, s.frag_lo[j], s.frag_dims[j],
+                                       ref_states[j][1])
+        hp[j], hbox[j] = hpj, (dlo, dd)
+    phi = {j: ref_states[j][1] for j in samp}
+    checked = 0
+    for p in range(len(pj)):
+        j, n = int(pj[p]), int(pn[p])
+        if j not in samp or n not in samp:
+            continue
+        Sb, Hb, _ = O.pair_blocks(j, n, s.frag_lo, s.frag_dims, phi, hp, hbox)
+        if j == n:
+            Hb = 0.5 * (Hb + Hb.T)
+            Sb = np.eye(Sb.shape[0])
+        k = Sb.size
+        gH = H[off[p]:off[p] + k].reshape(Hb.shape)
+        gS = S[off[p]:off[p] + k].reshape(Sb.shape)
+        eh = np.abs(gH - Hb).max() / max(np.abs(Hb).max(), 1e-300)
+        es = np.abs(gS - Sb).max()
+        _say(f"  block ({j},{n}): H rel {eh:.2e}, S {es:.2e}")
+        assert eh < tol_h and es < tol_h
+        checked += 1
+    m.close()
+    return checked
+
+
+@pytest.mark.timeout(600)
+def test_alkane_fp64_full_size():
+    s = make_system("alkane", seed=0)
+    V = s.potential()
+    g = s.grid
+    _say("alkane", g.nx, g.ny, g.nz, s.n_frag, "fragments", s.n_basis,
+         "states")
+    ctx = P.ofm_create(0, None, P.OFM_FP64)
+    f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
+                              s.frag_dims, s.frag_states, origin=g.origin)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0 and cv.all()
+    m = P.ofm_matrix_elements(ctx, f)
+    gs = P.ofm_solve_global(ctx, m, 1e-6)
+    _say("library stage times", ctx.stage_times(),
+         f"iterations max {it.max()}, kept {gs['n_kept']}")
+    # the whole spectrum of the pencil against a CPU dense solve of the
+    # same blocks
+    H, S = P.ofm_mats_copy(m)
+    Hd, Sd = _subset_dense(f, H, S, np.ones(s.n_basis, bool))
+    ref = O.global_solve(Hd, Sd, 1e-6)
+    assert ref["n_kept"] == gs["n_kept"]
+    err = np.abs(ref["E"] - gs["E"]).max()
+    _say(f"  global spectrum ({len(gs['E'])} eigenvalues) vs CPU dense "
+         f"solve of the same blocks: {err:.2e} Ha")
+    assert err < 1e-8
+    m.close()
+    samp = [127, 128, 129]   # consecutive windows overlap by half
+    checked = _sampled_blocks(ctx, f, V, g, s, samp, 1e-8, 1e-10, eps)
+    assert checked == 6
+    f.close()
+    ctx.close()
 
 
 @pytest.mark.timeout(600)
@@ -62,48 +151,11 @@ def test_thiophene_mixed_full_size():
                               np.eye(k))
     assert np.abs(S).max() <= 1 + 1e-6
     m.close()
-    # sampled fragments against the oracle's own eigenpairs
+    # sampled fragments against the oracle's own eigenpairs and blocks
     samp = _sample(s)
     _say("sample", samp, [tuple(s.frag_dims[j]) for j in samp])
-    boff = np.concatenate([[0], np.cumsum(st_)])
-    ref_states = {}
-    for j in samp:
-        e_o, phi_o = O.fragment_states(V, g.h, s.frag_lo[j], s.frag_dims[j],
-                                       int(st_[j]))
-        ref_states[j] = (e_o, phi_o)
-        err = np.abs(eps[boff[j]:boff[j + 1]] - e_o).max()
-        _say(f"  fragment {j}: max |eps - oracle| {err:.2e} Ha")
-        assert err < 1e-5
-    # import the oracle's states for the sample; compare their blocks
-    for j in samp:
-        P.ofm_set_states(f, j, ref_states[j][1].T, ref_states[j][0])
-    m = P.ofm_matrix_elements(ctx, f)
-    H, S = P.ofm_mats_copy(m)
-    hp, hbox = {}, {}
-    for j in samp:
-        dlo, dd, hpj = O.apply_whole_H(V, g.h, s.frag_lo[j], s.frag_dims[j],
-                                       ref_states[j][1])
-        hp[j], hbox[j] = hpj, (dlo, dd)
-    phi = {j: ref_states[j][1] for j in samp}
-    checked = 0
-    for p in range(len(pj)):
-        j, n = int(pj[p]), int(pn[p])
-        if j not in samp or n not in samp:
-            continue
-        Sb, Hb, _ = O.pair_blocks(j, n, s.frag_lo, s.frag_dims, phi, hp, hbox)
-        if j == n:
-            Hb = 0.5 * (Hb + Hb.T)
-            Sb = np.eye(Sb.shape[0])
-        k = Sb.size
-        gH = H[off[p]:off[p] + k].reshape(Hb.shape)
-        gS = S[off[p]:off[p] + k].reshape(Sb.shape)
-        eh = np.abs(gH - Hb).max() / max(np.abs(Hb).max(), 1e-300)
-        es = np.abs(gS - Sb).max()
-        _say(f"  block ({j},{n}): H rel {eh:.2e}, S {es:.2e}")
-        assert eh < 1e-6 and es < 1e-6
-        checked += 1
+    checked = _sampled_blocks(ctx, f, V, g, s, samp, 1e-5, 1e-6, eps)
     assert checked == 6
-    m.close()
     f.close()
     ctx.close()
 
