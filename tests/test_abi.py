@@ -65,3 +65,33 @@ def test_homo_lumo_gap_host_matches_oracle():
         P.ofm_homo_lumo_gap([1.0, 0.0], 0.0, 0.1)   # not ascending
     with pytest.raises(P.OfmError):
         P.ofm_homo_lumo_gap([0.0, 1.0], 0.0, -1.0)  # negative gap
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libofm.so not built")
+def test_null_handles_rejected_without_a_gpu():
+    """Every entry point that takes a context, fragment or matrix handle
+    returns OFM_E_INVALID for a NULL handle (all other pointers NULL, sizes
+    zero) before touching the device; ofm_homo_lumo_gap rejects NULL outputs
+    and ofm_last_error(NULL) still returns text."""
+    import ctypes as C
+
+    import paper_1011_4764_amd as P
+    L = P.lib()
+    skip = {"ofm_create", "ofm_version", "ofm_last_error"}
+    checked = 0
+    for name in _declared():
+        if name in skip:
+            continue
+        fn = getattr(L, name)
+        args = []
+        for t in fn.argtypes:
+            if t in (C.c_int, C.c_longlong):
+                args.append(t(0))
+            elif t is C.c_double:
+                args.append(t(0.0))
+            else:
+                args.append(None)
+        assert fn(*args) == P.OFM_E_INVALID, name
+        checked += 1
+    assert checked == len(_declared()) - len(skip)
+    assert isinstance(L.ofm_last_error(None), bytes)
