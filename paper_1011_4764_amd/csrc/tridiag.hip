@@ -471,8 +471,6 @@ __global__ void k_build_tinv(const double* __restrict__ G, int nb,
                                     rocblas_status_to_string(s_)};          \
   } while (0)
 
-// Reduction of the n x n symmetric A (full storage, n >= 2) to tridiagonal
-// form; D (n), E (n-1), tau (n-1) on the device.
 // Reduction of the n x n symmetric A (full storage, n >= 2, lda even and
 // >= n rounded up to even, rows n..lda-1 zero) to tridiagonal form; D (n),
 // E (n-1), tau (n-1) on the device.
