@@ -594,3 +594,47 @@ def test_more_error_paths(ctx, tiny0):
     assert len(g["E"]) == s.n_basis
     m.close()
     f.close()
+
+
+def test_two_contexts_in_flight_bit_identical(tiny0):
+    """Two contexts on two streams driven from two host threads at once (the
+    bench's throughput mode): every step returns the serial run's fragment
+    eigenvalues, blocks and global eigenvalues bit for bit."""
+    import threading
+    _say("two contexts in flight")
+    s = tiny0
+
+    def run(cx):
+        f = _build(cx, s)
+        st, eps, it, cv = P.ofm_solve_fragments(cx, f)
+        m = P.ofm_matrix_elements(cx, f)
+        H, S = P.ofm_mats_copy(m)
+        E = P.ofm_solve_global(cx, m, 1e-6)["E"]
+        m.close()
+        f.close()
+        return eps, H, S, E
+
+    c0 = P.ofm_create(0, None, P.OFM_FP64)
+    ref = run(c0)
+    c1 = P.ofm_create(0, None, P.OFM_FP64)
+    out, err = [None] * 6, []
+
+    def worker(cx, first):
+        try:
+            for k in range(first, 6, 2):
+                out[k] = run(cx)
+        except Exception as e:
+            err.append(e)
+
+    th = [threading.Thread(target=worker, args=(cx, i))
+          for i, cx in enumerate((c0, c1))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    c1.close()
+    c0.close()
+    assert not err, err
+    for o in out:
+        for a, b in zip(o, ref):
+            assert np.array_equal(a, b)
