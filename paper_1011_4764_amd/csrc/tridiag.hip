@@ -3,22 +3,24 @@
 // Householder reduction to tridiagonal form, T = Q^T A Q with
 // Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^T, in the blocked form of
 // Golub & Van Loan (Sec. 8.3.1, with the panel factorisation of LAPACK's
-// latrd).  The output follows the LAPACK lower-storage convention so that
-// rocSOLVER's tridiagonal eigensolvers (sterf, stedc) and Q application
-// (ormtr) consume it: D the diagonal, E the subdiagonal, v_i in A(i+2:n, i)
-// with its unit leading element implicit at A(i+1, i), which holds E(i) on
-// return, and tau_i.
+// latrd).  The output follows the LAPACK lower-storage convention (D the
+// diagonal, E the subdiagonal, v_i in A(i+2:n, i) with its unit leading
+// element implicit at A(i+1, i), which holds E(i) on return, and tau_i), so
+// rocSOLVER's divide and conquer (stedc) takes T directly; the eigenvalues
+// alone come from multisection on the Sturm count, and Q is applied to the
+// tridiagonal eigenvectors in blocks of reflectors (both below).
 //
 // Shape on the GPU: the matrix is kept in full symmetric storage (both
-// triangles), so the product with the trailing matrix is a column-parallel,
-// coalesced matrix-vector product; a 4096^2 FP64 matrix (128 MiB) stays in
-// the Infinity Cache.  Each column takes two launches and no workgroup ever
-// waits for another: k_mv forms y = A22 v and the panel projections
-// W^T v, V^T v (one dot product per wave), every workgroup rebuilding the
-// reflector from the previous launch's partial norms; k_fin, row-parallel,
-// forms w (its correction -tau/2 (w.v) v from w.v = tau (y.v - 2 u1.u2)),
-// stores v and w, and applies the panel's reflectors to the next column.
-// After a panel of NB columns one GEMM applies A22 -= V W^T + W V^T.
+// triangles) with the leading dimension padded to 64 rows, so the product
+// with the trailing matrix is a column-parallel, coalesced matrix-vector
+// product that streams each column once.  Each column takes two launches
+// and no workgroup ever waits for another: k_mv forms y = A22 v and the
+// panel projections W^T v, V^T v (one dot product per wave), every wave
+// rebuilding the reflector from the previous launch's partial norms; k_fin,
+// row-parallel, forms w (its correction -tau/2 (w.v) v from
+// w.v = tau (y.v - 2 u1.u2)), stores v and w, and applies the panel's
+// reflectors to the next column.  After a panel of NB columns one GEMM
+// applies A22 -= V W^T + W V^T.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -31,8 +33,10 @@
 namespace ofm {
 namespace {
 
-constexpr int NB = 32;     // panel width
-constexpr int TPB = 1024;  // threads of the column kernels
+#ifndef OFM_TD_NB
+#define OFM_TD_NB 32
+#endif
+constexpr int NB = OFM_TD_NB;   // panel width (a multiple of 4, at most 64)
 
 // one DPP step on both halves of a double
 template <int CTRL>
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(256) void k_fin(
   const double pwl = W[piv + (long long)lqc * ldw];
   double aw = 0, ac = 0;
 #pragma unroll
-  for (int sl = 0; sl < 8; ++sl) {
+  for (int sl = 0; sl < NB / 4; ++sl) {
     const int q = g + 4 * sl;
     const bool ok = q < il;
     const int qc = ok ? q : 0;
@@ -282,10 +286,6 @@ __global__ __launch_bounds__(256) void k_fin(
   }
 }
 
-// Sturm count of T - x I: the number of negative pivots of its LDL^T
-// factorisation, pivots of magnitude below pivmin replaced by -pivmin (the
-// safeguard of LAPACK's stebz).  The quotient uses a reciprocal of about
-// 1 ulp, so the count is that of T with entries perturbed by a few ulps.
 // 1/d from the hardware reciprocal and two Newton steps (about 1 ulp; |d|
 // is at least pivmin, a normal number)
 __device__ __forceinline__ double rcp_nr(double d) {
@@ -296,6 +296,10 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return fma(r, e, r);
 }
 
+// Sturm count of T - x I: the number of negative pivots of its LDL^T
+// factorisation, pivots of magnitude below pivmin replaced by -pivmin (the
+// safeguard of LAPACK's stebz).  The quotient uses a reciprocal of about
+// 1 ulp, so the count is that of T with entries perturbed by a few ulps.
 __device__ __forceinline__ int sturm_count(int n, const double* __restrict__ D,
                                            const double* __restrict__ E2,
                                            double x, double pivmin) {
