@@ -307,7 +307,11 @@ __global__ __launch_bounds__(H2T) void k_apply_hm(
     T an[PPT], vn[PPT], qn[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      an[k] = (ok[k] && t + 3 < nz) ? in[zoff + 3 * plane + pp[k]] : T(0);
+      // the input and y_{k-2} streams are read once (non-temporal, leaving
+      // L2 to V_j, which the box's other vectors read again)
+      an[k] = (ok[k] && t + 3 < nz)
+                  ? __builtin_nontemporal_load(&in[zoff + 3 * plane + pp[k]])
+                  : T(0);
       vn[k] = (ok[k] && t + 1 < nz) ? vv[zoff + plane + pp[k]] : T(0);
       qn[k] = (ok[k] && use_prev && t + 1 < nz)
                   ? __builtin_nontemporal_load(&pv[zoff + plane + pp[k]])
