@@ -287,9 +287,9 @@ ofm_status ofm_solve_global_subset(ofm_ctx* ctx, const ofm_mats* m,
    column-major, symmetric (both triangles are read; they should agree).
    w: n doubles, host, the eigenvalues in ascending order.  Z: NULL, or n*n
    doubles, host, column k the unit eigenvector of w[k] (each column's sign
-   is arbitrary).  Errors: OFM_E_INVALID for n < 1, n > 65536 or a NULL A or
-   w; OFM_E_DEVICE when the tridiagonal solver does not converge;
-   OFM_E_NOMEM. */
+   is arbitrary).  Errors: OFM_E_INVALID for n < 1, n > 65536, a NULL A or
+   w, or a NaN or Inf in A; OFM_E_DEVICE when the tridiagonal solver does
+   not converge; OFM_E_NOMEM. */
 ofm_status ofm_dense_eigh(ofm_ctx* ctx, int n, const double* A, double* w,
                           double* Z);
 

@@ -1165,6 +1165,9 @@ ofm_status ofm_dense_eigh(ofm_ctx* c, int n, const double* A, double* w,
     OFM_REQUIRE(A && w, OFM_E_INVALID, "A and w are required");
     OFM_REQUIRE(n >= 1 && n <= 65536, OFM_E_INVALID,
                 "n outside the dense solver's range [1, 65536]");
+    const long long nn = (long long)n * n;
+    for (long long e = 0; e < nn; ++e)
+      OFM_REQUIRE(std::isfinite(A[e]), OFM_E_INVALID, "A has a NaN or Inf");
     use_device(c);
     dense_eigh_host(c, n, A, w, Z);
     return OFM_OK;

@@ -170,3 +170,11 @@ def test_dense_eigh_errors(ctx):
     with pytest.raises(P.OfmError) as e:
         P.ofm_dense_eigh(ctx, np.zeros((0, 0)))
     assert e.value.status == P.OFM_E_INVALID
+    for bad in (np.nan, np.inf):
+        A = np.eye(5)
+        A[3, 1] = A[1, 3] = bad
+        with pytest.raises(P.OfmError) as e:
+            P.ofm_dense_eigh(ctx, A)
+        assert e.value.status == P.OFM_E_INVALID
+    w, _ = P.ofm_dense_eigh(ctx, np.eye(5))   # the context is still usable
+    assert np.allclose(w, 1.0)
