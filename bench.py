@@ -328,8 +328,8 @@ def main():
                      "avg_ms": gr["ms"] / max(gr["launches"], 1),
                      "GBps": (gr["bytes"] / gr["ms"] / 1e6) if gr["ms"] else 0,
                      "TFLOPs": (gr["flops"] / gr["ms"] / 1e9) if gr["ms"] else 0},
-            "tridiag": {"kernel": "k_mv + k_fin (Householder tridiagonal "
-                                  "reduction of the global solve)",
+            "tridiag": {"kernel": "k_mvt / k_mv + k_fin (Householder "
+                                  "tridiagonal reduction of the global solve)",
                         "reductions": td["launches"],
                         "avg_ms": td["ms"] / max(td["launches"], 1),
                         "alg_bytes": td["bytes"] / max(td["launches"], 1),

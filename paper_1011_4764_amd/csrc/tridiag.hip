@@ -11,16 +11,17 @@
 // tridiagonal eigenvectors in blocks of reflectors (both below).
 //
 // Shape on the GPU: the matrix is kept in full symmetric storage (both
-// triangles) with the leading dimension padded to 64 rows, so the product
-// with the trailing matrix is a column-parallel, coalesced matrix-vector
-// product that streams each column once.  Each column takes two launches
-// and no workgroup ever waits for another: k_mv forms y = A22 v and the
-// panel projections W^T v, V^T v (one dot product per wave), every wave
-// rebuilding the reflector from the previous launch's partial norms; k_fin,
-// row-parallel, forms w (its correction -tau/2 (w.v) v from
-// w.v = tau (y.v - 2 u1.u2)), stores v and w, and applies the panel's
-// reflectors to the next column.  After a panel of NB columns one GEMM
-// applies A22 -= V W^T + W V^T.
+// triangles) with the leading dimension padded to 64 rows.  Each column
+// takes two launches and no workgroup ever waits for another.  The first
+// forms y = A22 v and the panel projections W^T v, V^T v, rebuilding the
+// reflector from the previous launch's partial norms: for large trailing
+// matrices k_mvt reads the lower triangle once in tiles (half the bytes)
+// and leaves per-tile partial sums, for small ones k_mv streams whole
+// columns, one dot product per wave.  k_fin, row-parallel, completes y,
+// forms w (its correction -tau/2 (w.v) v from w.v = tau (y.v - 2 u1.u2)),
+// stores v and w, and applies the panel's reflectors to the next column.
+// After a panel of NB columns one GEMM applies A22 -= V W^T + W V^T to both
+// triangles.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -95,6 +96,67 @@ __global__ __launch_bounds__(FR) void k_pstart(const double* A, long long lda,
 constexpr int MV = 256;   // threads of k_mv (one wave per dot product)
 constexpr int MU = 4;     // double2 loads in flight per lane in k_mv
 
+// One wave: s1 = x(i+1) and sr = sum_{r>=i+2} x(r) c(r) for the column x
+// (rows i+1..n-1), read as 16-byte pairs from the even row rb = (i+1) & ~1
+// (the pair holding row i+1 is formed by lane 0 alone); wave-uniform sums.
+__device__ __forceinline__ void col_dot(const double* col, const double* c,
+                                        int i, int n, int lane, double& s1,
+                                        double& sr) {
+  const int rb = (i + 1) & ~1;
+  const int npair = (n - rb + 1) >> 1;
+  const double2* a2 = reinterpret_cast<const double2*>(col + rb);
+  const double2* c2 = reinterpret_cast<const double2*>(c + rb);
+  s1 = 0;
+  sr = 0;
+  if (lane == 0) {   // pair 0: rows rb, rb+1, one of them is i+1
+    const double2 a = a2[0], cc = c2[0];
+    if (rb == i + 1) {
+      s1 = a.x;
+      sr = a.y * cc.y;
+    } else {
+      s1 = a.y;
+    }
+  }
+  double acc[MU];
+#pragma unroll
+  for (int q = 0; q < MU; ++q) acc[q] = 0;
+  int k = 1 + lane;
+  for (; k + 64 * (MU - 1) < npair; k += 64 * MU) {
+    double2 a[MU], cc[MU];
+#pragma unroll
+    for (int q = 0; q < MU; ++q) {
+      a[q] = a2[k + 64 * q];
+      cc[q] = c2[k + 64 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < MU; ++q) acc[q] += a[q].x * cc[q].x + a[q].y * cc[q].y;
+  }
+  for (; k < npair; k += 64) {
+    const double2 a = a2[k], cc = c2[k];
+    acc[0] += a.x * cc.x + a.y * cc.y;
+  }
+#pragma unroll
+  for (int q = 0; q < MU; ++q) sr += acc[q];
+  s1 = wave_sum_d(s1);
+  sr = wave_sum_d(sr);
+}
+
+// The reflector of column i from alpha = c(i+1) and the squared norm xn2 of
+// c(i+2:n): beta = -sign(alpha) sqrt(alpha^2 + xn2), tau = (beta - alpha) /
+// beta, scale = 1 / (alpha - beta); the identity (tau = 0) when xn2 = 0.
+__device__ __forceinline__ void reflector(double alpha, double xn2,
+                                          double& beta, double& t,
+                                          double& scale) {
+  t = 0;
+  beta = alpha;
+  scale = 1;
+  if (xn2 > 0) {
+    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+}
+
 // Column i = p + il: c = A(i:n, i) holds the column with every earlier
 // reflector applied; v(i+1) = 1, v(r) = scale c(r) for r >= i+2.  Waves
 // 0..L-1 form y(k) = A22(:, k) . v, waves L..L+il-1 u1 = W(i+1:n, 0:il)^T v,
@@ -135,49 +197,10 @@ __global__ __launch_bounds__(MV) void k_mv(
     } else {
       col = A + (long long)(p + wave - L - il) * lda;
     }
-    const int rb = (i + 1) & ~1;
-    const int npair = (n - rb + 1) >> 1;
-    const double2* a2 = reinterpret_cast<const double2*>(col + rb);
-    const double2* c2 = reinterpret_cast<const double2*>(c + rb);
-    if (lane == 0) {   // pair 0: rows rb, rb+1, one of them is i+1
-      const double2 a = a2[0], cc = c2[0];
-      if (rb == i + 1) {
-        s1 = a.x;
-        sr = a.y * cc.y;
-      } else {
-        s1 = a.y;
-      }
-    }
-    double acc[MU];
-#pragma unroll
-    for (int q = 0; q < MU; ++q) acc[q] = 0;
-    int k = 1 + lane;
-    for (; k + 64 * (MU - 1) < npair; k += 64 * MU) {
-      double2 a[MU], cc[MU];
-#pragma unroll
-      for (int q = 0; q < MU; ++q) {
-        a[q] = a2[k + 64 * q];
-        cc[q] = c2[k + 64 * q];
-      }
-#pragma unroll
-      for (int q = 0; q < MU; ++q) acc[q] += a[q].x * cc[q].x + a[q].y * cc[q].y;
-    }
-    for (; k < npair; k += 64) {
-      const double2 a = a2[k], cc = c2[k];
-      acc[0] += a.x * cc.x + a.y * cc.y;
-    }
-#pragma unroll
-    for (int q = 0; q < MU; ++q) sr += acc[q];
-    s1 = wave_sum_d(s1);
-    sr = wave_sum_d(sr);
+    col_dot(col, c, i, n, lane, s1, sr);
   }
-  const double xn2 = wave_sum_d(ss);
-  double t = 0, beta = alpha, scale = 1;
-  if (xn2 > 0) {
-    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-    t = (beta - alpha) / beta;
-    scale = 1.0 / (alpha - beta);
-  }
+  double t, beta, scale;
+  reflector(alpha, wave_sum_d(ss), beta, t, scale);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     D[i] = cii;
     E[i] = beta;
@@ -198,11 +221,166 @@ __global__ __launch_bounds__(MV) void k_mv(
   if (threadIdx.x == 0) pm[blockIdx.x] = bs;
 }
 
-constexpr int FROWS = 64;   // rows per workgroup of k_fin (4 waves)
-constexpr int PMU = 8;      // partial sums in flight per lane in k_fin
+// Large trailing matrices: the product with A22 from its lower triangle
+// alone, half the bytes of k_mv.
+constexpr int TR = 256;      // rows per tile (two 16-byte pairs per lane)
+constexpr int TC = 32;       // columns per tile (8 per wave)
+constexpr int LTILE = 2048;  // trailing sizes from which k_mvt replaces k_mv
 
-// Column i = p + il, rows r = i+1..n-1, FROWS per workgroup; wave g sums
-// the panel terms q = g, g+4, ... < il for its workgroup's rows:
+// Tiles of A22 = A(k0:n, k0:n), k0 = i+1: tile row rb covers rows
+// rbase + rb TR .. (rbase = k0 & ~1, so that rows are read as aligned
+// pairs), tile column cb columns k0 + cb TC ..; tile row rb holds the tiles
+// that reach the diagonal or lie below it, cb < tile_cols(rb).
+__host__ __device__ inline int tile_cols(int rb, int rbase, int k0, int ncb) {
+  const int c = (rbase + (rb + 1) * TR - 1 - k0) / TC + 1;
+  return c < ncb ? c : ncb;
+}
+
+// Column i = p + il, k0 = i+1, x(r) = c(r) for r >= i+2 (zero elsewhere).
+// Workgroups 0..ntiles-1 each take one lower tile and form, from its
+// elements A(r, k) with r >= k (each stored element read once):
+//   P[rb][k - k0]       = sum_{r >= k, r in tile} A(r, k) x(r)   (8 columns
+//                         per wave, all TR rows),
+//   P[nrb + cb][r - k0] = sum_{k < r, k in tile} A(r, k) x(k)    (the
+//                         symmetric half, summed over the 4 waves),
+//   pq[tile]            = the tile's share of x^T A22 x;
+// so (A22 x)(r) is the sum of the slots that exist for r (k_fin adds them
+// up), and y = A22 v = A(:, k0) + scale A22 x since v = e_{k0} + scale x.
+// Workgroups ntiles.. form u1 = W(i+1:n, 0:il)^T v and u2 =
+// V(i+1:n, 0:il)^T v (one wave each) and build the reflector; the first of
+// them stores D, E, tau, scale and A(i+1, i+1) (as y[0]).
+// Storage as for k_mv; P holds nrb + ncb slots of leading dimension ldp >= L.
+__global__ __launch_bounds__(256) void k_mvt(
+    const double* A, long long lda, int n, int p, int il, const double* W,
+    long long ldw, const double* part, int np, double* D, double* E,
+    double* tau, double* sc, double* y, double* u, int ntiles, int nrb,
+    int ncb, double* P, long long ldp, double* pq) {
+  __shared__ double red[4][TR];
+  __shared__ double qs[4];
+  const int i = p + il, k0 = i + 1;
+  const double* c = A + (long long)i * lda;   // indexed by row
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if ((int)blockIdx.x >= ntiles) {
+    const int uw = ((int)blockIdx.x - ntiles) * 4 + w;
+    double ss = 0;
+    for (int k = lane; k < np; k += 64) ss += part[k];
+    const double alpha = c[k0], cii = c[i];
+    double s1 = 0, sr = 0;
+    if (uw < 2 * il) {
+      const double* col = uw < il ? W + (long long)uw * ldw
+                                  : A + (long long)(p + uw - il) * lda;
+      col_dot(col, c, i, n, lane, s1, sr);
+    }
+    double t, beta, scale;
+    reflector(alpha, wave_sum_d(ss), beta, t, scale);
+    if ((int)blockIdx.x == ntiles && threadIdx.x == 0) {
+      D[i] = cii;
+      E[i] = beta;
+      tau[i] = t;
+      sc[i] = scale;
+      y[0] = A[k0 + (long long)k0 * lda];   // k_fin updates it in place
+    }
+    if (uw < 2 * il && lane == 0) u[uw] = s1 + scale * sr;
+    return;
+  }
+  const int rbase = k0 & ~1;
+  int tl = blockIdx.x, rb = 0;
+  for (;; ++rb) {   // ends: blockIdx.x < the sum of tile_cols over rb < nrb
+    const int cnt = tile_cols(rb, rbase, k0, ncb);
+    if (tl < cnt) break;
+    tl -= cnt;
+  }
+  const int cb = tl;
+  constexpr int TRP = TR / 128;   // pairs per lane
+  const int npair = (n + 1) >> 1;
+  const double2* c2 = reinterpret_cast<const double2*>(c);
+  int pr[TRP];
+  double2 xr[TRP];
+#pragma unroll
+  for (int h = 0; h < TRP; ++h) {
+    pr[h] = (rbase >> 1) + rb * (TR / 2) + lane + 64 * h;
+    const int r0 = 2 * pr[h];
+    double2 x = c2[pr[h] < npair ? pr[h] : npair - 1];
+    x.x = (r0 < n && r0 >= k0 + 1) ? x.x : 0.0;
+    x.y = (r0 + 1 < n && r0 + 1 >= k0 + 1) ? x.y : 0.0;
+    xr[h] = x;
+  }
+  double2 rowp[TRP];
+#pragma unroll
+  for (int h = 0; h < TRP; ++h) rowp[h] = make_double2(0.0, 0.0);
+  const int kb = k0 + cb * TC + w * 8;
+  double2 a[8][TRP];
+  double xk[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kc = kb + j;
+    const int kcc = kc < n ? kc : n - 1;
+    const double2* a2 = reinterpret_cast<const double2*>(A + (long long)kcc * lda);
+#pragma unroll
+    for (int h = 0; h < TRP; ++h) a[j][h] = a2[pr[h] < npair ? pr[h] : npair - 1];
+    xk[j] = (kc < n && kc >= k0 + 1) ? c[kcc] : 0.0;
+  }
+  double q = 0, mine = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kc = kb + j;
+    double s = 0;
+#pragma unroll
+    for (int h = 0; h < TRP; ++h) {
+      const int r0 = 2 * pr[h];
+      const double ax = r0 >= kc ? a[j][h].x : 0.0;
+      const double ay = r0 + 1 >= kc ? a[j][h].y : 0.0;
+      s += ax * xr[h].x + ay * xr[h].y;
+      rowp[h].x += (r0 > kc ? a[j][h].x : 0.0) * xk[j];
+      rowp[h].y += (r0 + 1 > kc ? a[j][h].y : 0.0) * xk[j];
+    }
+    const double sj = wave_sum_d(s);
+    q += sj * xk[j];
+    if (lane == j) mine = sj;
+  }
+  if (lane < 8 && kb + lane < n) P[(long long)rb * ldp + (kb + lane - k0)] = mine;
+#pragma unroll
+  for (int h = 0; h < TRP; ++h) {
+    red[w][2 * (lane + 64 * h)] = rowp[h].x;
+    red[w][2 * (lane + 64 * h) + 1] = rowp[h].y;
+  }
+  __syncthreads();
+  double qr = 0;
+  for (int rr = threadIdx.x; rr < TR; rr += 256) {
+    const double s = (red[0][rr] + red[1][rr]) + (red[2][rr] + red[3][rr]);
+    const int r = rbase + rb * TR + rr;
+    if (r >= k0 && r < n) {
+      P[(long long)(nrb + cb) * ldp + (r - k0)] = s;
+      qr += (r >= k0 + 1 ? c[r] : 0.0) * s;
+    }
+  }
+  const double qrs = wave_sum_d(qr);
+  if (lane == 0) qs[w] = qrs + q;
+  __syncthreads();
+  if (threadIdx.x == 0) pq[blockIdx.x] = (qs[0] + qs[1]) + (qs[2] + qs[3]);
+}
+
+// Tiles of the product at trailing size L = n - k0 (host side).
+inline int tile_count(int n, int k0, int& nrb, int& ncb) {
+  const int rbase = k0 & ~1;
+  nrb = (n - rbase + TR - 1) / TR;
+  ncb = (n - k0 + TC - 1) / TC;
+  int t = 0;
+  for (int rb = 0; rb < nrb; ++rb) t += tile_cols(rb, rbase, k0, ncb);
+  return t;
+}
+
+constexpr int FROWS = 64;   // rows per workgroup of k_fin (one per lane)
+constexpr int PMU = 4;      // partial sums per lane and round in k_fin
+constexpr int SU = 16;      // slot loads per lane and round in k_fin (tiled)
+
+// waves per workgroup of k_fin: 4 on k_mv's output; 16 on k_mvt's, whose
+// slot sums add several times the loads
+__host__ __device__ constexpr int fin_waves(bool tiled) { return tiled ? 16 : 4; }
+
+// Column i = p + il, rows r = i+1..n-1, FROWS per workgroup of FW waves;
+// wave g sums the panel terms q = g, g+FW, ... < il for its workgroup's
+// rows:
 //   v(r) = scale c(r) (v(i+1) = 1), stored over c in A(:, i);
 //   w(r) = tau (y(r) - V(r,:) u1 - W(r,:) u2) + alpha v(r), stored as
 //          column il of W, with alpha = -tau/2 (w~ . v) and
@@ -210,13 +388,23 @@ constexpr int PMU = 8;      // partial sums in flight per lane in k_fin
 //   next column (when the panel has one): c'(r) = A(r, i+1)
 //          - sum_{q<=il} (V(r,q) W(i+1,q) + W(r,q) V(i+1,q)) in place, and
 //          the workgroup's partial sum of c'(r)^2 over r >= i+3.
-// The pivot row's w(i+1) is formed by every wave (and stored as such).
-// Every load is issued before the first barrier.
-__global__ __launch_bounds__(256) void k_fin(
+// y comes from k_mv (tiled = false: y complete, pm the shares of y . v) or
+// from k_mvt (tiled: y(r) = A(r, i+1) + scale (A22 x)(r), wave g adding the
+// slots g, g+FW, ... of P that exist for row r; pm the shares of
+// x^T A22 x, and y . v = A(i+1, i+1) + 2 scale (A22 x)(i+1)
+// + scale^2 x^T A22 x).
+// The kernel is bound by the latency of its loads (at most n/64
+// workgroups): the FW waves split every sum (the pm shares too) and issue
+// all their loads (addresses clamped, so none is conditional) before the
+// first wait; wave 0 combines the sums after the barrier and forms the
+// pivot row's w(i+1) and the rows.
+template <bool tiled, int FW = fin_waves(tiled)>
+__global__ __launch_bounds__(64 * FW) void k_fin(
     double* A, long long lda, int n, int p, int il, int nb_panel, double* W,
     long long ldw, const double* tau, const double* sc, const double* y,
-    const double* u, const double* pm, int gm, double* part) {
-  __shared__ double sw[4][64], scn[4][64];
+    const double* u, const double* pm, int gm, double* part, const double* P,
+    long long ldp, int nrb, int ncb) {
+  __shared__ double sw[FW][64], scn[FW][64], sy[tiled ? FW : 1][64], sp[2][FW];
   const int i = p + il, piv = i + 1;
   const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool next = il + 1 < nb_panel;
@@ -224,63 +412,132 @@ __global__ __launch_bounds__(256) void k_fin(
   const int rc = r < n ? r : n - 1;
   double* cv = A + (long long)i * lda;
   double* cn = A + (long long)(next ? i + 1 : i) * lda;
-  const double cvr = cv[rc], cnr = cn[rc], yr = y[rc - piv], y0 = y[0];
+  const double cvr = cv[rc], cnr = cn[rc];
+  const double yr0 = tiled ? A[rc + (long long)piv * lda] : y[rc - piv];
   const double t = tau[i], scale = sc[i];
-  double pacc[PMU];
-#pragma unroll
-  for (int q = 0; q < PMU; ++q) pacc[q] = 0;
-  int k = lane;
-  for (; k + 64 * (PMU - 1) < gm; k += 64 * PMU) {
-#pragma unroll
-    for (int q = 0; q < PMU; ++q) pacc[q] += pm[k + 64 * q];
-  }
-  for (; k < gm; k += 64) pacc[0] += pm[k];
+  const double y00 = y[0];   // A(i+1, i+1) when tiled (row piv of cn changes)
   const bool lq = lane < il;
   const int lqc = lq ? lane : 0;
   const double u1l = u[lqc], u2l = u[il + lqc];
   const double pvl = A[piv + (long long)(p + lqc) * lda];
   const double pwl = W[piv + (long long)lqc * ldw];
-  double aw = 0, ac = 0;
+  // panel terms of this wave
+  constexpr int QW = (NB + FW - 1) / FW;
+  double vq[QW], wq[QW], wpq[QW], vpq[QW];
 #pragma unroll
-  for (int sl = 0; sl < NB / 4; ++sl) {
-    const int q = g + 4 * sl;
-    const bool ok = q < il;
-    const int qc = ok ? q : 0;
-    const double vq = A[rc + (long long)(p + qc) * lda];
-    const double wq = W[rc + (long long)qc * ldw];
-    const double wpq = W[piv + (long long)qc * ldw];
-    const double vpq = A[piv + (long long)(p + qc) * lda];
-    const double u1 = ok ? u[qc] : 0.0, u2 = ok ? u[il + qc] : 0.0;
-    const double m = ok ? 1.0 : 0.0;
-    aw += vq * u1 + wq * u2;
-    ac += m * (vq * wpq + wq * vpq);
+  for (int sl = 0; sl < QW; ++sl) {
+    const int q = g + FW * sl;
+    const int qc = q < il ? q : 0;
+    vq[sl] = A[rc + (long long)(p + qc) * lda];
+    wq[sl] = W[rc + (long long)qc * ldw];
+    wpq[sl] = W[piv + (long long)qc * ldw];
+    vpq[sl] = A[piv + (long long)(p + qc) * lda];
+  }
+  // this wave's share of the pm partial sums and (tiled) of the slots: the
+  // first round of each is loaded before anything is summed, the rest (more
+  // than 64 FW PMU shares or FW SU slots) in further rounds
+  double vp[PMU];
+#pragma unroll
+  for (int q = 0; q < PMU; ++q) {
+    const int k = g * 64 + lane + 64 * FW * q;
+    const double x = pm[k < gm ? k : gm - 1];
+    vp[q] = k < gm ? x : 0.0;
+  }
+  double ya = 0, y0a = 0;
+  int rbase = 0, cbr = 0, nrow = 0;
+  const int ns = nrb + ncb;
+  auto slot = [&](int sq) {
+    const bool ex = sq < ns && (sq < nrb ? cbr < tile_cols(sq, rbase, piv, ncb)
+                                         : sq - nrb < nrow);
+    const double x = P[(long long)(sq < ns ? sq : ns - 1) * ldp + (rc - piv)];
+    return ex ? x : 0.0;
+  };
+  if constexpr (tiled) {
+    rbase = piv & ~1;
+    cbr = (rc - piv) / TC;
+    nrow = tile_cols((rc - rbase) / TR, rbase, piv, ncb);
+    double v[SU];
+#pragma unroll
+    for (int q = 0; q < SU; ++q) v[q] = slot(g + FW * q);
+    // (A22 x)(i+1): the column slots alone (no element lies left of i+1)
+    const int k = g * 64 + lane;
+    const double x0 = P[(long long)(k < nrb ? k : nrb - 1) * ldp];
+    y0a = k < nrb ? x0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < SU; ++q) ya += v[q];
+    for (int sl = g + FW * SU; sl < ns; sl += FW * SU) {
+#pragma unroll
+      for (int q = 0; q < SU; ++q) v[q] = slot(sl + FW * q);
+#pragma unroll
+      for (int q = 0; q < SU; ++q) ya += v[q];
+    }
+    for (int k1 = k + 64 * FW; k1 < nrb; k1 += 64 * FW) y0a += P[(long long)k1 * ldp];
   }
   double ps = 0;
 #pragma unroll
-  for (int q = 0; q < PMU; ++q) ps += pacc[q];
-  const double yv = wave_sum_d(ps);
+  for (int q = 0; q < PMU; ++q) ps += vp[q];
+  for (int k0 = g * 64 + lane + 64 * FW * PMU; k0 < gm; k0 += 64 * FW * PMU) {
+#pragma unroll
+    for (int q = 0; q < PMU; ++q) {
+      const int k = k0 + 64 * FW * q;
+      const double x = pm[k < gm ? k : gm - 1];
+      vp[q] = k < gm ? x : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PMU; ++q) ps += vp[q];
+  }
+  double aw = 0, ac = 0;
+#pragma unroll
+  for (int sl = 0; sl < QW; ++sl) {
+    const int q = g + FW * sl;
+    const bool ok = q < il;
+    const double u1 = ok ? u[q] : 0.0, u2 = ok ? u[il + q] : 0.0;
+    const double m = ok ? 1.0 : 0.0;
+    aw += vq[sl] * u1 + wq[sl] * u2;
+    ac += m * (vq[sl] * wpq[sl] + wq[sl] * vpq[sl]);
+  }
+  sw[g][lane] = aw;
+  scn[g][lane] = ac;
+  if constexpr (tiled) sy[g][lane] = ya;
+  const double psw = wave_sum_d(ps);
+  const double y0w = tiled ? wave_sum_d(y0a) : 0.0;
+  if (lane == 0) {
+    sp[0][g] = psw;
+    sp[1][g] = y0w;
+  }
+  __syncthreads();
+  if (g != 0) return;   // wave 0 holds the rows
+  double yv = 0, x0 = 0, sumw = 0, sumc = 0, sya = 0;
+#pragma unroll
+  for (int k = 0; k < FW; ++k) {
+    yv += sp[0][k];
+    x0 += sp[1][k];
+    sumw += sw[k][lane];
+    sumc += scn[k][lane];
+    if constexpr (tiled) sya += sy[k][lane];
+  }
+  double y0 = y00;
+  if constexpr (tiled) {
+    yv = y00 + 2.0 * scale * x0 + scale * scale * yv;
+    y0 = y00 + scale * x0;
+  }
   const double uu = wave_sum_d(lq ? u1l * u2l : 0.0);
   const double alpha = -0.5 * t * (t * (yv - 2.0 * uu));
   const double wp = t * (y0 - wave_sum_d(lq ? pvl * u1l + pwl * u2l : 0.0)) + alpha;
-  sw[g][lane] = aw;
-  scn[g][lane] = ac;
-  __syncthreads();
   double ssq = 0;
-  if (g == 0 && r < n) {
-    const double sumw = (sw[0][lane] + sw[1][lane]) + (sw[2][lane] + sw[3][lane]);
+  if (r < n) {
+    const double yr = tiled ? yr0 + scale * sya : yr0;
     const double vr = r == piv ? 1.0 : scale * cvr;
     const double wr = r == piv ? wp : t * (yr - sumw) + alpha * vr;
     cv[r] = vr;
     W[r + (long long)il * ldw] = wr;
     if (next) {
-      const double sumc =
-          (scn[0][lane] + scn[1][lane]) + (scn[2][lane] + scn[3][lane]);
       const double cr = cnr - sumc - (vr * wp + wr);   // q = il: V(piv, il) = 1
       cn[r] = cr;
       if (r >= i + 3) ssq = cr * cr;
     }
   }
-  if (next && g == 0) {   // only wave 0 holds rows
+  if (next) {
     const double bs = wave_sum_d(ssq);
     if (lane == 0) part[blockIdx.x] = bs;
   }
@@ -483,8 +740,18 @@ void sytrd_lower(hipStream_t s, rocblas_handle h, int n, double* A,
   const long long ldw = lda;
   const int max_gm = (n + 2 * NB + MV / 64 - 1) / (MV / 64);
   const int max_part = (n + FROWS - 1) / FROWS + 1;
-  DevBuf<double> W((size_t)ldw * NB), y(n), u(2 * NB), sc(n), pm(max_gm),
-      part(max_part);
+  // tiled product (k_mvt) for the columns with L >= LTILE: partial-sum slots
+  // of leading dimension n and one x^T A22 x share per tile
+  int max_tiles = 0, max_slots = 0;
+  for (int k0 = 1; n - k0 >= LTILE; ++k0) {
+    int nrb, ncb;
+    max_tiles = std::max(max_tiles, tile_count(n, k0, nrb, ncb));
+    max_slots = std::max(max_slots, nrb + ncb);
+  }
+  const long long ldP = n;
+  DevBuf<double> W((size_t)ldw * NB), y(n), u(2 * NB), sc(n),
+      pm(std::max(max_gm, max_tiles)), part(max_part),
+      P((size_t)ldP * std::max(max_slots, 1));
   DevBuf<double> Z1((size_t)n * 2 * NB), Z2((size_t)n * 2 * NB);
   OFM_HIP(hipMemsetAsync(W.p, 0, sizeof(double) * ldw * NB, s));
   const double one = 1.0, mone = -1.0;
@@ -496,14 +763,24 @@ void sytrd_lower(hipStream_t s, rocblas_handle h, int n, double* A,
     OFM_HIP(hipGetLastError());
     for (int il = 0; il < b; ++il) {
       const int L = n - (p + il) - 1;
-      const int gm = (L + 2 * il + MV / 64 - 1) / (MV / 64);
       const int gf = (L + FROWS - 1) / FROWS;
-      hipLaunchKernelGGL(k_mv, dim3(gm), dim3(MV), 0, s, A, lda, n, p, il,
-                         W.p, ldw, part.p, np, D, E, tau, sc.p, y.p, u.p,
-                         pm.p);
+      int gm, nrb = 0, ncb = 0;
+      if (L >= LTILE) {
+        gm = tile_count(n, p + il + 1, nrb, ncb);
+        const int gu = std::max(1, (2 * il + 3) / 4);
+        hipLaunchKernelGGL(k_mvt, dim3(gm + gu), dim3(256), 0, s, A, lda, n,
+                           p, il, W.p, ldw, part.p, np, D, E, tau, sc.p, y.p,
+                           u.p, gm, nrb, ncb, P.p, ldP, pm.p);
+      } else {
+        gm = (L + 2 * il + MV / 64 - 1) / (MV / 64);
+        hipLaunchKernelGGL(k_mv, dim3(gm), dim3(MV), 0, s, A, lda, n, p, il,
+                           W.p, ldw, part.p, np, D, E, tau, sc.p, y.p, u.p,
+                           pm.p);
+      }
       OFM_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_fin, dim3(gf), dim3(256), 0, s, A, lda, n, p, il,
-                         b, W.p, ldw, tau, sc.p, y.p, u.p, pm.p, gm, part.p);
+      hipLaunchKernelGGL(nrb > 0 ? k_fin<true> : k_fin<false>, dim3(gf),
+                         dim3(64 * fin_waves(nrb > 0)), 0, s, A, lda, n, p, il, b, W.p, ldw, tau,
+                         sc.p, y.p, u.p, pm.p, gm, part.p, P.p, ldP, nrb, ncb);
       OFM_HIP(hipGetLastError());
       np = gf;
     }
@@ -587,12 +864,16 @@ void dense_eigh(ofm_ctx* c, hipStream_t s, void* blas_handle, int n, double* A,
   hipLaunchKernelGGL(k_pad_copy, dim3(2048), dim3(256), 0, s, A, n, Ap.p, ldp);
   OFM_HIP(hipGetLastError());
   {
-    // the reduction streams the trailing matrix once per column (k_mv):
-    // sum over columns of 8 L (L + 2 il) bytes, L = n - i - 1
+    // the reduction streams the trailing matrix once per column, its lower
+    // triangle (k_mvt, L >= LTILE) or both triangles (k_mv), and the panel's
+    // 2 il columns: 8 (L (L + 1) / 2 + 2 il L) or 8 L (L + 2 il) bytes,
+    // L = n - i - 1
     double bytes = 0;
     for (int i = 0; i + 1 < n; ++i) {
       const double L = n - i - 1;
-      bytes += 8.0 * L * (L + 2.0 * (i % NB));
+      const double il = i % NB;
+      bytes += L >= LTILE ? 8.0 * (L * (L + 1) / 2 + 2.0 * il * L)
+                          : 8.0 * L * (L + 2.0 * il);
     }
     Timed tm(c, "tridiag", bytes, bytes / 4.0);
     sytrd_lower(s, h, n, Ap.p, ldp, w, E.p, tau.p);

@@ -53,10 +53,14 @@ def _check(A, w, Z, w_ref=None):
         assert orth <= 8 * n * EPS
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 31, 32, 33, 34, 64, 65, 97, 300, 1025])
+@pytest.mark.parametrize("n", [1, 2, 3, 31, 32, 33, 34, 64, 65, 97, 300, 1025,
+                               2049, 2056, 2601])
 def test_random_symmetric(ctx, n):
     """Random symmetric matrices: one panel, exact multiples of the panel
-    width (n - 1 reflectors = 31, 63, 64, ...), ragged tails."""
+    width (n - 1 reflectors = 31, 63, 64, ...), ragged tails; from 2049 on
+    the first columns (trailing size >= 2048) take the lower-triangle tiled
+    product: one column (2049), eight (2056), and an odd size with ragged
+    tiles on both edges (2601)."""
     _say("dense eigh random", n)
     rng = np.random.default_rng(1000 + n)
     A = _sym(rng, n)
