@@ -108,6 +108,34 @@ def test_diagonal_and_zero_columns(ctx):
     _check(A, w, Z, np.linalg.eigvalsh(A))
 
 
+def test_zero_columns_in_tiled_columns(ctx):
+    """The same degenerate reflectors where the product runs over the lower
+    triangle in tiles (trailing size >= 2048): zero columns below the
+    diagonal at 3, 31 and 32 (tau = 0 inside and at the end of a panel) of
+    a 2100 x 2100 matrix, and a diagonal 2100 x 2100 matrix (every column
+    zero, every tile product zero)."""
+    n = 2100
+    rng = np.random.default_rng(2100)
+    A = _sym(rng, n) / np.sqrt(n)
+    for c in (3, 31, 32):
+        A[c + 1:, c] = 0
+        A[c, c + 1:] = 0
+    _say("dense eigh zero columns, tiled", n)
+    w, Z = P.ofm_dense_eigh(ctx, A, want_vectors=True)
+    w_ref = np.linalg.eigvalsh(A)
+    tol = 8 * n * EPS * np.abs(w_ref).max()
+    err = np.abs(w - w_ref).max()
+    _say(f"  max|dw|={err:.2e} tol={tol:.2e}")
+    assert err <= tol
+    idx = np.linspace(0, n - 1, 16).astype(int)
+    res = np.linalg.norm(A @ Z[:, idx] - Z[:, idx] * w[idx], axis=0).max()
+    assert res <= tol
+    assert np.abs(Z[:, idx].T @ Z - np.eye(n)[idx]).max() <= 8 * n * EPS
+    d = rng.standard_normal(n)
+    w, _ = P.ofm_dense_eigh(ctx, np.diag(d))
+    assert np.abs(w - np.sort(d)).max() <= 8 * n * EPS * np.abs(d).max()
+
+
 def test_degenerate_spectra(ctx):
     """Zero matrix, identity (one n-fold eigenvalue) and a rank-deficient
     overlap-like Gram matrix B B^T (half its eigenvalues are zero, the
