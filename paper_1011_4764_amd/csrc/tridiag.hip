@@ -372,11 +372,11 @@ inline int tile_count(int n, int k0, int& nrb, int& ncb) {
 
 constexpr int FROWS = 64;   // rows per workgroup of k_fin (one per lane)
 constexpr int PMU = 4;      // partial sums per lane and round in k_fin
-constexpr int SU = 16;      // slot loads per lane and round in k_fin (tiled)
+constexpr int SU = 24;      // slot loads per lane and round in k_fin (tiled)
 
-// waves per workgroup of k_fin: 4 on k_mv's output; 16 on k_mvt's, whose
-// slot sums add several times the loads
-__host__ __device__ constexpr int fin_waves(bool tiled) { return tiled ? 16 : 4; }
+// waves per workgroup of k_fin: 4 on k_mv's output; 8 on k_mvt's, whose
+// slot sums add several times the loads (4 and 16 measured slower there)
+__host__ __device__ constexpr int fin_waves(bool tiled) { return tiled ? 8 : 4; }
 
 // Column i = p + il, rows r = i+1..n-1, FROWS per workgroup of FW waves;
 // wave g sums the panel terms q = g, g+FW, ... < il for its workgroup's
