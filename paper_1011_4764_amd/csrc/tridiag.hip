@@ -94,46 +94,49 @@ __global__ __launch_bounds__(FR) void k_pstart(const double* A, long long lda,
 }
 
 constexpr int MV = 256;   // threads of k_mv (one wave per dot product)
-constexpr int MU = 4;     // double2 loads in flight per lane in k_mv
+constexpr int MU = 4;     // 16-byte pairs per lane and round in col_dot
 
 // One wave: s1 = x(i+1) and sr = sum_{r>=i+2} x(r) c(r) for the column x
 // (rows i+1..n-1), read as 16-byte pairs from the even row rb = (i+1) & ~1
-// (the pair holding row i+1 is formed by lane 0 alone); wave-uniform sums.
+// (pair 0 holds row i+1; lane 0 forms its terms); wave-uniform sums.  The
+// loads are unconditional (indices clamped, the excess selected away), MU
+// pairs per lane and round, so that a column of up to 128 MU rows and the
+// caller's earlier loads take one round trip to memory.
 __device__ __forceinline__ void col_dot(const double* col, const double* c,
                                         int i, int n, int lane, double& s1,
                                         double& sr) {
   const int rb = (i + 1) & ~1;
-  const int npair = (n - rb + 1) >> 1;
+  const int npair = (n - rb + 1) >> 1;   // >= 1
   const double2* a2 = reinterpret_cast<const double2*>(col + rb);
   const double2* c2 = reinterpret_cast<const double2*>(c + rb);
-  s1 = 0;
-  sr = 0;
-  if (lane == 0) {   // pair 0: rows rb, rb+1, one of them is i+1
-    const double2 a = a2[0], cc = c2[0];
-    if (rb == i + 1) {
-      s1 = a.x;
-      sr = a.y * cc.y;
-    } else {
-      s1 = a.y;
-    }
-  }
+  const double2 a0 = a2[0], c0 = c2[0];
   double acc[MU];
 #pragma unroll
   for (int q = 0; q < MU; ++q) acc[q] = 0;
-  int k = 1 + lane;
-  for (; k + 64 * (MU - 1) < npair; k += 64 * MU) {
+  for (int k = 1 + lane; k < npair; k += 64 * MU) {
     double2 a[MU], cc[MU];
 #pragma unroll
     for (int q = 0; q < MU; ++q) {
-      a[q] = a2[k + 64 * q];
-      cc[q] = c2[k + 64 * q];
+      const int kq = k + 64 * q;
+      const int kc = kq < npair ? kq : npair - 1;
+      a[q] = a2[kc];
+      cc[q] = c2[kc];
     }
 #pragma unroll
-    for (int q = 0; q < MU; ++q) acc[q] += a[q].x * cc[q].x + a[q].y * cc[q].y;
+    for (int q = 0; q < MU; ++q) {
+      const double t = a[q].x * cc[q].x + a[q].y * cc[q].y;
+      acc[q] += k + 64 * q < npair ? t : 0.0;
+    }
   }
-  for (; k < npair; k += 64) {
-    const double2 a = a2[k], cc = c2[k];
-    acc[0] += a.x * cc.x + a.y * cc.y;
+  s1 = 0;
+  sr = 0;
+  if (lane == 0) {   // pair 0: rows rb, rb+1, one of them is i+1
+    if (rb == i + 1) {
+      s1 = a0.x;
+      sr = a0.y * c0.y;
+    } else {
+      s1 = a0.y;
+    }
   }
 #pragma unroll
   for (int q = 0; q < MU; ++q) sr += acc[q];
@@ -181,8 +184,7 @@ __global__ __launch_bounds__(MV) void k_mv(
   // the reflector's inputs, loaded with the columns; every wave sums the
   // partial norms itself (same order everywhere, so every wave of every
   // workgroup gets the same value)
-  double ss = 0;
-  for (int k = lane; k < np; k += 64) ss += part[k];
+  const double p0 = part[lane < np ? lane : np - 1];   // np >= 1
   const double alpha = c[i + 1], cii = c[i];
   double s1 = 0, sr = 0, cy = 0;   // x(i+1), sum_{r>=i+2} x(r) c(r), c(ycol)
   int ycol = -1;
@@ -199,6 +201,8 @@ __global__ __launch_bounds__(MV) void k_mv(
     }
     col_dot(col, c, i, n, lane, s1, sr);
   }
+  double ss = lane < np ? p0 : 0.0;
+  for (int k = lane + 64; k < np; k += 64) ss += part[k];   // np > 64: rare
   double t, beta, scale;
   reflector(alpha, wave_sum_d(ss), beta, t, scale);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -262,8 +266,7 @@ __global__ __launch_bounds__(256) void k_mvt(
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if ((int)blockIdx.x >= ntiles) {
     const int uw = ((int)blockIdx.x - ntiles) * 4 + w;
-    double ss = 0;
-    for (int k = lane; k < np; k += 64) ss += part[k];
+    const double p0 = part[lane < np ? lane : np - 1];   // np >= 1
     const double alpha = c[k0], cii = c[i];
     double s1 = 0, sr = 0;
     if (uw < 2 * il) {
@@ -271,6 +274,8 @@ __global__ __launch_bounds__(256) void k_mvt(
                                   : A + (long long)(p + uw - il) * lda;
       col_dot(col, c, i, n, lane, s1, sr);
     }
+    double ss = lane < np ? p0 : 0.0;
+    for (int k = lane + 64; k < np; k += 64) ss += part[k];   // np > 64
     double t, beta, scale;
     reflector(alpha, wave_sum_d(ss), beta, t, scale);
     if ((int)blockIdx.x == ntiles && threadIdx.x == 0) {
