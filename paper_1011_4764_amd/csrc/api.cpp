@@ -27,6 +27,11 @@
 
 using namespace ofm;
 
+std::shared_mutex& ofm::capture_lock() {
+  static std::shared_mutex m;
+  return m;
+}
+
 namespace {
 
 const char* kVersion = "ofm-mi355x 0.1 (gfx950)";
@@ -393,6 +398,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       // the active flags, locks and intervals are read from device memory),
       // so it is captured once and replayed every outer iteration
       if (!sweep_exec) {
+        std::unique_lock<std::shared_mutex> lk(capture_lock());
         hipGraph_t g = nullptr;
         OFM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {

@@ -26,6 +26,7 @@ namespace {
 
 #define OFM_BLAS(call)                                                      \
   do {                                                                      \
+    std::shared_lock<std::shared_mutex> lk_(ofm::capture_lock());           \
     rocblas_status s_ = (call);                                             \
     if (s_ != rocblas_status_success)                                       \
       throw Error{OFM_E_DEVICE, std::string(#call) + " failed: " +          \
@@ -113,6 +114,7 @@ namespace ofm {
 
 void destroy_blas(ofm_ctx* c) {
   if (c && c->blas) {
+    std::shared_lock<std::shared_mutex> lk(capture_lock());
     (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
     c->blas = nullptr;
   }

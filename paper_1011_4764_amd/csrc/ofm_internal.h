@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cstdint>
 #include <map>
+#include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -186,7 +188,16 @@ struct ofm_mats {
 // ---------------------------------------------------------------------------
 // helpers shared by the host files
 // ---------------------------------------------------------------------------
+// Serialises HIP stream capture with rocBLAS / rocSOLVER calls across host
+// threads (contexts driven from several threads at once): a capture in one
+// thread (the fragment sweep's graph) and a call in another that touches the
+// legacy stream (rocBLAS's hipBLASLt back end does, on first use) make that
+// call fail, and hipBLASLt ends the process on the error.  A capture holds
+// this lock exclusively, every rocBLAS / rocSOLVER call shared (calls of
+// different threads still overlap); none is taken inside another.
 namespace ofm {
+
+std::shared_mutex& capture_lock();
 
 struct Error {
   ofm_status code;

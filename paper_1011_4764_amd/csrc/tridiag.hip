@@ -731,6 +731,7 @@ __global__ void k_build_tinv(const double* __restrict__ G, int nb,
 
 #define OFM_BLAS_TD(call)                                                   \
   do {                                                                      \
+    std::shared_lock<std::shared_mutex> lk_(ofm::capture_lock());           \
     rocblas_status s_ = (call);                                             \
     if (s_ != rocblas_status_success)                                       \
       throw Error{OFM_E_DEVICE, std::string(#call) + " failed: " +          \

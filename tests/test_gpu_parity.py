@@ -638,3 +638,56 @@ def test_two_contexts_in_flight_bit_identical(tiny0):
     for o in out:
         for a, b in zip(o, ref):
             assert np.array_equal(a, b)
+
+
+def test_new_contexts_while_another_thread_captures(tiny0):
+    """Contexts created and driven in one thread (each with a fresh rocBLAS
+    handle, whose first calls initialise its back end) while another thread
+    solves fragment sets over and over (each solve captures its sweep as a
+    HIP graph): the library serialises captures with BLAS calls, so both
+    threads finish and every global solve returns the serial eigenvalues."""
+    import threading
+    _say("new contexts while another thread captures")
+    s = tiny0
+
+    def whole(cx):
+        f = _build(cx, s)
+        P.ofm_solve_fragments(cx, f)
+        m = P.ofm_matrix_elements(cx, f)
+        E = P.ofm_solve_global(cx, m, 1e-6)["E"]
+        m.close()
+        f.close()
+        return E
+
+    c0 = P.ofm_create(0, None, P.OFM_FP64)
+    ref = whole(c0)
+    out, err = [], []
+
+    def capturer():
+        try:
+            for _ in range(6):
+                f = _build(c0, s)
+                P.ofm_solve_fragments(c0, f)
+                f.close()
+        except Exception as e:
+            err.append(e)
+
+    def creator():
+        try:
+            for _ in range(4):
+                cx = P.ofm_create(0, None, P.OFM_FP64)
+                out.append(whole(cx))
+                cx.close()
+        except Exception as e:
+            err.append(e)
+
+    th = [threading.Thread(target=capturer), threading.Thread(target=creator)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    c0.close()
+    assert not err, err
+    assert len(out) == 4
+    for E in out:
+        assert np.array_equal(E, ref)
