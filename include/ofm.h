@@ -39,7 +39,10 @@
  *    ofm_frags_info / ofm_fragment_geometry (two-call pattern).
  *  - All device work is enqueued on the context stream; every call that
  *    returns results on the host synchronises that stream first.  A context
- *    and the handles made with it must be used by one host thread at a time.
+ *    and the handles made with it must be used by one host thread at a time;
+ *    different contexts may be driven from different threads at once (the
+ *    library serialises its stream captures with its rocBLAS / rocSOLVER
+ *    calls, which may not overlap across threads).
  *  - The precision form is fixed when the context is created.
  */
 #ifndef OFM_H
