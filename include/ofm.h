@@ -290,9 +290,14 @@ ofm_status ofm_solve_global_subset(ofm_ctx* ctx, const ofm_mats* m,
    column-major, symmetric (both triangles are read; they should agree).
    w: n doubles, host, the eigenvalues in ascending order.  Z: NULL, or n*n
    doubles, host, column k the unit eigenvector of w[k] (each column's sign
-   is arbitrary).  Errors: OFM_E_INVALID for n < 1, n > 65536, a NULL A or
-   w, or a NaN or Inf in A; OFM_E_DEVICE when the tridiagonal solver does
-   not converge; OFM_E_NOMEM. */
+   is arbitrary).  Device memory, freed on return: two copies of A (one
+   with its leading dimension rounded up to 64), with Z also Z and
+   rocSOLVER's divide-and-conquer workspace, and from n = 2049 on the tiled
+   product's partial sums, (n/256 + n/32 + 2) n doubles (about 1/29 of A).
+   Errors:
+   OFM_E_INVALID for n < 1, n > 65536, a NULL A or w, or a NaN or Inf in A;
+   OFM_E_DEVICE when the tridiagonal solver does not converge;
+   OFM_E_NOMEM. */
 ofm_status ofm_dense_eigh(ofm_ctx* ctx, int n, const double* A, double* w,
                           double* Z);
 
