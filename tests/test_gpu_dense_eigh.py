@@ -195,6 +195,29 @@ def test_largest_tested_size_sampled(ctx):
     assert err2 <= tol
 
 
+def test_two_slot_rounds_sampled(ctx):
+    """n = 6000: the first columns' rows take 6000/256 + 6000/32 > 192 partial
+    sums of the tiled product, more than one round of k_fin's slot loads;
+    values (with and without vectors) against LAPACK and 16 sampled
+    eigenpairs."""
+    n = 6000
+    rng = np.random.default_rng(6000)
+    A = _sym(rng, n) / np.sqrt(n)
+    _say("dense eigh", n)
+    w, Z = P.ofm_dense_eigh(ctx, A, want_vectors=True)
+    w_ref = np.linalg.eigvalsh(A)
+    tol = 8 * n * EPS * np.abs(w_ref).max()
+    err = np.abs(w - w_ref).max()
+    _say(f"  max|dw|={err:.2e} tol={tol:.2e}")
+    assert err <= tol
+    idx = np.linspace(0, n - 1, 16).astype(int)
+    res = np.linalg.norm(A @ Z[:, idx] - Z[:, idx] * w[idx], axis=0).max()
+    assert res <= tol
+    assert np.abs(Z[:, idx].T @ Z - np.eye(n)[idx]).max() <= 8 * n * EPS
+    w2, _ = P.ofm_dense_eigh(ctx, A)
+    assert np.abs(w2 - w_ref).max() <= tol
+
+
 def test_dense_eigh_errors(ctx):
     _say("dense eigh errors")
     with pytest.raises(ValueError):
