@@ -7,6 +7,14 @@ eigenpairs (1e-8 Ha); with the oracle's states imported for them, their
 blocks match the oracle's (1e-10 of max|H|); the whole global spectrum
 matches a CPU dense solve of the same blocks (1e-8 Ha).
 
+The amorphous system (10,000 atoms in 20 self-avoiding chains, 1024
+fragments with box edges of 24..40 points per axis and 8..32 states, 20,534
+basis states) in FP64: every fragment converges (boxes whose plane exceeds
+the multi-step kernel's limit run in strips), three overlapping fragments
+match the oracle's eigenpairs (1e-8 Ha) and, with the oracle's states
+imported, their blocks (1e-10 of max|H|); the global solve keeps a basis and
+returns an ascending spectrum.
+
 The polythiophene-like system (4096 overlapping trimer fragments,
 32^3..48^3 boxes, 24 states each, 98,304 basis states) in the mixed form:
 every fragment converges; a sample of three overlapping fragments is checked
@@ -114,6 +122,37 @@ def test_alkane_fp64_full_size():
     samp = [127, 128, 129]   # consecutive windows overlap by half
     checked = _sampled_blocks(ctx, f, V, g, s, samp, 1e-8, 1e-10, eps)
     assert checked == 6
+    f.close()
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_amorphous_fp64_full_size():
+    s = make_system("amorphous", seed=0)
+    V = s.potential()
+    g = s.grid
+    _say("amorphous", g.nx, g.ny, g.nz, s.n_frag, "fragments", s.n_basis,
+         "states")
+    ctx = P.ofm_create(0, None, P.OFM_FP64)
+    f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
+                              s.frag_dims, s.frag_states, origin=g.origin)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0 and cv.all()
+    m = P.ofm_matrix_elements(ctx, f)
+    gs = P.ofm_solve_global(ctx, m, 1e-6)
+    _say("library stage times", ctx.stage_times(),
+         f"iterations max {it.max()}, kept {gs['n_kept']}")
+    assert 0 < gs["n_kept"] <= s.n_basis
+    assert np.all(np.diff(gs["E"]) >= 0) and np.isfinite(gs["E"]).all()
+    m.close()
+    # the three consecutive windows of one chain with the smallest boxes
+    vol = s.frag_dims.prod(1)
+    best = min(range(0, s.n_frag - 2), key=lambda k: vol[k:k + 3].sum())
+    samp = [best, best + 1, best + 2]
+    pj, pn, _ = f.pairs()
+    expect = sum(1 for a, b in zip(pj, pn) if a in samp and b in samp)
+    checked = _sampled_blocks(ctx, f, V, g, s, samp, 1e-8, 1e-10, eps)
+    assert checked == expect >= 5
     f.close()
     ctx.close()
 
