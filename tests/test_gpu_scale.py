@@ -7,6 +7,11 @@ eigenpairs (1e-8 Ha); with the oracle's states imported for them, their
 blocks match the oracle's (1e-10 of max|H|); the whole global spectrum
 matches a CPU dense solve of the same blocks (1e-8 Ha).
 
+The same alkane workload in the mixed form: every fragment converges; three
+overlapping fragments match the oracle's eigenpairs (1e-5 Ha) and, with the
+oracle's states imported, their blocks (1e-6 of max|H|); the eigenvalues in
+the window [E_1, E_1 + 0.3 Ha] of the FP64 run match that run's (1e-5 Ha).
+
 The amorphous system (10,000 atoms in 20 self-avoiding chains, 1024
 fragments with box edges of 24..40 points per axis and 8..32 states, 20,534
 basis states) in FP64: every fragment converges (boxes whose plane exceeds
@@ -124,6 +129,39 @@ def test_alkane_fp64_full_size():
     assert checked == 6
     f.close()
     ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_alkane_mixed_full_size():
+    s = make_system("alkane", seed=0)
+    V = s.potential()
+    g = s.grid
+    _say("alkane mixed", s.n_frag, "fragments", s.n_basis, "states")
+    E = {}
+    for name, prec in (("fp64", P.OFM_FP64), ("mixed", P.OFM_MIXED_BF16X3)):
+        ctx = P.ofm_create(0, None, prec)
+        f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
+                                  s.frag_dims, s.frag_states, origin=g.origin)
+        st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+        assert st == 0 and cv.all()
+        m = P.ofm_matrix_elements(ctx, f)
+        E[name] = P.ofm_solve_global(ctx, m, 1e-6)["E"]
+        m.close()
+        _say(f"  {name}: iterations max {it.max()}, kept {len(E[name])}")
+        if name == "mixed":
+            checked = _sampled_blocks(ctx, f, V, g, s, [127, 128, 129], 1e-5,
+                                      1e-6, eps)
+            assert checked == 6
+        f.close()
+        ctx.close()
+    lo, hi = E["fp64"][0], E["fp64"][0] + 0.3
+    w64 = E["fp64"][(E["fp64"] >= lo) & (E["fp64"] <= hi)]
+    wmx = E["mixed"][(E["mixed"] >= lo - 1e-5) & (E["mixed"] <= hi + 1e-5)]
+    assert len(wmx) == len(w64) > 0
+    err = np.abs(wmx - w64).max()
+    _say(f"  window [{lo:.4f}, {hi:.4f}] Ha: {len(w64)} eigenvalues, "
+         f"max |E_mixed - E_fp64| {err:.2e} Ha")
+    assert err < 1e-5
 
 
 @pytest.mark.timeout(600)
