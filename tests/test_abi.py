@@ -95,3 +95,17 @@ def test_null_handles_rejected_without_a_gpu():
         checked += 1
     assert checked == len(_declared()) - len(skip)
     assert isinstance(L.ofm_last_error(None), bytes)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it says so and exits with
+    status 2 before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    assert r.stdout.strip() == ""
