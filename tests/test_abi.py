@@ -100,7 +100,6 @@ def test_null_handles_rejected_without_a_gpu():
 def test_bench_refuses_more_than_one_gpu():
     """bench.py measures one GPU: asked for more it says so and exits with
     status 2 before touching a device."""
-    import subprocess
     import sys
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"),
