@@ -186,21 +186,36 @@ ofm_status ofm_pairs(const ofm_frags* f, int* pair_j, int* pair_n,
 ofm_status ofm_solve_fragments(ofm_ctx* ctx, ofm_frags* f,
                                const ofm_solve_opts* opts, double* eps,
                                int* iters, unsigned char* converged);
+/* Per-fragment flags of the last ofm_solve_fragments (n_frag ints, host):
+   bit 0 -- the Cholesky factorisation of a CholQR Gram matrix lost a pivot
+            and the shifted factorisation (G + 1e-12 b_j I after unit-diagonal
+            scaling) was used at least once;
+   bit 1 -- the shifted factorisation lost a pivot as well (the block was
+            numerically rank deficient); such a fragment is reported as not
+            converged and the solve returns OFM_E_NOCONV.
+   All zero before the first solve.  Errors: OFM_E_INVALID for NULL. */
+ofm_status ofm_solve_flags(const ofm_frags* f, int* flags);
 /* States of fragment j: phi is s_j*n_j doubles, state-major (state i at
    phi + i*n_j, points x fastest); eps is s_j doubles.  Host.  Sign gauge:
    the largest-|.| component of every state is positive (first on ties). */
 ofm_status ofm_get_states(const ofm_frags* f, int j, double* phi, double* eps);
 /* Import states for fragment j (same layout; host), e.g. to evaluate matrix
    elements for externally computed states or to resume.  The whole-system
-   H|phi> is recomputed for j.  Rows are used as given (no orthonormalisation).
- */
+   H|phi> is recomputed for j.  Rows are used as given (no orthonormalisation):
+   S_jj of an imported fragment is computed from its states in both forms
+   (in the mixed form with FP64 products on the FP32-stored states), whereas
+   the mixed form takes S_jj = I for states that ofm_solve_fragments
+   orthonormalised in FP64. */
 ofm_status ofm_set_states(ofm_frags* f, int j, const double* phi,
                           const double* eps);
 /* H|phi> of fragment j with the whole-system H on its dilated box: s_j *
    (ddims product) doubles, state-major, x fastest (host). */
 ofm_status ofm_get_hphi(const ofm_frags* f, int j, double* hphi);
 /* Apply the fragment Hamiltonian H_j to nvec vectors of box j (state-major,
-   host in and out): the stencil of the eigensolver, exposed for checking. */
+   host in and out): the stencil of the eigensolver, exposed for checking.
+   Errors: OFM_E_INVALID for nvec outside [1, OFM_MAX_APPLY_VECTORS], j out
+   of range or a NULL buffer (no device work is done then). */
+#define OFM_MAX_APPLY_VECTORS 32767
 ofm_status ofm_apply_fragment_h(ofm_ctx* ctx, ofm_frags* f, int j, int nvec,
                                 const double* x, double* y);
 

@@ -463,20 +463,31 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   std::vector<double> theta(f->th_total);
   std::vector<int> it_h(nf);
   std::vector<unsigned char> cv(nf);
+  f->solve_flags.assign(nf, 0);
   OFM_HIP(hipMemcpyAsync(theta.data(), f->d_theta, sizeof(double) * theta.size(),
                          hipMemcpyDeviceToHost, s));
   OFM_HIP(hipMemcpyAsync(it_h.data(), f->d_iters, sizeof(int) * nf,
                          hipMemcpyDeviceToHost, s));
   OFM_HIP(hipMemcpyAsync(cv.data(), f->d_conv, nf, hipMemcpyDeviceToHost, s));
+  OFM_HIP(hipMemcpyAsync(f->solve_flags.data(), f->d_flags, sizeof(int) * nf,
+                         hipMemcpyDeviceToHost, s));
   OFM_HIP(hipStreamSynchronize(s));
   collect_stats(c);
   f->eps_host.assign(f->n_basis, 0.0);
   bool all = true;
+  int n_rank = 0;
   for (int j = 0; j < nf; ++j) {
     const auto& d = f->host[j];
     for (int i = 0; i < d.n_states; ++i)
       f->eps_host[d.basis_off + i] = theta[d.th_off + i];
+    // a block that stayed rank deficient after the shifted factorisation
+    // cannot be trusted to be orthonormal: not converged
+    if (f->solve_flags[j] & 2) {
+      cv[j] = 0;
+      ++n_rank;
+    }
     all = all && cv[j];
+    f->solver_states[j] = 1;
   }
   if (eps) std::memcpy(eps, f->eps_host.data(), sizeof(double) * f->n_basis);
   if (iters) std::memcpy(iters, it_h.data(), sizeof(int) * nf);
@@ -484,6 +495,10 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   f->have_states = true;
   if (!all) {
     c->err = "eigensolver reached max_iter before every fragment converged";
+    if (n_rank)
+      c->err += "; " + std::to_string(n_rank) +
+                " fragment(s) kept a rank-deficient block after the shifted "
+                "Cholesky factorisation (ofm_solve_flags bit 1)";
     return OFM_E_NOCONV;
   }
   return OFM_OK;
@@ -571,6 +586,8 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
     try {
       plan_fragments(f, *grid, n_frag, frags, OFM_GUARD_VECTORS);
       plan_pairs(f, atom_xyz, frag_atom_ptr, frag_atom_idx, d_cut);
+      f->solver_states.assign(n_frag, 0);
+      f->solve_flags.assign(n_frag, 0);
       // tile lists
       std::vector<int2> stiles, rtiles;
       int th = 0;
@@ -790,6 +807,13 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
   });
 }
 
+ofm_status ofm_solve_flags(const ofm_frags* f, int* flags) {
+  if (!f || !flags) return OFM_E_INVALID;
+  for (int j = 0; j < f->n_frag; ++j)
+    flags[j] = j < (int)f->solve_flags.size() ? f->solve_flags[j] : 0;
+  return OFM_OK;
+}
+
 ofm_status ofm_get_states(const ofm_frags* f, int j, double* phi,
                           double* eps) {
   if (!f || j < 0 || j >= f->n_frag) return OFM_E_INVALID;
@@ -843,6 +867,7 @@ ofm_status ofm_set_states(ofm_frags* f, int j, const double* phi,
     if (f->eps_host.size() != (size_t)f->n_basis) f->eps_host.assign(f->n_basis, 0.0);
     for (int i = 0; i < d.n_states; ++i)
       f->eps_host[d.basis_off + i] = eps ? eps[i] : 0.0;
+    f->solver_states[j] = 0;
     f->have_states = true;
     return OFM_OK;
   });
@@ -875,8 +900,11 @@ ofm_status ofm_apply_fragment_h(ofm_ctx* c, ofm_frags* f, int j, int nvec,
                                 const double* x, double* y) {
   if (!c) return OFM_E_INVALID;
   return guarded(c, [&]() -> ofm_status {
-    OFM_REQUIRE(f && f->ctx == c && j >= 0 && j < f->n_frag && nvec >= 1 && x && y,
+    OFM_REQUIRE(f && f->ctx == c && j >= 0 && j < f->n_frag && x && y,
                 OFM_E_INVALID, "bad arguments");
+    // the stencil's tiles carry the vector index in 15 bits
+    OFM_REQUIRE(nvec >= 1 && nvec <= OFM_MAX_APPLY_VECTORS, OFM_E_INVALID,
+                "nvec must be in [1, 32767]");
     use_device(c);
     const FragDev& d = f->host[j];
     const size_t w = wsize(c);
@@ -1024,11 +1052,39 @@ ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {
       m->states.push_back(d.n_states);
       m->basis_off.push_back(d.basis_off);
     }
+    // mixed form: the diagonal S block of solver-orthonormalised states is
+    // the identity; for imported states it is computed with FP64 products
+    // (a separate task list, launched after the grouped contraction)
+    std::vector<PairTask> diag_s;
+    if (c->precision != OFM_FP64) {
+      std::vector<PairTask> rest;
+      rest.reserve(tasks.size());
+      for (auto& t : tasks) {
+        if (t.sym && t.which == 0) {
+          const int j = (int)(std::lower_bound(f->block_off.begin(),
+                                               f->block_off.end(), t.c_off) -
+                              f->block_off.begin());
+          if (!f->solver_states[f->pair_j[j]]) {
+            diag_s.push_back(t);
+            continue;
+          }
+          t.ident = 1;
+        }
+        rest.push_back(t);
+      }
+      tasks.swap(rest);
+    }
     PairTask* dt = nullptr;
+    PairTask* dt2 = nullptr;
     try {
       m->d_H = dev_alloc<double>(f->n_values);
       m->d_S = dev_alloc<double>(f->n_values);
       dt = dev_alloc<PairTask>(tasks.size());
+      dt2 = dev_alloc<PairTask>(diag_s.size());
+      if (!diag_s.empty())
+        OFM_HIP(hipMemcpyAsync(dt2, diag_s.data(),
+                               sizeof(PairTask) * diag_s.size(),
+                               hipMemcpyHostToDevice, c->stream));
       hipStream_t s = c->stream;
       OFM_HIP(hipMemsetAsync(m->d_H, 0, sizeof(double) * f->n_values, s));
       OFM_HIP(hipMemsetAsync(m->d_S, 0, sizeof(double) * f->n_values, s));
@@ -1048,20 +1104,26 @@ ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {
         k::pair_elements<double>(c, f, dt, (int)tasks.size(),
                                  arena<double>(f->d_x), arena<double>(f->d_hphi),
                                  m->d_H, m->d_S, flops, bytes);
-      else
+      else {
         k::pair_elements<float>(c, f, dt, (int)tasks.size(),
                                 arena<float>(f->d_x), arena<float>(f->d_hphi),
                                 m->d_H, m->d_S, flops, bytes);
+        k::pair_elements_f64_on_f32(c, f, dt2, (int)diag_s.size(),
+                                    arena<float>(f->d_x),
+                                    arena<float>(f->d_hphi), m->d_H, m->d_S);
+      }
       OFM_HIP(hipStreamSynchronize(s));
       collect_stats(c);
     } catch (...) {
       dev_free(dt);
+      dev_free(dt2);
       dev_free(m->d_H);
       dev_free(m->d_S);
       delete m;
       throw;
     }
     dev_free(dt);
+    dev_free(dt2);
     c->t_elem = now_ms() - t0;
     c->live += 1;
     *out = m;

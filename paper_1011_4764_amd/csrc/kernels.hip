@@ -457,8 +457,14 @@ __global__ __launch_bounds__(WG) void k_cholinv(
       }
       __syncthreads();
     }
-    if (!fail) break;
-    if (threadIdx.x == 0 && flags) atomicOr(&flags[j], 1);
+    // every thread takes the verdict into a register, and all of them have
+    // taken it before thread 0 may reset `fail` for the shifted attempt
+    const int failed = fail;
+    __syncthreads();
+    if (!failed) break;
+    // bit 0: the shifted factorisation was needed; bit 1: it lost a pivot
+    // as well (the block is numerically rank deficient)
+    if (threadIdx.x == 0 && flags) atomicOr(&flags[j], attempt == 0 ? 1 : 2);
   }
   // inverse of the upper-triangular factor, one column per thread
   double* Qj = Q + fr.small_off;
@@ -1044,11 +1050,13 @@ __device__ __forceinline__ void pair_store(const PairTask& tk,
   }
 }
 
-// FP64 MFMA 16x16x4; RMAX >= the largest state count, a multiple of 16
-template <int RMAX>
+// FP64 MFMA 16x16x4; RMAX >= the largest state count, a multiple of 16.
+// TI is the storage type of the operands (FP32 operands are widened to FP64
+// when staged, so the products and sums are FP64 either way).
+template <int RMAX, typename TI>
 __global__ __launch_bounds__(WG) void k_pair(
     const PairTask* __restrict__ tasks, int ntask,
-    const double* __restrict__ PHI, const double* __restrict__ HPHI,
+    const TI* __restrict__ PHI, const TI* __restrict__ HPHI,
     double* __restrict__ Hout, double* __restrict__ Sout) {
   constexpr int KST = 64, LP = KST + 1;
   constexpr int UMAX = (RMAX / 16) * (RMAX / 16) > 4
@@ -1056,8 +1064,8 @@ __global__ __launch_bounds__(WG) void k_pair(
   const int ti = blockIdx.x;
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
-  const double* A = PHI + tk.a_off;
-  const double* B = (tk.which ? HPHI : PHI) + tk.b_off;
+  const TI* A = PHI + tk.a_off;
+  const TI* B = (tk.which ? HPHI : PHI) + tk.b_off;
   double* C = (tk.which ? Hout : Sout) + tk.c_off;
   const int gx = (tk.om[0] + 3) >> 2;
   const long long ngrp = (long long)gx * tk.om[1] * tk.om[2];
@@ -1082,8 +1090,10 @@ __global__ __launch_bounds__(WG) void k_pair(
 #pragma unroll
     for (int m = 0; m < RMAX / (WG / KST); ++m) {
       const int i = i0 + (WG / KST) * m;
-      As[i * LP + pt] = (valid && i < tk.ma) ? A[(long long)i * tk.lda + ia] : 0.0;
-      Bs[i * LP + pt] = (valid && i < tk.mb) ? B[(long long)i * tk.ldb + ib] : 0.0;
+      As[i * LP + pt] =
+          (valid && i < tk.ma) ? (double)A[(long long)i * tk.lda + ia] : 0.0;
+      Bs[i * LP + pt] =
+          (valid && i < tk.mb) ? (double)B[(long long)i * tk.ldb + ib] : 0.0;
     }
     stage_advance(sp, KST / 4, gx, tk.om[1]);
     __syncthreads();
@@ -1137,9 +1147,10 @@ __global__ __launch_bounds__(WG) void k_pair(
 }
 
 // mixed form of the pair contraction: split-BF16 x3 MFMA 16x16x32 on FP32
-// states, FP32 sums of a stage flushed into FP64; diagonal S blocks are the
-// identity (the states are orthonormalised in FP64, and the dropped
-// a_lo b_lo term would bias their diagonal by ~2^-18)
+// states, FP32 sums of a stage flushed into FP64; the diagonal S block of a
+// fragment whose states the solver orthonormalised in FP64 is the identity
+// (tasks marked `ident`; the dropped a_lo b_lo term would bias its diagonal
+// by ~2^-18), imported states get theirs from k_pair<.., float>
 template <int RMAX>
 __global__ __launch_bounds__(WG) void k_pair_x3(
     const PairTask* __restrict__ tasks, int ntask,
@@ -1152,7 +1163,7 @@ __global__ __launch_bounds__(WG) void k_pair_x3(
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
   double* C = (tk.which ? Hout : Sout) + tk.c_off;
-  if (tk.sym && tk.which == 0) {
+  if (tk.ident) {
     for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG)
       C[e] = (e / tk.mb == e % tk.mb) ? 1.0 : 0.0;
     return;
@@ -1265,7 +1276,8 @@ void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
 #define PAIR(R)                                                              \
   do {                                                                       \
     if constexpr (sizeof(T) == 8)                                            \
-      hipLaunchKernelGGL(k_pair<R>, dim3(n_tasks), dim3(WG), 0, c->stream,   \
+      hipLaunchKernelGGL((k_pair<R, double>), dim3(n_tasks), dim3(WG), 0,    \
+                         c->stream,                                          \
                          tasks, n_tasks, (const double*)phi,                 \
                          (const double*)hphi, H, S);                         \
     else                                                                     \
@@ -1278,6 +1290,23 @@ void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
   else if (rm == 48) PAIR(48);
   else PAIR(64);
 #undef PAIR
+  OFM_HIP(hipGetLastError());
+}
+void pair_elements_f64_on_f32(ofm_ctx* c, const ofm_frags* f,
+                              const PairTask* tasks, int n_tasks,
+                              const float* phi, const float* hphi, double* H,
+                              double* S) {
+  if (n_tasks <= 0) return;
+  const int rm = f->max_states <= 16 ? 16 : f->max_states <= 32 ? 32
+               : f->max_states <= 48 ? 48 : 64;
+#define PAIRF(R)                                                             \
+  hipLaunchKernelGGL((k_pair<R, float>), dim3(n_tasks), dim3(WG), 0,         \
+                     c->stream, tasks, n_tasks, phi, hphi, H, S)
+  if (rm == 16) PAIRF(16);
+  else if (rm == 32) PAIRF(32);
+  else if (rm == 48) PAIRF(48);
+  else PAIRF(64);
+#undef PAIRF
   OFM_HIP(hipGetLastError());
 }
 template void pair_elements<double>(ofm_ctx*, const ofm_frags*,

@@ -62,6 +62,9 @@ struct PairTask {
   int ma, mb;
   int sym;                  // 1: diagonal block, symmetrise on write
   int which;                // 0: S block, 1: H block
+  int ident;                // mixed form: write the identity (diagonal S
+                            // block of solver-orthonormalised states)
+  int pad;
 };
 
 // per-fragment Chebyshev filter state (device)
@@ -170,7 +173,12 @@ struct ofm_frags {
   int* d_nactive = nullptr;
   std::vector<double> eps_host;  // sum_j s_j, valid when have_states
   bool have_states = false;
-  bool imported = false;
+  // per fragment: 1 when its states come from ofm_solve_fragments (FP64
+  // CholQR-orthonormal), 0 when imported with ofm_set_states
+  std::vector<char> solver_states;
+  // per fragment after a solve: bit 0 the CholQR Gram needed the shifted
+  // Cholesky factorisation, bit 1 that one lost a pivot too
+  std::vector<int> solve_flags;
 };
 
 struct ofm_mats {
@@ -341,6 +349,12 @@ template <typename T>
 void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
                    int n_tasks, const T* phi, const T* hphi, double* H,
                    double* S, double flops, double bytes);
+// FP64 MFMA products on FP32 operands (mixed form: diagonal S blocks of
+// imported states)
+void pair_elements_f64_on_f32(ofm_ctx* c, const ofm_frags* f,
+                              const PairTask* tasks, int n_tasks,
+                              const float* phi, const float* hphi, double* H,
+                              double* S);
 template <typename T>
 void convert(hipStream_t s, const double* in, T* out, long long n);
 template <typename T>

@@ -34,8 +34,9 @@ EXPORTS = [
     "ofm_kernel_stats", "ofm_reset_stats", "ofm_stage_times",
     "ofm_set_stencil_variant", "ofm_set_fragment_wells", "ofm_select_homo",
     "ofm_solve_global_subset", "ofm_homo_energies", "ofm_homo_lumo_gap",
-    "ofm_dense_eigh",
+    "ofm_dense_eigh", "ofm_solve_flags",
 ]
+OFM_MAX_APPLY_VECTORS = 32767
 
 
 class OfmGrid(C.Structure):
@@ -94,6 +95,7 @@ def lib():
             "ofm_pairs": ([_P, _I, _I, _LL], C.c_int),
             "ofm_solve_fragments": ([_P, _P, C.POINTER(OfmSolveOpts), _D, _I,
                                      C.POINTER(C.c_ubyte)], C.c_int),
+            "ofm_solve_flags": ([_P, _I], C.c_int),
             "ofm_get_states": ([_P, C.c_int, _D, _D], C.c_int),
             "ofm_set_states": ([_P, C.c_int, _D, _D], C.c_int),
             "ofm_get_hphi": ([_P, C.c_int, _D], C.c_int),
@@ -309,6 +311,15 @@ def ofm_solve_fragments(ctx: Context, frags: Fragments, tol=0.0, max_iter=0,
     if st != OFM_E_NOCONV or raise_on_noconv:
         _check(st, ctx.handle)
     return st, eps, it, cv.astype(bool)
+
+
+def ofm_solve_flags(frags: Fragments):
+    """Per-fragment flags of the last solve (bit 0: shifted Cholesky used,
+    bit 1: shifted Cholesky lost a pivot too)."""
+    fl = np.zeros(frags.n_frag, np.int32)
+    _check(lib().ofm_solve_flags(frags.handle, fl.ctypes.data_as(_I)),
+           frags.ctx.handle)
+    return fl
 
 
 def ofm_get_states(frags: Fragments, j):

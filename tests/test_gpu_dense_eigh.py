@@ -155,6 +155,55 @@ def test_degenerate_spectra(ctx):
     assert np.abs(w[:65]).max() <= 8 * 130 * EPS * w[-1]
 
 
+def _glued_wilkinson(m, copies, glue):
+    """`copies` Wilkinson W_m^+ matrices (diagonal |k - (m-1)/2|, unit
+    off-diagonal) glued by off-diagonal entries `glue`: its eigenvalues come
+    in pairs and clusters closer than 1e-13."""
+    d = np.abs(np.arange(m) - (m - 1) / 2.0)
+    D = np.tile(d, copies)
+    E = np.ones(m * copies - 1)
+    E[m - 1::m] = glue
+    return np.diag(D) + np.diag(E, 1) + np.diag(E, -1)
+
+
+@pytest.mark.parametrize("glue", [1e-8, 1e-14])
+def test_glued_wilkinson_clusters(ctx, glue):
+    """Glued Wilkinson matrices (tight pairs and clusters of eigenvalues):
+    every eigenvalue is bracketed independently on the Sturm count, so the
+    count must be monotone in x for the results to come out ascending with
+    none counted twice or missed.  Values against LAPACK within the bound,
+    ascending, and the multiplicity of each cluster preserved."""
+    A = _glued_wilkinson(21, 20, glue)
+    n = A.shape[0]
+    _say("dense eigh glued Wilkinson", n, "glue", glue)
+    w_ref = np.linalg.eigvalsh(A)
+    w, Z = P.ofm_dense_eigh(ctx, A, want_vectors=True)
+    _check(A, w, Z, w_ref)
+    # cluster sizes agree (a doubly counted or missed eigenvalue changes one)
+    tol = 8 * n * EPS * np.abs(w_ref).max()
+    for c in np.unique(np.round(w_ref, 6)):
+        assert np.count_nonzero(np.abs(w - c) < 5e-7) == \
+            np.count_nonzero(np.abs(w_ref - c) < 5e-7)
+    assert np.abs(w - w_ref).max() <= tol
+
+
+def test_clustered_spectrum(ctx):
+    """Many eigenvalues within a few ulps of each other in a random basis
+    (three clusters of 60 plus spread values)."""
+    n = 300
+    rng = np.random.default_rng(9)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([1.0 + 1e-15 * rng.standard_normal(60),
+                          -2.0 + 1e-15 * rng.standard_normal(60),
+                          0.25 + 1e-15 * rng.standard_normal(60),
+                          rng.uniform(-3, 3, n - 180)])
+    A = (Q * lam) @ Q.T
+    A = (A + A.T) / 2
+    _say("dense eigh clustered")
+    w, Z = P.ofm_dense_eigh(ctx, A, want_vectors=True)
+    _check(A, w, Z, np.linalg.eigvalsh(A))
+
+
 def test_wide_dynamic_range(ctx):
     """Eigenvalues spread over 1e-10 .. 1 in a random orthonormal basis:
     the small ones come out within the absolute bound set by ||A||."""

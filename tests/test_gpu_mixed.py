@@ -103,6 +103,65 @@ def test_mixed_elements_imported_states(mctx, case):
         k += sz
 
 
+def test_mixed_diag_s_of_non_orthonormal_imports(mctx, tiny0):
+    """Imported states are used as given: in the mixed form a fragment whose
+    states were imported gets S_jj = Phi_j^T Phi_j (FP64 products on its
+    FP32-stored states), not the identity the solver's FP64-orthonormalised
+    states receive.  Non-orthonormal imports (oracle states mixed by a
+    random non-orthogonal matrix) are checked against the brute-force Gram
+    matrix of the same FP32-rounded states; off-diagonal and H blocks keep
+    the mixed bound.  After a solve the diagonal S blocks are I again."""
+    _say("mixed: diagonal S of non-orthonormal imports")
+    s = tiny0
+    V = s.potential()
+    r = O.run(V, 0.5, s.frag_lo, s.frag_dims, s.frag_states, solve=False)
+    rng = np.random.default_rng(17)
+    mix = [np.eye(6) + 0.3 * rng.standard_normal((6, 6)) for _ in range(3)]
+    phi = [r.phi[j] @ mix[j] for j in range(3)]
+    f = _build(mctx, s)
+    for j in range(3):
+        P.ofm_set_states(f, j, phi[j].T)
+    pj, pn, off = f.pairs()
+    m = P.ofm_matrix_elements(mctx, f)
+    H, S = P.ofm_mats_copy(m)
+    m.close()
+    hp = {}
+    for j in range(3):
+        dlo, dd, h_ = O.apply_whole_H(V, 0.5, s.frag_lo[j], s.frag_dims[j],
+                                      phi[j])
+        hp[j] = (h_, (dlo, dd))
+    for p in range(len(pj)):
+        j, n = int(pj[p]), int(pn[p])
+        Sb, Hb, _ = O.pair_blocks(j, n, s.frag_lo, s.frag_dims, phi,
+                                  {k: hp[k][0] for k in hp},
+                                  {k: hp[k][1] for k in hp})
+        gS = S[off[p]:off[p] + 36].reshape(6, 6)
+        gH = H[off[p]:off[p] + 36].reshape(6, 6)
+        if j == n:
+            Hb = 0.5 * (Hb + Hb.T)
+            p32 = phi[j].astype(np.float32).astype(np.float64)
+            ref = p32.T @ p32
+            es = np.abs(gS - ref).max() / np.abs(ref).max()
+            _say(f"  S_{j}{j} vs Gram of the FP32 states: {es:.2e}")
+            assert es < 1e-12
+            assert np.abs(gS - np.eye(6)).max() > 0.1   # not the identity
+        else:
+            es = np.abs(gS - Sb).max() / max(np.abs(Sb).max(), 1e-300)
+            assert es < 1e-6
+        eh = np.abs(gH - Hb).max() / np.abs(Hb).max()
+        assert eh < 1e-6
+    st, eps, it, cv = P.ofm_solve_fragments(mctx, f)
+    assert st == 0
+    m = P.ofm_matrix_elements(mctx, f)
+    H, S = P.ofm_mats_copy(m)
+    m.close()
+    for p in range(len(pj)):
+        if pj[p] == pn[p]:
+            assert np.array_equal(S[off[p]:off[p] + 36].reshape(6, 6),
+                                  np.eye(6))
+    f.close()
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_mixed_end_to_end_tiny(mctx, seed):
     s = tiny_chain(seed)

@@ -243,6 +243,59 @@ def test_error_paths(ctx, tiny0):
     assert st == P.OFM_E_NOCONV and not cv.all()
 
 
+def test_apply_rejects_too_many_vectors(ctx, tiny0):
+    """nvec above OFM_MAX_APPLY_VECTORS (the stencil's tiles carry the vector
+    index in 15 bits) is rejected before any device work; the buffers are
+    never read, so a one-element buffer suffices."""
+    import ctypes as C
+    _say("apply: nvec bound")
+    f = _build(ctx, tiny0)
+    one = np.zeros(1)
+    dp = one.ctypes.data_as(C.POINTER(C.c_double))
+    for nvec in (P.OFM_MAX_APPLY_VECTORS + 1, 1 << 20, 0, -1):
+        st = P.lib().ofm_apply_fragment_h(ctx.handle, f.handle, 0, nvec, dp, dp)
+        assert st == P.OFM_E_INVALID, nvec
+    # the context stays usable
+    x = np.random.default_rng(0).standard_normal((2, 12 ** 3))
+    y = P.ofm_apply_fragment_h(ctx, f, 0, x)
+    H = O.hamiltonian_box(tiny0.potential(), 0.5, tiny0.frag_lo[0],
+                          tiny0.frag_dims[0])
+    assert np.abs(y - (H @ x.T).T).max() < 1e-12 * np.abs(y).max()
+
+
+def test_shifted_cholesky_flagged_and_converges(ctx, tiny0):
+    """A filter of degree 128 on small boxes (8^3, 4 states, block of 12)
+    makes the filtered block numerically rank deficient, so the CholQR
+    Cholesky loses a pivot and the shifted factorisation takes over (a CPU
+    model of the solver flags 15 of 16 such boxes and converges on all).
+    The solve reports it per fragment in ofm_solve_flags (bit 0), no block
+    stays rank deficient (bit 1), and every fragment converges to the
+    oracle's eigenvalues.  A default solve afterwards clears the flags."""
+    _say("shifted Cholesky path, degree 128")
+    V = tiny0.potential()
+    lo = [(2 * k, 2, 2) for k in range(8)]
+    dims = [(8, 8, 8)] * 8
+    st = [4] * 8
+    s = box_system((24, 12, 12), 0.5, lo, dims, st, V=V)
+    f = _build(ctx, s)
+    assert (P.ofm_solve_flags(f) == 0).all()
+    status, eps, it, cv = P.ofm_solve_fragments(ctx, f, degree=128)
+    fl = P.ofm_solve_flags(f)
+    _say("  flags", fl.tolist(), "iterations", it.tolist())
+    assert status == 0 and cv.all()
+    assert (fl & 1).any()
+    assert not (fl & 2).any()
+    for j in range(8):
+        e_o, _ = O.fragment_states(V, 0.5, lo[j], dims[j], 4)
+        assert np.abs(eps[4 * j:4 * j + 4] - e_o).max() < 1e-8
+    status, eps2, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert status == 0 and cv.all()
+    assert np.abs(eps2 - eps).max() < 1e-8
+    fl2 = P.ofm_solve_flags(f)
+    _say("  flags at the default degree", fl2.tolist())
+    assert not (fl2 & 2).any()
+
+
 # ------------------------------------------------------------------ global solve
 
 def _run_path(ctx, lo, dims, st, V, h=0.5):

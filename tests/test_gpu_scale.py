@@ -10,15 +10,17 @@ matches a CPU dense solve of the same blocks (1e-8 Ha).
 The same alkane workload in the mixed form: every fragment converges; three
 overlapping fragments match the oracle's eigenpairs (1e-5 Ha) and, with the
 oracle's states imported, their blocks (1e-6 of max|H|); the eigenvalues in
-the window [E_1, E_1 + 0.3 Ha] of the FP64 run match that run's (1e-5 Ha).
+the window [E_1, E_1 + 0.3 Ha] of the FP64 run match that run's (1e-5 Ha);
+the kept counts of S differ by no more than Weyl's inequality allows.
 
 The amorphous system (10,000 atoms in 20 self-avoiding chains, 1024
 fragments with box edges of 24..40 points per axis and 8..32 states, 20,534
-basis states) in FP64: every fragment converges (boxes whose plane exceeds
-the multi-step kernel's limit run in strips), three overlapping fragments
-match the oracle's eigenpairs (1e-8 Ha) and, with the oracle's states
-imported, their blocks (1e-10 of max|H|); the global solve keeps a basis and
-returns an ascending spectrum.
+basis states) in FP64: every fragment converges, three overlapping
+fragments match the oracle's eigenpairs (1e-8 Ha) and, with the oracle's
+states imported, their blocks (1e-10 of max|H|); the window's eigenpairs
+pass the validity checks of the thresholded pencil on the GPU's blocks.  In
+the mixed form: sampled fragments and blocks against the oracle (1e-5 Ha,
+1e-6), the FP64 window within 1e-5 Ha, kept counts within the Weyl bound.
 
 The polythiophene-like system (4096 overlapping trimer fragments,
 32^3..48^3 boxes, 24 states each, 98,304 basis states) in the mixed form:
@@ -137,7 +139,7 @@ def test_alkane_mixed_full_size():
     V = s.potential()
     g = s.grid
     _say("alkane mixed", s.n_frag, "fragments", s.n_basis, "states")
-    E = {}
+    E, kept, Ssp = {}, {}, {}
     for name, prec in (("fp64", P.OFM_FP64), ("mixed", P.OFM_MIXED_BF16X3)):
         ctx = P.ofm_create(0, None, prec)
         f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
@@ -145,9 +147,12 @@ def test_alkane_mixed_full_size():
         st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
         assert st == 0 and cv.all()
         m = P.ofm_matrix_elements(ctx, f)
-        E[name] = P.ofm_solve_global(ctx, m, 1e-6)["E"]
+        gs = P.ofm_solve_global(ctx, m, 1e-6)
+        E[name], kept[name] = gs["E"], gs["n_kept"]
+        Hb, Sb = P.ofm_mats_copy(m)
+        Ssp[name] = _sparse_pencil(f, Hb, Sb)[1]
         m.close()
-        _say(f"  {name}: iterations max {it.max()}, kept {len(E[name])}")
+        _say(f"  {name}: iterations max {it.max()}, kept {kept[name]}")
         if name == "mixed":
             checked = _sampled_blocks(ctx, f, V, g, s, [127, 128, 129], 1e-5,
                                       1e-6, eps)
@@ -162,10 +167,71 @@ def test_alkane_mixed_full_size():
     _say(f"  window [{lo:.4f}, {hi:.4f}] Ha: {len(w64)} eigenvalues, "
          f"max |E_mixed - E_fp64| {err:.2e} Ha")
     assert err < 1e-5
+    # kept counts: Weyl bound on the CPU (LAPACK eigenvalues of FP64 S)
+    import scipy.sparse.linalg as spla
+    dS = Ssp["mixed"] - Ssp["fp64"]
+    nrm = float(abs(spla.eigsh(dS, k=1, which="LM",
+                               return_eigenvectors=False)[0]))
+    w = np.linalg.eigvalsh(Ssp["fp64"].toarray())
+    band = int(np.count_nonzero(np.abs(w - 1e-6) <= nrm))
+    _say(f"  kept counts: mixed {kept['mixed']}, FP64 {kept['fp64']}; "
+         f"||dS||_2 {nrm:.2e}, FP64 eigenvalues of S within it of tau: {band}")
+    assert abs(kept["mixed"] - kept["fp64"]) <= band
 
 
-@pytest.mark.timeout(600)
-def test_amorphous_fp64_full_size():
+def _sparse_pencil(f, H, S):
+    """H and S as symmetric scipy CSR matrices from the packed upper blocks
+    (host copy helper, no method arithmetic)."""
+    import scipy.sparse as sp
+    pj, pn, off = f.pairs()
+    st = f.states
+    bo = np.concatenate([[0], np.cumsum(st)])
+    rows, cols, hv, sv = [], [], [], []
+    for p in range(len(pj)):
+        j, n = int(pj[p]), int(pn[p])
+        sj, sn = int(st[j]), int(st[n])
+        r = np.repeat(np.arange(bo[j], bo[j + 1]), sn)
+        c = np.tile(np.arange(bo[n], bo[n + 1]), sj)
+        h = H[off[p]:off[p] + sj * sn]
+        s_ = S[off[p]:off[p] + sj * sn]
+        rows.append(r); cols.append(c); hv.append(h); sv.append(s_)
+        if j != n:
+            rows.append(c); cols.append(r); hv.append(h); sv.append(s_)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    N = int(bo[-1])
+    Hs = sp.csr_matrix((np.concatenate(hv), (rows, cols)), shape=(N, N))
+    Ss = sp.csr_matrix((np.concatenate(sv), (rows, cols)), shape=(N, N))
+    return Hs, Ss
+
+
+def _pencil_validity(Hs, Ss, E, C, tau, tol):
+    """Checks of a window of eigenpairs of the thresholded pencil that need
+    no eigendecomposition of S: with C = X Y (X = U_K s_K^-1/2 spanning the
+    kept directions of S, Y orthonormal eigenvectors of X^T H X),
+      C^T S C = I and C^T H C = diag(E)              (Galerkin conditions),
+      r_k = H c_k - E_k S c_k satisfies X^T r_k = 0, so r_k lies in the
+      dropped space of S and ||S r_k|| <= tau ||r_k||.
+    (||r_k|| itself need not be small: H couples kept and dropped
+    directions.)  Returns the three measured deviations."""
+    SC = Ss @ C
+    HC = Hs @ C
+    g_s = np.abs(C.T @ SC - np.eye(C.shape[1])).max()
+    g_h = np.abs(C.T @ HC - np.diag(E)).max()
+    R = HC - SC * E
+    SR = Ss @ R
+    rn = np.linalg.norm(R, axis=0)
+    excess = (np.linalg.norm(SR, axis=0) - tau * rn).max()
+    _say(f"  validity: |C^T S C - I| {g_s:.2e}, |C^T H C - E| {g_h:.2e}, "
+         f"max ||r|| {rn.max():.2e}, max(||S r|| - tau ||r||) {excess:.2e}")
+    assert g_s <= tol and g_h <= tol and excess <= tol
+    return g_s, g_h, excess
+
+
+@pytest.fixture(scope="module")
+def amorphous_fp64():
+    """The amorphous system in FP64: fragment stage, elements, the whole
+    spectrum of the pencil, and the window [E_1, E_1 + 0.3 Ha] with its
+    coefficients."""
     s = make_system("amorphous", seed=0)
     V = s.potential()
     g = s.grid
@@ -175,21 +241,115 @@ def test_amorphous_fp64_full_size():
     f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
                               s.frag_dims, s.frag_states, origin=g.origin)
     st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
-    assert st == 0 and cv.all()
     m = P.ofm_matrix_elements(ctx, f)
     gs = P.ofm_solve_global(ctx, m, 1e-6)
-    _say("library stage times", ctx.stage_times(),
-         f"iterations max {it.max()}, kept {gs['n_kept']}")
-    assert 0 < gs["n_kept"] <= s.n_basis
-    assert np.all(np.diff(gs["E"]) >= 0) and np.isfinite(gs["E"]).all()
+    lo, hi = gs["E"][0], gs["E"][0] + 0.3
+    gw = P.ofm_solve_global(ctx, m, 1e-6, lo, hi, want_vectors=True)
+    H, S = P.ofm_mats_copy(m)
+    _say("  FP64 stage times", ctx.stage_times(),
+         f"iterations max {it.max()}, kept {gs['n_kept']}, window "
+         f"{len(gw['E'])} eigenvalues")
     m.close()
+    d = dict(s=s, V=V, g=g, ctx=ctx, f=f, st=st, eps=eps, it=it, cv=cv,
+             E=gs["E"], n_kept=gs["n_kept"], window=(lo, hi), Ew=gw["E"],
+             C=gw["C"], H=H, S=S)
+    yield d
+    f.close()
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_amorphous_fp64_full_size(amorphous_fp64):
+    """1024 uneven fragments in FP64: every fragment converges; the window's
+    eigenpairs pass the validity checks of the thresholded pencil on the
+    GPU's own blocks (1e-8 of max|H|) and agree with the values-only solve;
+    three overlapping fragments match the oracle's eigenpairs (1e-8 Ha) and,
+    with the oracle's states imported, their blocks (1e-10 of max|H|)."""
+    d = amorphous_fp64
+    s, V, g, ctx, f = d["s"], d["V"], d["g"], d["ctx"], d["f"]
+    assert d["st"] == 0 and d["cv"].all()
+    assert 0 < d["n_kept"] <= s.n_basis
+    E, Ew = d["E"], d["Ew"]
+    assert np.all(np.diff(E) >= 0) and np.isfinite(E).all()
+    lo, hi = d["window"]
+    ref_w = E[(E >= lo) & (E <= hi)]
+    assert len(Ew) == len(ref_w) > 0
+    _say(f"  window: {len(Ew)} eigenvalues, values-only vs vectors path "
+         f"{np.abs(Ew - ref_w).max():.2e} Ha")
+    assert np.abs(Ew - ref_w).max() < 1e-8
+    Hs, Ss = _sparse_pencil(f, d["H"], d["S"])
+    tol = 1e-8 * np.abs(d["H"]).max()
+    _pencil_validity(Hs, Ss, Ew, d["C"], 1e-6, tol)
     # the three consecutive windows of one chain with the smallest boxes
     vol = s.frag_dims.prod(1)
     best = min(range(0, s.n_frag - 2), key=lambda k: vol[k:k + 3].sum())
     samp = [best, best + 1, best + 2]
     pj, pn, _ = f.pairs()
     expect = sum(1 for a, b in zip(pj, pn) if a in samp and b in samp)
-    checked = _sampled_blocks(ctx, f, V, g, s, samp, 1e-8, 1e-10, eps)
+    checked = _sampled_blocks(ctx, f, V, g, s, samp, 1e-8, 1e-10, d["eps"])
+    assert checked == expect >= 5
+
+
+def _kept_count_bound(ctx64, S64_sparse, dS_sparse, tau):
+    """Weyl's inequality: every eigenvalue of S moves by at most ||dS||_2
+    under S -> S + dS, so the kept count |{s >= tau}| can change by at most
+    the number of FP64 eigenvalues of S within ||dS||_2 of tau.  Returns
+    (||dS||_2, that number)."""
+    import scipy.sparse.linalg as spla
+    nrm = float(abs(spla.eigsh(dS_sparse, k=1, which="LM",
+                               return_eigenvectors=False)[0]))
+    Sd = S64_sparse.toarray()
+    w, _ = P.ofm_dense_eigh(ctx64, Sd.T)
+    band = int(np.count_nonzero(np.abs(w - tau) <= nrm))
+    return nrm, band, w
+
+
+@pytest.mark.timeout(900)
+def test_amorphous_mixed_full_size(amorphous_fp64):
+    """The amorphous system in the mixed form: every fragment converges;
+    three overlapping fragments match the oracle's eigenpairs (1e-5 Ha) and,
+    with the oracle's states imported, their blocks (1e-6 of max|H|); the
+    window [E_1, E_1 + 0.3 Ha] of the FP64 run, passed verbatim, holds the
+    same number of eigenvalues within 1e-5 Ha of FP64's.  The kept count of
+    S may differ from FP64's only by the FP64 eigenvalues of S within
+    ||S_mixed - S_fp64||_2 of the threshold (Weyl)."""
+    d = amorphous_fp64
+    s, V, g = d["s"], d["V"], d["g"]
+    ctx = P.ofm_create(0, None, P.OFM_MIXED_BF16X3)
+    f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
+                              s.frag_dims, s.frag_states, origin=g.origin)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0 and cv.all()
+    m = P.ofm_matrix_elements(ctx, f)
+    gs = P.ofm_solve_global(ctx, m, 1e-6)
+    Hm, Sm = P.ofm_mats_copy(m)
+    m.close()
+    _say("  mixed stage times", ctx.stage_times(),
+         f"iterations max {it.max()}, kept {gs['n_kept']} (FP64 "
+         f"{d['n_kept']})")
+    lo, hi = d["window"]
+    w64 = d["Ew"]
+    Em = gs["E"]
+    wmx = Em[(Em >= lo - 1e-5) & (Em <= hi + 1e-5)]
+    assert len(wmx) == len(w64) > 0
+    err = np.abs(wmx - w64).max()
+    _say(f"  window [{lo:.4f}, {hi:.4f}] Ha: {len(w64)} eigenvalues, "
+         f"max |E_mixed - E_fp64| {err:.2e} Ha")
+    assert err < 1e-5
+    H64s, S64s = _sparse_pencil(d["f"], d["H"], d["S"])
+    _, Sms = _sparse_pencil(f, Hm, Sm)
+    nrm, band, _ = _kept_count_bound(d["ctx"], S64s, Sms - S64s, 1e-6)
+    dk = abs(gs["n_kept"] - d["n_kept"])
+    _say(f"  kept counts: mixed {gs['n_kept']}, FP64 {d['n_kept']}; "
+         f"||dS||_2 {nrm:.2e}, FP64 eigenvalues of S within it of tau: "
+         f"{band}")
+    assert dk <= band
+    vol = s.frag_dims.prod(1)
+    best = min(range(0, s.n_frag - 2), key=lambda k: vol[k:k + 3].sum())
+    samp = [best, best + 1, best + 2]
+    pj, pn, _ = f.pairs()
+    expect = sum(1 for a, b in zip(pj, pn) if a in samp and b in samp)
+    checked = _sampled_blocks(ctx, f, V, g, s, samp, 1e-5, 1e-6, eps)
     assert checked == expect >= 5
     f.close()
     ctx.close()

@@ -317,6 +317,38 @@ def test_own_atoms_fragments(tiny0):
     assert np.abs(r.H - 0.5 * (Hb + Hb.T)).max() < 1e-12
 
 
+# ------------------------------------------------ energy window (reading)
+
+def test_window_below_cutoff_worked_example():
+    """Hand-worked window of the tiny configurations: the upper bound is the
+    lowest basis cutoff, i.e. the minimum over fragments of each fragment's
+    highest kept eigenvalue, and the bound is inclusive.  The fragment
+    spectra are chosen so that the maximum over fragments, the minimum of
+    the lowest eigenvalues, the last fragment's cutoff or an exclusive bound
+    would each select a different set."""
+    eps = [np.array([-1.0, -0.5, 0.30]),     # cutoff 0.30
+           np.array([-0.8, 0.10]),           # cutoff 0.10  <- the minimum
+           np.array([-0.9, -0.2, 0.05, 0.70])]   # cutoff 0.70 (last one)
+    lo, hi = O.window_below_cutoff(eps)
+    assert lo == -np.inf and hi == 0.10
+    # the pencil's eigenvalues: one sits exactly on the cutoff
+    E = np.array([-0.95, -0.4, 0.0, 0.10, 0.2, 0.5])
+    sel = E[(E >= lo) & (E <= hi)]
+    assert sel.tolist() == [-0.95, -0.4, 0.0, 0.10]   # inclusive bound
+    # the alternatives a wrong rule would give, to show the example
+    # separates them
+    assert max(e[-1] for e in eps) == 0.70
+    assert min(e[0] for e in eps) == -1.0
+    assert eps[-1][-1] == 0.70
+    assert E[E < hi].tolist() == [-0.95, -0.4, 0.0]
+    # on an oracle run, the window returned is exactly the eigenvalues up to
+    # the cutoff, through the same selection
+    H = np.diag(E)
+    S = np.eye(len(E))
+    g = O.global_solve(H, S, 1e-6, lo, hi)
+    assert g["window"].tolist() == [-0.95, -0.4, 0.0, 0.10]
+
+
 # ------------------------------------------- basis near the HOMO (Sec. III-B)
 
 def test_select_top_and_by_gap_worked_examples():
