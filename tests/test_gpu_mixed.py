@@ -1,7 +1,8 @@
 """GPU parity of the mixed form (FP32 vectors and stencil, split-BF16 x3
 MFMA contractions, FP64 Cholesky / small eigensolves / global solve) against
 the FP64 oracle: eigenvalues within 1e-5 Ha, matrix elements within 1e-6
-relative to max|H|, diagonal S blocks exactly the identity."""
+relative to max|H|; diagonal S blocks exactly the identity for the solver's
+states, computed from the states for imported ones."""
 import numpy as np
 import pytest
 
@@ -93,14 +94,12 @@ def test_mixed_elements_imported_states(mctx, case):
     _say("  H rel", eh, "S offdiag", es)
     assert eh < 1e-6
     assert es < 1e-6
-    # diagonal S blocks are the identity exactly
-    k = 0
-    for j, n in zip(pj, pn):
-        sz = int(st[j]) * int(st[n])
-        if j == n:
-            assert np.array_equal(S[k:k + sz].reshape(st[j], st[j]),
-                                  np.eye(int(st[j])))
-        k += sz
+    # imported states: the diagonal S blocks are computed from the states
+    # (FP64 products on their FP32 values), within FP32 rounding of the
+    # oracle's Phi_j^T Phi_j = I
+    ed = np.abs(S - Sr)[dg].max()
+    _say("  S diagonal blocks", ed)
+    assert ed < 1e-6
 
 
 def test_mixed_diag_s_of_non_orthonormal_imports(mctx, tiny0):
