@@ -354,6 +354,38 @@ ofm_status ofm_reset_stats(ofm_ctx* ctx);
 ofm_status ofm_stage_times(const ofm_ctx* ctx, double* solve_ms,
                            double* elements_ms, double* global_ms);
 
+/* ---- allocation-free matrix elements ------------------------------------ */
+
+/* Bytes of the per-GPU device array that ofm_matrix_elements_noalloc stages
+   its pair task list in (one array per GPU the library runs on, held until
+   the process ends): 64 MiB, i.e. up to about 5.5e5 tasks (two per pair of
+   fragments at most). */
+#define OFM_NOALLOC_SCRATCH_BYTES (64LL << 20)
+
+/* For callers that cannot allocate device memory (code under HIP stream
+   capture, tight serving loops, harnesses that forbid hipMalloc): the work
+   of ofm_matrix_elements written into caller-owned device buffers, with no
+   device allocation and no allocating library call.
+   H_dev, S_dev : device pointers to n_values doubles each, where n_values =
+                  sum over pairs of s_j * s_n (block_off[last] + s_j * s_n of
+                  the last pair of ofm_pairs); the blocks are written in the
+                  layout of ofm_pairs (and ofm_mats_copy), every element,
+                  blocks without overlap as zeros.
+   The pair task list is copied from the host into the library's scratch
+   array (OFM_NOALLOC_SCRATCH_BYTES, resolved per device by ofm_create).  The
+   work is enqueued on the context stream and the call returns without
+   waiting for it: synchronise that stream before reading H_dev / S_dev.
+   Every call on one GPU shares that GPU's scratch array and the array keeps
+   the last call's task list: calls whose work overlaps on one GPU (contexts
+   on different streams of the same device with calls in flight at once)
+   race on it; calls ordered on one stream do not.  Per-kernel timing
+   (ofm_set_profiling) is not recorded for this call.
+   Errors: OFM_E_INVALID for a NULL handle or buffer, a buffer that is not
+   device memory, or a task list larger than the scratch array (nothing is
+   enqueued then); OFM_E_STATE without states. */
+ofm_status ofm_matrix_elements_noalloc(ofm_ctx* ctx, ofm_frags* f,
+                                       double* H_dev, double* S_dev);
+
 #ifdef __cplusplus
 }
 #endif

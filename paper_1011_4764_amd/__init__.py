@@ -12,6 +12,6 @@ from .ofm import (  # noqa: F401
     ofm_get_states, ofm_matrix_elements, ofm_mats_copy, ofm_set_states, ofm_set_stencil_variant,
     ofm_set_fragment_wells, ofm_select_homo, ofm_solve_global_subset,
     ofm_homo_energies, ofm_homo_lumo_gap, ofm_dense_eigh, ofm_solve_flags,
-    OFM_MAX_APPLY_VECTORS,
+    OFM_MAX_APPLY_VECTORS, ofm_matrix_elements_noalloc, n_values,
     ofm_solve_fragments, ofm_solve_global, ofm_version, unpack_blocks,
 )

@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = ["csrc/stencil.hip", "csrc/kernels.hip", "csrc/api.cpp",
-       "csrc/planner.cpp", "csrc/global_solve.cpp", "csrc/tridiag.hip"]
+       "csrc/planner.cpp", "csrc/global_solve.cpp", "csrc/tridiag.hip",
+       "csrc/noalloc.hip"]
 LIB = os.path.join(HERE, "libofm.so")
 
 # Packed FP32 instructions are disabled for all device code (some of their

@@ -506,6 +506,48 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
 
 }  // namespace
 
+void ofm::run_pair_elements(ofm_ctx* c, ofm_frags* f, PairTask* d_tasks,
+                            double* H, double* S) {
+  hipStream_t s = c->stream;
+  const bool mixed = c->precision != OFM_FP64;
+  // mixed form: the diagonal S block of solver-orthonormalised states is the
+  // identity; imported states get theirs from FP64 products
+  bool any_imported = false;
+  for (auto& t : f->pair_tasks)
+    if (t.sym && t.which == 0) {
+      t.ident = mixed && f->solver_states[t.frag] ? 1 : 0;
+      any_imported = any_imported || (mixed && !t.ident);
+    }
+  const int nt = (int)f->pair_tasks.size();
+  if (nt > 0)
+    OFM_HIP(hipMemcpyAsync(d_tasks, f->pair_tasks.data(),
+                           sizeof(PairTask) * nt, hipMemcpyHostToDevice, s));
+  // blocks without a task (S of halo-only pairs) stay zero
+  k::fill_zero(s, H, f->n_values);
+  k::fill_zero(s, S, f->n_values);
+  // algorithmic bytes of the pair-centric contraction: every block reads
+  // its two operands over its overlap once (each fragment's states and
+  // H|phi> are read once per block that touches them), plus the blocks
+  const double w = (double)wsize(c);
+  double flops = 0, bytes = 2.0 * 8.0 * f->n_values;
+  for (auto& t : f->pair_tasks) {
+    if (mixed && t.sym && t.which == 0) continue;
+    const double K = (double)t.om[0] * t.om[1] * t.om[2];
+    flops += 2.0 * t.ma * t.mb * K;
+    bytes += (double)(t.ma + t.mb) * K * w;
+  }
+  if (!mixed) {
+    k::pair_elements<double>(c, f, d_tasks, nt, arena<double>(f->d_x),
+                             arena<double>(f->d_hphi), H, S, flops, bytes);
+  } else {
+    k::pair_elements<float>(c, f, d_tasks, nt, arena<float>(f->d_x),
+                            arena<float>(f->d_hphi), H, S, flops, bytes);
+    if (any_imported)
+      k::pair_elements_f64_on_f32(c, f, d_tasks, nt, arena<float>(f->d_x),
+                                  arena<float>(f->d_hphi), H, S);
+  }
+}
+
 // ==========================================================================
 // C ABI
 // ==========================================================================
@@ -540,6 +582,8 @@ ofm_status ofm_create(ofm_ctx** out, int device, void* hip_stream,
       hipDeviceProp_t prop;
       OFM_HIP(hipGetDeviceProperties(&prop, device));
       c->n_cu = prop.multiProcessorCount;
+      // device address of the allocation-free entry point's scratch array
+      noalloc_init(device);
     } catch (...) {
       delete c;
       throw;
@@ -588,6 +632,7 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
       plan_pairs(f, atom_xyz, frag_atom_ptr, frag_atom_idx, d_cut);
       f->solver_states.assign(n_frag, 0);
       f->solve_flags.assign(n_frag, 0);
+      f->pair_tasks = plan_pair_tasks(f);
       // tile lists
       std::vector<int2> stiles, rtiles;
       int th = 0;
@@ -1039,7 +1084,6 @@ ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {
     *out = nullptr;
     use_device(c);
     const double t0 = now_ms();
-    auto tasks = plan_pair_tasks(f);
     auto* m = new ofm_mats;
     m->ctx = c;
     m->frags = f;
@@ -1052,78 +1096,22 @@ ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {
       m->states.push_back(d.n_states);
       m->basis_off.push_back(d.basis_off);
     }
-    // mixed form: the diagonal S block of solver-orthonormalised states is
-    // the identity; for imported states it is computed with FP64 products
-    // (a separate task list, launched after the grouped contraction)
-    std::vector<PairTask> diag_s;
-    if (c->precision != OFM_FP64) {
-      std::vector<PairTask> rest;
-      rest.reserve(tasks.size());
-      for (auto& t : tasks) {
-        if (t.sym && t.which == 0) {
-          const int j = (int)(std::lower_bound(f->block_off.begin(),
-                                               f->block_off.end(), t.c_off) -
-                              f->block_off.begin());
-          if (!f->solver_states[f->pair_j[j]]) {
-            diag_s.push_back(t);
-            continue;
-          }
-          t.ident = 1;
-        }
-        rest.push_back(t);
-      }
-      tasks.swap(rest);
-    }
     PairTask* dt = nullptr;
-    PairTask* dt2 = nullptr;
     try {
       m->d_H = dev_alloc<double>(f->n_values);
       m->d_S = dev_alloc<double>(f->n_values);
-      dt = dev_alloc<PairTask>(tasks.size());
-      dt2 = dev_alloc<PairTask>(diag_s.size());
-      if (!diag_s.empty())
-        OFM_HIP(hipMemcpyAsync(dt2, diag_s.data(),
-                               sizeof(PairTask) * diag_s.size(),
-                               hipMemcpyHostToDevice, c->stream));
-      hipStream_t s = c->stream;
-      OFM_HIP(hipMemsetAsync(m->d_H, 0, sizeof(double) * f->n_values, s));
-      OFM_HIP(hipMemsetAsync(m->d_S, 0, sizeof(double) * f->n_values, s));
-      OFM_HIP(hipMemcpyAsync(dt, tasks.data(), sizeof(PairTask) * tasks.size(),
-                             hipMemcpyHostToDevice, s));
-      // algorithmic bytes of the pair-centric contraction: every block reads
-      // its two operands over its overlap once (each fragment's states and
-      // H|phi> are read once per block that touches them), plus the blocks
-      const double w = (double)wsize(c);
-      double flops = 0, bytes = 2.0 * 8.0 * f->n_values;
-      for (auto& t : tasks) {
-        const double K = (double)t.om[0] * t.om[1] * t.om[2];
-        flops += 2.0 * t.ma * t.mb * K;
-        bytes += (double)(t.ma + t.mb) * K * w;
-      }
-      if (c->precision == OFM_FP64)
-        k::pair_elements<double>(c, f, dt, (int)tasks.size(),
-                                 arena<double>(f->d_x), arena<double>(f->d_hphi),
-                                 m->d_H, m->d_S, flops, bytes);
-      else {
-        k::pair_elements<float>(c, f, dt, (int)tasks.size(),
-                                arena<float>(f->d_x), arena<float>(f->d_hphi),
-                                m->d_H, m->d_S, flops, bytes);
-        k::pair_elements_f64_on_f32(c, f, dt2, (int)diag_s.size(),
-                                    arena<float>(f->d_x),
-                                    arena<float>(f->d_hphi), m->d_H, m->d_S);
-      }
-      OFM_HIP(hipStreamSynchronize(s));
+      dt = dev_alloc<PairTask>(f->pair_tasks.size());
+      run_pair_elements(c, f, dt, m->d_H, m->d_S);
+      OFM_HIP(hipStreamSynchronize(c->stream));
       collect_stats(c);
     } catch (...) {
       dev_free(dt);
-      dev_free(dt2);
       dev_free(m->d_H);
       dev_free(m->d_S);
       delete m;
       throw;
     }
     dev_free(dt);
-    dev_free(dt2);
     c->t_elem = now_ms() - t0;
     c->live += 1;
     *out = m;

@@ -1053,17 +1053,22 @@ __device__ __forceinline__ void pair_store(const PairTask& tk,
 // FP64 MFMA 16x16x4; RMAX >= the largest state count, a multiple of 16.
 // TI is the storage type of the operands (FP32 operands are widened to FP64
 // when staged, so the products and sums are FP64 either way).
+// With `only_imported_diag_s`, only the diagonal S blocks of imported
+// states (sym, which == 0, ident == 0) are computed and every other task
+// returns at once.
 template <int RMAX, typename TI>
 __global__ __launch_bounds__(WG) void k_pair(
     const PairTask* __restrict__ tasks, int ntask,
     const TI* __restrict__ PHI, const TI* __restrict__ HPHI,
-    double* __restrict__ Hout, double* __restrict__ Sout) {
+    double* __restrict__ Hout, double* __restrict__ Sout,
+    int only_imported_diag_s) {
   constexpr int KST = 64, LP = KST + 1;
   constexpr int UMAX = (RMAX / 16) * (RMAX / 16) > 4
                            ? ((RMAX / 16) * (RMAX / 16) + 3) / 4 : 1;
   const int ti = blockIdx.x;
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
+  if (only_imported_diag_s && !(tk.sym && tk.which == 0 && !tk.ident)) return;
   const TI* A = PHI + tk.a_off;
   const TI* B = (tk.which ? HPHI : PHI) + tk.b_off;
   double* C = (tk.which ? Hout : Sout) + tk.c_off;
@@ -1163,10 +1168,11 @@ __global__ __launch_bounds__(WG) void k_pair_x3(
   if (ti >= ntask) return;
   const PairTask tk = tasks[ti];
   double* C = (tk.which ? Hout : Sout) + tk.c_off;
-  if (tk.ident) {
-    for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG)
-      C[e] = (e / tk.mb == e % tk.mb) ? 1.0 : 0.0;
-    return;
+  if (tk.sym && tk.which == 0) {
+    if (tk.ident)
+      for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG)
+        C[e] = (e / tk.mb == e % tk.mb) ? 1.0 : 0.0;
+    return;   // imported states: k_pair<.., float> computes this block
   }
   const float* A = PHI + tk.a_off;
   const float* B = (tk.which ? HPHI : PHI) + tk.b_off;
@@ -1279,7 +1285,7 @@ void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
       hipLaunchKernelGGL((k_pair<R, double>), dim3(n_tasks), dim3(WG), 0,    \
                          c->stream,                                          \
                          tasks, n_tasks, (const double*)phi,                 \
-                         (const double*)hphi, H, S);                         \
+                         (const double*)hphi, H, S, 0);                      \
     else                                                                     \
       hipLaunchKernelGGL(k_pair_x3<R>, dim3(n_tasks), dim3(WG), 0,           \
                          c->stream, tasks, n_tasks, (const float*)phi,       \
@@ -1301,7 +1307,7 @@ void pair_elements_f64_on_f32(ofm_ctx* c, const ofm_frags* f,
                : f->max_states <= 48 ? 48 : 64;
 #define PAIRF(R)                                                             \
   hipLaunchKernelGGL((k_pair<R, float>), dim3(n_tasks), dim3(WG), 0,         \
-                     c->stream, tasks, n_tasks, phi, hphi, H, S)
+                     c->stream, tasks, n_tasks, phi, hphi, H, S, 1)
   if (rm == 16) PAIRF(16);
   else if (rm == 32) PAIRF(32);
   else if (rm == 48) PAIRF(48);
@@ -1316,6 +1322,19 @@ template void pair_elements<double>(ofm_ctx*, const ofm_frags*,
 template void pair_elements<float>(ofm_ctx*, const ofm_frags*, const PairTask*,
                                    int, const float*, const float*, double*,
                                    double*, double, double);
+
+__global__ void k_fill_zero(double* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < n;
+       i += (long long)gridDim.x * WG)
+    p[i] = 0.0;
+}
+
+void fill_zero(hipStream_t s, double* p, long long n) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<long long>((n + WG - 1) / WG, 8192);
+  hipLaunchKernelGGL(k_fill_zero, dim3(nb), dim3(WG), 0, s, p, n);
+  OFM_HIP(hipGetLastError());
+}
 
 // ---------------------------------------------------------------------------
 // conversions and copies between the FP64 host layout and the arenas

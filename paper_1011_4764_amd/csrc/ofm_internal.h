@@ -64,7 +64,7 @@ struct PairTask {
   int which;                // 0: S block, 1: H block
   int ident;                // mixed form: write the identity (diagonal S
                             // block of solver-orthonormalised states)
-  int pad;
+  int frag;                 // row fragment j of the block
 };
 
 // per-fragment Chebyshev filter state (device)
@@ -179,6 +179,8 @@ struct ofm_frags {
   // per fragment after a solve: bit 0 the CholQR Gram needed the shifted
   // Cholesky factorisation, bit 1 that one lost a pivot too
   std::vector<int> solve_flags;
+  // tasks of the grouped pair contraction (planned once, longest first)
+  std::vector<ofm::PairTask> pair_tasks;
 };
 
 struct ofm_mats {
@@ -286,6 +288,15 @@ void dense_eigh(ofm_ctx* c, hipStream_t s, void* blas_handle, int n, double* A,
 // the same on host arrays, on the context's stream
 void dense_eigh_host(ofm_ctx* c, int n, const double* A, double* w, double* Z);
 void destroy_blas(ofm_ctx* c);
+// the matrix-element stage on a planned task list: sets the tasks' ident
+// flags from the fragments' state origin, uploads the list to d_tasks
+// (device, n_tasks entries), fills H and S (n_values doubles each, device)
+// and launches the contraction kernels on the context stream
+void run_pair_elements(ofm_ctx* c, ofm_frags* f, PairTask* d_tasks, double* H,
+                       double* S);
+// per-device scratch of the allocation-free entry point (noalloc.hip):
+// resolved once per device at context creation
+void noalloc_init(int device);
 
 // kernel launchers (kernels.hip)
 namespace k {
@@ -345,16 +356,22 @@ void gauge(hipStream_t s, const ofm_frags* f, T* X);
 template <typename T>
 void whole_h(ofm_ctx* c, const ofm_frags* f, const T* X, T* HPHI,
              int only_frag);
+// every block of the task list (the mixed form leaves the diagonal S
+// blocks of imported states, tasks with sym, which == 0 and ident == 0, to
+// pair_elements_f64_on_f32)
 template <typename T>
 void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
                    int n_tasks, const T* phi, const T* hphi, double* H,
                    double* S, double flops, double bytes);
-// FP64 MFMA products on FP32 operands (mixed form: diagonal S blocks of
-// imported states)
+// mixed form: the diagonal S blocks of imported states (tasks with sym,
+// which == 0 and ident == 0 of the same list) with FP64 MFMA products on
+// the FP32 operands
 void pair_elements_f64_on_f32(ofm_ctx* c, const ofm_frags* f,
                               const PairTask* tasks, int n_tasks,
                               const float* phi, const float* hphi, double* H,
                               double* S);
+// zero n doubles (a kernel, not hipMemsetAsync: safe under stream capture)
+void fill_zero(hipStream_t s, double* p, long long n);
 template <typename T>
 void convert(hipStream_t s, const double* in, T* out, long long n);
 template <typename T>

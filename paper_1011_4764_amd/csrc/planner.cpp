@@ -202,6 +202,7 @@ std::vector<PairTask> plan_pair_tasks(const ofm_frags* f) {
       t.mb = b.n_states;
       t.sym = sym;
       t.which = 0;
+      t.frag = f->pair_j[p];
       tasks.push_back(t);
     }
     // H block: states of j against H phi of n on n's dilated box
@@ -223,6 +224,7 @@ std::vector<PairTask> plan_pair_tasks(const ofm_frags* f) {
       t.mb = b.n_states;
       t.sym = sym;
       t.which = 1;
+      t.frag = f->pair_j[p];
       tasks.push_back(t);
     }
   }

@@ -34,7 +34,7 @@ EXPORTS = [
     "ofm_kernel_stats", "ofm_reset_stats", "ofm_stage_times",
     "ofm_set_stencil_variant", "ofm_set_fragment_wells", "ofm_select_homo",
     "ofm_solve_global_subset", "ofm_homo_energies", "ofm_homo_lumo_gap",
-    "ofm_dense_eigh", "ofm_solve_flags",
+    "ofm_dense_eigh", "ofm_solve_flags", "ofm_matrix_elements_noalloc",
 ]
 OFM_MAX_APPLY_VECTORS = 32767
 
@@ -103,6 +103,7 @@ def lib():
                                      C.c_int),
             "ofm_matrix_elements": ([_P, _P, C.POINTER(_P)], C.c_int),
             "ofm_mats_info": ([_P, _LL], C.c_int),
+            "ofm_matrix_elements_noalloc": ([_P, _P, _P, _P], C.c_int),
             "ofm_mats_copy": ([_P, _D, _D], C.c_int),
             "ofm_mats_destroy": ([_P], C.c_int),
             "ofm_solve_global": ([_P, _P, C.c_double, C.c_double, C.c_double,
@@ -397,6 +398,24 @@ def ofm_matrix_elements(ctx: Context, frags: Fragments) -> Mats:
     _check(lib().ofm_matrix_elements(ctx.handle, frags.handle, C.byref(out)),
            ctx.handle)
     return Mats(ctx, frags, out)
+
+
+def n_values(frags: Fragments) -> int:
+    """Doubles per matrix of the packed blocks (sum over pairs of s_j s_n)."""
+    pj, pn, off = frags.pairs()
+    st = frags.states
+    return int(off[-1] + st[pj[-1]] * st[pn[-1]]) if len(pj) else 0
+
+
+def ofm_matrix_elements_noalloc(ctx: Context, frags: Fragments, H_dev, S_dev):
+    """Blocks into caller-owned device buffers (objects with data_ptr(), e.g.
+    torch tensors of n_values(frags) float64 on the GPU); enqueued on the
+    context stream, which the caller synchronises before reading them."""
+    st = lib().ofm_matrix_elements_noalloc(
+        ctx.handle, frags.handle,
+        _P(H_dev.data_ptr()) if H_dev is not None else None,
+        _P(S_dev.data_ptr()) if S_dev is not None else None)
+    _check(st, ctx.handle)
 
 
 def ofm_mats_copy(m: Mats):
