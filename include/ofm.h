@@ -66,11 +66,17 @@ typedef enum {
 
 typedef enum {
   OFM_FP64 = 0,          /* all vector arithmetic and products in FP64       */
-  OFM_MIXED_BF16X3 = 1   /* vectors and stencil in FP32; subspace and element
-                            contractions as 3-term split-BF16 MFMA products
-                            with FP32 accumulation and FP64 cross-tile sums;
+  OFM_MIXED_BF16X3 = 1,  /* vectors and stencil in FP32; the Rayleigh-Ritz
+                            and element contractions as 3-term split-BF16
+                            MFMA products (a_hi b_hi + a_hi b_lo + a_lo b_hi)
+                            with FP32 sums over at most a few hundred points
+                            added in FP64; CholQR Gram (FP64 products),
                             Cholesky, small eigensolves and the global solve
                             in FP64                                          */
+  OFM_MIXED_FP16X3 = 2   /* as OFM_MIXED_BF16X3 with the split in FP16:
+                            a_hi = f16(a), a_lo = f16((a - a_hi) 2^11), the
+                            cross products scaled back by 2^-11 (dropped term
+                            ~2^-22 |a b| against ~2^-16 for BF16)           */
 } ofm_precision;
 
 /* Global grid: point (ix,iy,iz) at origin + (ix,iy,iz)*h (bohr). */
@@ -108,11 +114,11 @@ typedef struct {
                             launch with the vector held on chip (same bits
                             as the per-step launches) [on]; -1: per-step
                             launches for every box                         */
-  int fused;             /* when every box's xy plane fits one workgroup
-                            (at most 2048 points in FP64, 4096 in FP32),
-                            filter steps per launch: 0 or 2: two [default];
-                            3: three; -1 (or 1): one.  Same bits in every
-                            case.                                          */
+  int fused;             /* filter steps per launch for the boxes whose xy
+                            plane holds at most 2048 points (larger planes
+                            run one step per launch): 0 or 2: two
+                            [default]; 3: three; -1 (or 1): one.  Same bits
+                            in every case.                                 */
 } ofm_solve_opts;
 
 typedef struct ofm_ctx ofm_ctx;
@@ -242,6 +248,14 @@ ofm_status ofm_set_fragment_wells(ofm_frags* f, int n_atoms,
    variant computes identical values. */
 ofm_status ofm_set_stencil_variant(ofm_frags* f, int variant);
 
+/* Pin the variant of the pair-contraction kernels for calls on ctx (0: a
+   chunk of the overlap is loaded and then multiplied; 1: the next chunk's
+   loads stay in flight during the products), or -1 to let the first
+   ofm_matrix_elements call per (precision, block-width class) time both and
+   keep the faster (the default; the choice is cached in ctx).  Every variant
+   computes identical values. */
+ofm_status ofm_set_pair_variant(ofm_ctx* ctx, int variant);
+
 /* ---- matrix elements (Sec. II) ------------------------------------------ */
 
 /* H and S blocks for every pair j <= n: S_jn = Phi_j^T Phi_n over box_j ^
@@ -298,6 +312,44 @@ ofm_status ofm_solve_global_subset(ofm_ctx* ctx, const ofm_mats* m,
                                    double s_thresh, double e_lo, double e_hi,
                                    int* n_kept, int* n_eig, double* E,
                                    double* C, double* s_min);
+
+/* ---- windowed solve of a large basis (Sec. II, Sec. III-D) -------------- */
+
+/* Keep mask (n_basis bytes, host, fragment by fragment in basis order) of the
+   basis functions whose fragment eigenvalue lies in [e_lo, e_hi] (inclusive),
+   from the last ofm_solve_fragments (or imported states).
+   Errors: OFM_E_INVALID for a NULL mask or non-finite bounds; OFM_E_STATE
+   without states. */
+ofm_status ofm_select_band(const ofm_frags* f, double e_lo, double e_hi,
+                           unsigned char* keep);
+
+/* Eigenvalues of Eq. 2 in the window [e_lo, e_hi] for a basis too large for
+   the dense pencil: the pencil is restricted to the basis functions whose
+   fragment eigenvalue lies within a margin of the window (ofm_select_band
+   on [e_lo - margin, e_hi + margin]), solved as ofm_solve_global_subset
+   (threshold s_thresh).  Round r uses the margin margin0 + r * margin_step,
+   r < max_rounds; a round whose band holds no more functions than the last
+   one solved is skipped.  The window has converged when two successive
+   solved bands give the same number of window eigenvalues, equal within tol
+   (Ha), or when a band holds the whole basis (that round is the full
+   ofm_solve_global_subset of every function).  This is a reduction of the
+   basis, not an exact solve of the whole pencil: the omitted functions
+   shift the window's eigenvalues at second order in their coupling, which
+   the convergence test bounds only empirically.
+   n_eig  : eigenvalues written to E (capacity n_basis), ascending.
+   margin : margin of the last round (host, may be NULL).
+   n_sel  : basis functions of the last round's pencil (host, may be NULL).
+   n_kept : kept directions of S in the last round (host, may be NULL).
+   Returns OFM_E_NOCONV (last round's eigenvalues returned) when max_rounds
+   pass without two agreeing rounds.  Errors: OFM_E_INVALID for
+   margin0 < 0, margin_step <= 0, max_rounds < 2, tol < 0, e_hi < e_lo or
+   non-finite arguments, and as ofm_solve_global_subset. */
+ofm_status ofm_solve_global_window(ofm_ctx* ctx, const ofm_mats* m,
+                                   double s_thresh, double e_lo, double e_hi,
+                                   double margin0, double margin_step,
+                                   int max_rounds, double tol, int* n_eig,
+                                   double* E, double* margin, long long* n_sel,
+                                   int* n_kept);
 
 /* The dense FP64 symmetric eigensolver behind ofm_solve_global (it
    diagonalises S and H' of the canonical orthogonalisation that solves

@@ -53,6 +53,7 @@ __all__ = [
     "full_grid_eigs", "line_spectrum", "box_spectrum", "OracleResult",
     "run", "window_below_cutoff", "own_wells", "select_top",
     "select_by_gap", "subset", "homo_energies", "homo_lumo_gap",
+    "select_band", "window_by_band",
 ]
 
 #: stencil reach (points) of the 4th-order central second difference
@@ -396,6 +397,48 @@ def subset(H, S, keep):
     submatrices)."""
     idx = np.flatnonzero(keep)
     return H[np.ix_(idx, idx)], S[np.ix_(idx, idx)]
+
+
+def select_band(eps, e_lo, e_hi):
+    """Keep mask over the basis (fragment by fragment) of the states whose
+    fragment eigenvalue lies in [e_lo, e_hi], bounds included.  With the
+    restricted pencil (subset) this is the windowed solve of a basis too
+    large for the whole pencil (Sec. II: the generalised eigenproblem of the
+    fragment basis; Sec. III-D: its cost grows as the cube of the basis)."""
+    e = np.concatenate([np.asarray(x, float) for x in eps])
+    return (e >= e_lo) & (e <= e_hi)
+
+
+def window_by_band(H, S, eps, e_lo, e_hi, tau=1e-6, margin0=0.1,
+                   margin_step=0.1, max_rounds=6, tol=1e-8):
+    """Eigenvalues of the thresholded pencil in [e_lo, e_hi] on the basis
+    functions within a margin of the window.  The margin grows by
+    margin_step from margin0 (max_rounds margins at most); a margin whose
+    band holds no more functions than the last one solved is skipped.  The
+    result is converged when two successive solved bands give the same
+    number of window eigenvalues, equal within tol, or when a band holds the
+    whole basis (then it is the full solve).  Returns (E, converged, margin
+    of the last solved band, number of basis functions in it)."""
+    n_all = sum(len(x) for x in eps)
+    prev = None
+    last = -1
+    out = (np.zeros(0), False, margin0, 0)
+    for r in range(max_rounds):
+        d = margin0 + r * margin_step
+        keep = select_band(eps, e_lo - d, e_hi + d)
+        n = int(keep.sum())
+        if n == 0 or n == last:
+            continue
+        Hs, Ss = subset(H, S, keep)
+        E = global_solve(Hs, Ss, tau, e_lo, e_hi)["window"]
+        conv = n == n_all or (
+            prev is not None and len(prev) == len(E) and
+            (len(E) == 0 or np.abs(E - prev).max() <= tol))
+        out = (E, conv, d, n)
+        if conv:
+            break
+        prev, last = E, n
+    return out
 
 
 def homo_energies(H, n_states):

@@ -169,7 +169,9 @@ void free_frags(ofm_frags* f) {
   void* ptrs[] = {f->d_frag, f->d_v, f->d_v32, f->d_x, f->d_p, f->d_hx,
                   f->d_hphi, f->d_tiles[0], f->d_tiles[1], f->d_tiles[2],
                   f->d_ftiles, f->d_tiles_nr[0], f->d_tiles_nr[1],
-                  f->d_tiles_nr[2], f->d_vt[0], f->d_vt[1],
+                  f->d_tiles_nr[2], f->d_vt[0][0], f->d_vt[0][1],
+                  f->d_vt[0][2], f->d_vt[0][3], f->d_vt[1][0], f->d_vt[1][1],
+                  f->d_vt[1][2], f->d_vt[1][3],
                   f->d_tiles_rest[0][0], f->d_tiles_rest[0][1],
                   f->d_tiles_rest[0][2], f->d_tiles_rest[1][0],
                   f->d_tiles_rest[1][1], f->d_tiles_rest[1][2],
@@ -312,11 +314,10 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   // rest one step per launch in strips
   const bool res = sizeof(T) == 4 && cfg.resident && f->n_ftiles > 0;
   const int vset = res ? 1 : 0;
-  const int ppt2 = cfg.fused >= 2 && f->n_vt[vset] > 0
-                       ? k::multistep_ppt((int)w, f->vt_plane[vset]) : 0;
-  int2* const* strip_tiles = ppt2 > 0 ? f->d_tiles_rest[vset]
+  const bool have_ms = cfg.fused >= 2 && f->n_vt_all[vset] > 0;
+  int2* const* strip_tiles = have_ms ? f->d_tiles_rest[vset]
                              : res ? f->d_tiles_nr : f->d_tiles;
-  const int* strip_n = ppt2 > 0 ? f->n_tiles_rest[vset]
+  const int* strip_n = have_ms ? f->n_tiles_rest[vset]
                        : res ? f->n_tiles_nr : f->n_tiles;
   // the autotuning sweep runs every non-resident box in strips
   int2* const* tune_tiles = res ? f->d_tiles_nr : f->d_tiles;
@@ -325,16 +326,20 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
     // filter work: unlocked vectors of the active fragments, per class
     double snb = 0, snpt = 0, mnb = 0, mnpt = 0, rnb = 0, rnpt = 0;
+    double cnb[4] = {0, 0, 0, 0}, cnpt[4] = {0, 0, 0, 0};
     for (int j = 0; j < nf; ++j)
       if (act[j] && fsh[j].lock < f->host[j].bw) {
         const FragDev& d = f->host[j];
         const double u = (double)d.npts * (d.bw - fsh[j].lock);
+        const int ppt = k::multistep_ppt((int)w, d);
         if (res && k::resident_eligible((int)w, d)) {
           rnb += u;
           rnpt += d.npts;
-        } else if (ppt2 > 0 && !tuning && k::multistep_eligible((int)w, d)) {
+        } else if (have_ms && !tuning && ppt > 0) {
           mnb += u;
           mnpt += d.npts;
+          cnb[ppt - 1] += u;
+          cnpt[ppt - 1] += d.npts;
         } else {
           snb += u;
           snpt += d.npts;
@@ -348,7 +353,9 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                            f->d_fs, cfg.degree, (2 * rnb + rnpt) * w,
                            32.0 * rnb * cfg.degree);
     }
-    const bool use_ms = ppt2 > 0 && !tuning;
+    const bool use_ms = have_ms && !tuning;
+    int ms_classes = 0;
+    for (int cl = 0; cl < 4; ++cl) ms_classes += f->n_vt[vset][cl] > 0;
     int2* const* st_tiles = tuning ? tune_tiles : strip_tiles;
     const int* st_n = tuning ? tune_n : strip_n;
     auto sweep = [&](bool timed_each) {
@@ -362,10 +369,15 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         int step = 1;
         for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused))
           for (int i = 0; i < count; ++i) {
-            const double by = (step == 1 ? 3 * mnb : 4 * mnb) * w + mnpt * w;
-            k::apply_hm<T>(timed_each ? c : nullptr, f, in, pv, f->d_vt[vset],
-                           f->n_vt[vset], ppt2, ns, f->d_active, step, f->d_fs,
-                           by, 32.0 * mnb * ns);
+            for (int cl = 0; cl < 4; ++cl) {
+              if (f->n_vt[vset][cl] == 0) continue;
+              const double by =
+                  (step == 1 ? 3 * cnb[cl] : 4 * cnb[cl]) * w + cnpt[cl] * w;
+              k::apply_hm<T>(timed_each ? c : nullptr, f, in, pv,
+                             f->d_vt[vset][cl], f->n_vt[vset][cl], cl + 1, ns,
+                             f->d_active, step, f->d_fs, by,
+                             32.0 * cnb[cl] * ns);
+            }
             if (ns % 2) std::swap(in, pv);
             step += ns;
           }
@@ -418,11 +430,13 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       double by = 0;
       int launches = 0;
       if (use_ms) {
+        int steps_l = 0;
         for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused)) {
           (void)ns;
-          launches += count;
+          steps_l += count;
         }
-        by += (3 * mnb + mnpt) * w + (launches - 1) * (4 * mnb + mnpt) * w;
+        launches += steps_l * ms_classes;
+        by += (3 * mnb + mnpt) * w + (steps_l - 1) * (4 * mnb + mnpt) * w;
       }
       if (st_n[var] > 0) {
         launches += cfg.degree;
@@ -507,14 +521,14 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
 }  // namespace
 
 void ofm::run_pair_elements(ofm_ctx* c, ofm_frags* f, PairTask* d_tasks,
-                            double* H, double* S) {
+                            double* H, double* S, bool may_tune) {
   hipStream_t s = c->stream;
   const bool mixed = c->precision != OFM_FP64;
   // mixed form: the diagonal S block of solver-orthonormalised states is the
   // identity; imported states get theirs from FP64 products
   bool any_imported = false;
   for (auto& t : f->pair_tasks)
-    if (t.sym && t.which == 0) {
+    if (t.sym) {
       t.ident = mixed && f->solver_states[t.frag] ? 1 : 0;
       any_imported = any_imported || (mixed && !t.ident);
     }
@@ -525,23 +539,85 @@ void ofm::run_pair_elements(ofm_ctx* c, ofm_frags* f, PairTask* d_tasks,
   // blocks without a task (S of halo-only pairs) stay zero
   k::fill_zero(s, H, f->n_values);
   k::fill_zero(s, S, f->n_values);
-  // algorithmic bytes of the pair-centric contraction: every block reads
-  // its two operands over its overlap once (each fragment's states and
-  // H|phi> are read once per block that touches them), plus the blocks
+  // algorithmic bytes of the pair-centric contraction: every pair reads the
+  // states of j and H|phi> of n over Omega' and the states of n over Omega
+  // once (each fragment's data is read once per pair that touches it), plus
+  // both blocks; flops 2 s_j s_n per point of each block's support
   const double w = (double)wsize(c);
   double flops = 0, bytes = 2.0 * 8.0 * f->n_values;
   for (auto& t : f->pair_tasks) {
-    if (mixed && t.sym && t.which == 0) continue;
-    const double K = (double)t.om[0] * t.om[1] * t.om[2];
-    flops += 2.0 * t.ma * t.mb * K;
-    bytes += (double)(t.ma + t.mb) * K * w;
+    const double K1 = (double)t.om[0] * t.om[1] * t.om[2];
+    const double K0 = t.has_s ? (double)(t.s_hi[0] - t.s_lo[0]) *
+                                    (t.s_hi[1] - t.s_lo[1]) *
+                                    (t.s_hi[2] - t.s_lo[2])
+                              : 0.0;
+    const bool s_done = !(mixed && t.sym);   // mixed: S_jj set or separate
+    flops += 2.0 * t.ma * t.mb * (K1 + (s_done ? K0 : 0.0));
+    bytes += ((double)(t.ma + t.mb) * K1 + (s_done ? t.mb * K0 : 0.0)) * w;
   }
-  if (!mixed) {
-    k::pair_elements<double>(c, f, d_tasks, nt, arena<double>(f->d_x),
-                             arena<double>(f->d_hphi), H, S, flops, bytes);
-  } else {
-    k::pair_elements<float>(c, f, d_tasks, nt, arena<float>(f->d_x),
-                            arena<float>(f->d_hphi), H, S, flops, bytes);
+  auto launch = [&](int variant) {
+    if (!mixed)
+      k::pair_elements<double>(c, f, d_tasks, nt, arena<double>(f->d_x),
+                               arena<double>(f->d_hphi), H, S, flops, bytes,
+                               variant);
+    else
+      k::pair_elements<float>(c, f, d_tasks, nt, arena<float>(f->d_x),
+                              arena<float>(f->d_hphi), H, S, flops, bytes,
+                              variant);
+  };
+  // kernel variant: pinned, cached per (precision, tile class), or timed
+  // once here (every variant writes every block with the same bits, so the
+  // last timed run leaves the result)
+  const int key = (int)c->precision * 16 + (f->max_states + 15) / 16;
+  int variant = c->pair_variant;
+  bool done = false;
+  if (variant < 0) {
+    auto it = c->pair_tuned.find(key);
+    if (it != c->pair_tuned.end()) {
+      variant = it->second;
+    } else if (may_tune) {
+      hipEvent_t e[k::NPAIRVARIANT][2];
+      for (auto& ev : e) {
+        OFM_HIP(hipEventCreate(&ev[0]));
+        OFM_HIP(hipEventCreate(&ev[1]));
+      }
+      float best_ms = 0;
+      int best = 0;
+      try {
+        for (int v = 0; v < k::NPAIRVARIANT; ++v) {
+          OFM_HIP(hipEventRecord(e[v][0], s));
+          launch(v);
+          OFM_HIP(hipEventRecord(e[v][1], s));
+        }
+        for (int v = 0; v < k::NPAIRVARIANT; ++v) {
+          OFM_HIP(hipEventSynchronize(e[v][1]));
+          float ms = 0;
+          OFM_HIP(hipEventElapsedTime(&ms, e[v][0], e[v][1]));
+          if (v == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = v;
+          }
+        }
+      } catch (...) {
+        for (auto& ev : e) {
+          (void)hipEventDestroy(ev[0]);
+          (void)hipEventDestroy(ev[1]);
+        }
+        throw;
+      }
+      for (auto& ev : e) {
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+      }
+      c->pair_tuned[key] = best;
+      variant = best;
+      done = true;
+    } else {
+      variant = 1;
+    }
+  }
+  if (!done) launch(variant);
+  if (mixed) {
     if (any_imported)
       k::pair_elements_f64_on_f32(c, f, d_tasks, nt, arena<float>(f->d_x),
                                   arena<float>(f->d_hphi), H, S);
@@ -559,7 +635,8 @@ ofm_status ofm_create(ofm_ctx** out, int device, void* hip_stream,
                       ofm_precision precision) {
   if (!out) return OFM_E_INVALID;
   *out = nullptr;
-  if (precision != OFM_FP64 && precision != OFM_MIXED_BF16X3) {
+  if (precision != OFM_FP64 && precision != OFM_MIXED_BF16X3 &&
+      precision != OFM_MIXED_FP16X3) {
     g_create_err = "unknown precision form";
     return OFM_E_INVALID;
   }
@@ -681,17 +758,19 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
                f->d_tiles_rest[1][v], f->n_tiles_rest[1][v]);
       }
       for (int set = 0; set < 2; ++set) {
-        std::vector<int2> vt;
-        int mp = 0;
+        std::vector<int2> vt[4];
         for (int j = 0; j < n_frag; ++j) {
           const FragDev& d = f->host[j];
           if (set == 1 && k::resident_eligible((int)w, d)) continue;
-          if (!k::multistep_eligible((int)w, d)) continue;
-          mp = std::max(mp, d.dims[0] * d.dims[1]);
-          for (int v = 0; v < d.bw; ++v) vt.push_back(make_int2(j, v));
+          const int ppt = k::multistep_ppt((int)w, d);
+          if (ppt == 0) continue;
+          for (int v = 0; v < d.bw; ++v) vt[ppt - 1].push_back(make_int2(j, v));
         }
-        f->vt_plane[set] = mp;
-        upload(vt, f->d_vt[set], f->n_vt[set]);
+        f->n_vt_all[set] = 0;
+        for (int cl = 0; cl < 4; ++cl) {
+          upload(vt[cl], f->d_vt[set][cl], f->n_vt[set][cl]);
+          f->n_vt_all[set] += f->n_vt[set][cl];
+        }
       }
       {
         std::vector<int2> ft;
@@ -1069,6 +1148,12 @@ ofm_status ofm_set_fragment_wells(ofm_frags* f, int n_atoms,
   });
 }
 
+ofm_status ofm_set_pair_variant(ofm_ctx* c, int variant) {
+  if (!c || variant < -1 || variant >= k::NPAIRVARIANT) return OFM_E_INVALID;
+  c->pair_variant = variant;
+  return OFM_OK;
+}
+
 ofm_status ofm_set_stencil_variant(ofm_frags* f, int variant) {
   if (!f || variant < -1 || variant >= k::NVARIANT) return OFM_E_INVALID;
   f->variant = variant;
@@ -1101,7 +1186,7 @@ ofm_status ofm_matrix_elements(ofm_ctx* c, ofm_frags* f, ofm_mats** out) {
       m->d_H = dev_alloc<double>(f->n_values);
       m->d_S = dev_alloc<double>(f->n_values);
       dt = dev_alloc<PairTask>(f->pair_tasks.size());
-      run_pair_elements(c, f, dt, m->d_H, m->d_S);
+      run_pair_elements(c, f, dt, m->d_H, m->d_S, true);
       OFM_HIP(hipStreamSynchronize(c->stream));
       collect_stats(c);
     } catch (...) {
@@ -1209,6 +1294,90 @@ ofm_status ofm_select_homo(const ofm_frags* f, int n_max, double gap_min,
             break;
           }
       for (int i = 0; i < s; ++i) keep[d.basis_off + i] = i >= s - n ? 1 : 0;
+    }
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_select_band(const ofm_frags* f, double e_lo, double e_hi,
+                           unsigned char* keep) {
+  if (!f) return OFM_E_INVALID;
+  ofm_ctx* c = f->ctx;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(keep && std::isfinite(e_lo) && std::isfinite(e_hi),
+                OFM_E_INVALID, "keep is required and the bounds must be finite");
+    OFM_REQUIRE(f->have_states && (long long)f->eps_host.size() == f->n_basis,
+                OFM_E_STATE, "no states yet");
+    for (long long i = 0; i < f->n_basis; ++i) {
+      const double e = f->eps_host[i];
+      keep[i] = (e >= e_lo && e <= e_hi) ? 1 : 0;
+    }
+    return OFM_OK;
+  });
+}
+
+ofm_status ofm_solve_global_window(ofm_ctx* c, const ofm_mats* m,
+                                   double s_thresh, double e_lo, double e_hi,
+                                   double margin0, double margin_step,
+                                   int max_rounds, double tol, int* n_eig,
+                                   double* E, double* margin, long long* n_sel,
+                                   int* n_kept) {
+  if (!c) return OFM_E_INVALID;
+  return guarded(c, [&]() -> ofm_status {
+    OFM_REQUIRE(m && m->ctx == c && n_eig && E, OFM_E_INVALID, "bad arguments");
+    OFM_REQUIRE(std::isfinite(s_thresh) && s_thresh >= 0, OFM_E_INVALID,
+                "s_thresh must be finite and >= 0");
+    OFM_REQUIRE(std::isfinite(e_lo) && std::isfinite(e_hi) && e_hi >= e_lo,
+                OFM_E_INVALID, "the window must be finite with e_hi >= e_lo");
+    OFM_REQUIRE(std::isfinite(margin0) && margin0 >= 0 &&
+                    std::isfinite(margin_step) && margin_step > 0,
+                OFM_E_INVALID, "margin0 must be >= 0 and margin_step > 0");
+    OFM_REQUIRE(max_rounds >= 2 && std::isfinite(tol) && tol >= 0,
+                OFM_E_INVALID, "max_rounds must be >= 2 and tol >= 0");
+    const ofm_frags* f = m->frags;
+    OFM_REQUIRE(f->have_states && (long long)f->eps_host.size() == f->n_basis,
+                OFM_E_STATE, "no fragment eigenvalues");
+    use_device(c);
+    const double t0 = now_ms();
+    std::vector<unsigned char> keep(f->n_basis);
+    std::vector<double> cur(f->n_basis), prev;
+    bool have_prev = false, conv = false;
+    long long last = -1;
+    int ne = 0;
+    for (int r = 0; r < max_rounds && !conv; ++r) {
+      const double d = margin0 + r * margin_step;
+      long long cnt = 0;
+      for (long long i = 0; i < f->n_basis; ++i) {
+        const double e = f->eps_host[i];
+        keep[i] = (e >= e_lo - d && e <= e_hi + d) ? 1 : 0;
+        cnt += keep[i];
+      }
+      // a band that adds nothing to the last one solved gives nothing new
+      if (cnt == 0 || cnt == last) continue;
+      int kept = 0;
+      global_solve(c, m, s_thresh, e_lo, e_hi, &kept, &ne, cur.data(), nullptr,
+                   nullptr, keep.data());
+      if (cnt == f->n_basis) {   // the whole basis: the full solve
+        conv = true;
+      } else if (have_prev && (int)prev.size() == ne) {
+        double dmax = 0;
+        for (int i = 0; i < ne; ++i) dmax = std::max(dmax, std::fabs(cur[i] - prev[i]));
+        conv = dmax <= tol;
+      }
+      prev.assign(cur.begin(), cur.begin() + ne);
+      have_prev = true;
+      last = cnt;
+      if (margin) *margin = d;
+      if (n_sel) *n_sel = cnt;
+      if (n_kept) *n_kept = kept;
+    }
+    ne = have_prev ? (int)prev.size() : 0;
+    *n_eig = ne;
+    for (int i = 0; i < ne; ++i) E[i] = prev[i];
+    c->t_global = now_ms() - t0;
+    if (!conv) {
+      c->err = "the window's eigenvalues did not settle within max_rounds";
+      return OFM_E_NOCONV;
     }
     return OFM_OK;
   });

@@ -9,8 +9,9 @@
 //                   Ritz), one workgroup per fragment, FP64 in LDS.
 //  * k_rotate       X <- X Q (and HX <- HX Q with fused residual norms).
 //  * k_whole_h      H|phi> with the whole-system H on the dilated box.
-//  * k_pair         grouped pair contraction C = A^T B over box overlaps,
-//                   FP64 MFMA, one workgroup per block.
+//  * k_pair         grouped pair contraction: H_jn and S_jn of a pair over
+//                   the box overlaps, FP64 MFMA, one workgroup per pair
+//                   (k_pair_x3: split-BF16 x3 MFMA, mixed form).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -284,34 +285,77 @@ template void gram<float>(ofm_ctx*, const ofm_frags*, const float*,
                           const float*, double*, const int*, double, double);
 
 // ---------------------------------------------------------------------------
-// mixed form: 3-term split-BF16 products on MFMA (16x16x32) with FP32
-// accumulation.  a = a_hi + a_lo with a_hi = bf16(a), a_lo = bf16(a - a_hi);
-// a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi (the dropped a_lo b_lo term is
-// ~2^-16 |a b|).  Each chunk's FP32 sums are stored as FP64 partials and the
-// partials are added in FP64 by the consumer.
-// Operand placement as for the FP64 kernel, 8 consecutive points per lane;
+// mixed forms: 3-term split products on MFMA (16x16x32) with FP32
+// accumulation, a b ~ a_hi b_hi + (a_hi b_lo + a_lo b_hi) s:
+//  * BF16 x3: a_hi = bf16(a), a_lo = bf16(a - a_hi), s = 1; the dropped
+//    a_lo b_lo term is ~2^-16 |a b|;
+//  * FP16 x3: a_hi = f16(a), a_lo = f16((a - a_hi) 2^11), s = 2^-11 (the
+//    scaled low part stays in FP16's normal range wherever a_hi does, and
+//    below it a_lo carries what the subnormal a_hi loses); the dropped term
+//    is ~2^-22 |a b|.  Box vectors are unit-norm states or H times them, so
+//    every operand lies far inside FP16's range (|a| <= ~40).
+// a_hi b_hi and the two cross products go to separate FP32 accumulators,
+// which are added into FP64 sums (cross scaled by s) every few hundred
+// points: the FP32 error stays that of a short sum, the long sums are
+// FP64.  The separate cross accumulator matters in the BF16 form too: with
+// the cross products added into the a_hi b_hi accumulator over four
+// products, the element error measured 8.5e-5 of max|H| on the tiny chain
+// against 5.6e-7 (the small cross terms lose their low bits when an MFMA
+// adds them to a large accumulator).
+// Operand placement as for the FP64 kernels, 8 consecutive points per lane;
 // accumulator item i of lane l holds row 4 (l/16) + i, column l % 16.
 // ---------------------------------------------------------------------------
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ void split8(const float* v, bf8v& hi, bf8v& lo) {
+template <int MODE>   // 0: split-BF16 x3, 1: scaled split-FP16 x3
+struct Split3;
+
+template <>
+struct Split3<0> {
+  typedef bf8v V;
+  static constexpr double kCross = 1.0;
+  static __device__ __forceinline__ void split(const float* v, V& hi, V& lo) {
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const __bf16 h = (__bf16)v[t];
-    hi[t] = h;
-    lo[t] = (__bf16)(v[t] - (float)h);
+    for (int t = 0; t < 8; ++t) {
+      const __bf16 h = (__bf16)v[t];
+      hi[t] = h;
+      lo[t] = (__bf16)(v[t] - (float)h);
+    }
   }
-}
+  static __device__ __forceinline__ f4v mma(const V& a, const V& b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
 
-__device__ __forceinline__ f4v mfma_x3(const float* a, const float* b, f4v acc) {
-  bf8v ah, al, bh, bl;
-  split8(a, ah, al);
-  split8(b, bh, bl);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-  return acc;
+template <>
+struct Split3<1> {
+  typedef h8v V;
+  static constexpr double kCross = 1.0 / 2048.0;
+  static __device__ __forceinline__ void split(const float* v, V& hi, V& lo) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const _Float16 h = (_Float16)v[t];
+      hi[t] = h;
+      lo[t] = (_Float16)((v[t] - (float)h) * 2048.0f);
+    }
+  }
+  static __device__ __forceinline__ f4v mma(const V& a, const V& b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// acc_hh += a_hi b_hi, acc_x += a_hi b_lo + a_lo b_hi
+template <int MODE>
+__device__ __forceinline__ void mma3(const typename Split3<MODE>::V& ah,
+                                     const typename Split3<MODE>::V& al,
+                                     const typename Split3<MODE>::V& bh,
+                                     const typename Split3<MODE>::V& bl,
+                                     f4v& hh, f4v& x) {
+  hh = Split3<MODE>::mma(ah, bh, hh);
+  x = Split3<MODE>::mma(ah, bl, x);
+  x = Split3<MODE>::mma(al, bh, x);
 }
 
 __device__ __forceinline__ void load8(const float* p, float* o) {
@@ -321,10 +365,15 @@ __device__ __forceinline__ void load8(const float* p, float* o) {
   o[4] = w[0]; o[5] = w[1]; o[6] = w[2]; o[7] = w[3];
 }
 
+// points per FP64 flush of the Gram kernel's FP32 sums (per wave and tile)
+constexpr int GRAM_FLUSH_PTS = 256;
+
+template <int MODE>
 __global__ __launch_bounds__(WG) void k_gram_x3(
     const FragDev* __restrict__ F, int nf, const float* __restrict__ A,
     const float* __restrict__ B, double* __restrict__ partial,
     const int* __restrict__ active) {
+  using SP = Split3<MODE>;
   const int j = blockIdx.x / GCH, ch = blockIdx.x % GCH;
   if (j >= nf) return;
   if (active && !active[j]) return;
@@ -346,18 +395,30 @@ __global__ __launch_bounds__(WG) void k_gram_x3(
       const bool va = ra < bw, vb = rb < bw;
       const float* pa = A + fr.x_off + (long long)(va ? ra : 0) * fr.ld;
       const float* pb = B + fr.x_off + (long long)(vb ? rb : 0) * fr.ld;
-      f4v acc = {0, 0, 0, 0};
+      f4v hh = {0, 0, 0, 0}, x = {0, 0, 0, 0};
+      double tot[4] = {0, 0, 0, 0};
+      int since = 0;
       // kb and ke are multiples of 32: uniform trip count across the wave
       for (int k = kb + 8 * g; k < ke; k += 32) {
         float a[8] = {0, 0, 0, 0, 0, 0, 0, 0}, b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (va) load8(pa + k, a);
         if (vb) load8(pb + k, b);
-        acc = mfma_x3(a, b, acc);
+        typename SP::V ah, al, bh, bl;
+        SP::split(a, ah, al);
+        SP::split(b, bh, bl);
+        mma3<MODE>(ah, al, bh, bl, hh, x);
+        if (++since == GRAM_FLUSH_PTS / 32) {
+          since = 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) tot[i] += (double)hh[i] + SP::kCross * (double)x[i];
+          hh = x = f4v{0, 0, 0, 0};
+        }
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        tot[i] += (double)hh[i] + SP::kCross * (double)x[i];
         const int row = ti * 16 + 4 * g + i, col = tj * 16 + r;
-        if (row < bw && col < bw) out[row * bw + col] = (double)acc[i];
+        if (row < bw && col < bw) out[row * bw + col] = tot[i];
       }
     }
   }
@@ -366,8 +427,12 @@ __global__ __launch_bounds__(WG) void k_gram_x3(
 void gram_x3(ofm_ctx* c, const ofm_frags* f, const float* A, const float* B,
              double* G, const int* active, double bytes, double flops) {
   Timed tm(c, "gram", bytes, flops);
-  hipLaunchKernelGGL(k_gram_x3, dim3(f->n_frag * GCH), dim3(WG), 0, c->stream,
-                     f->d_frag, f->n_frag, A, B, G, active);
+  if (c->precision == OFM_MIXED_FP16X3)
+    hipLaunchKernelGGL(k_gram_x3<1>, dim3(f->n_frag * GCH), dim3(WG), 0,
+                       c->stream, f->d_frag, f->n_frag, A, B, G, active);
+  else
+    hipLaunchKernelGGL(k_gram_x3<0>, dim3(f->n_frag * GCH), dim3(WG), 0,
+                       c->stream, f->d_frag, f->n_frag, A, B, G, active);
   OFM_HIP(hipGetLastError());
 }
 
@@ -989,339 +1054,558 @@ template void whole_h<float>(ofm_ctx*, const ofm_frags*, const float*, float*,
                              int);
 
 // ---------------------------------------------------------------------------
-// grouped pair contraction: one workgroup per (pair, S|H) block
+// grouped pair contraction: one workgroup per pair, its H and S blocks
+// together
 // ---------------------------------------------------------------------------
-// The overlap Omega of a block is walked row by row (x fastest), each row
-// padded to a multiple of 4 points, in stages of KST padded points.  A stage
-// is loaded into LDS with one thread per (state, point) -- a wave reads
-// consecutive points of one state row -- and the MFMA tiles read their
-// operands from LDS.  Work split of a block over the 4 waves: blocks with
-// fewer than four 16x16 tiles split every stage's points instead (k-slices),
-// summed in a fixed order at the end.
-struct StagePos {   // a thread's point inside the current stage
-  int xg, yy, zz;   // 4-point group along x, row y, plane z of Omega
+// Omega' (the support of the H block, with Omega, the support of S, inside
+// it) is walked in groups of G consecutive points along x, every row of
+// Omega' padded to whole groups.  Lane (r, g) of a wave feeds state r of
+// each 16-state tile with the G points of group g of the wave's current
+// chunk of four groups, loaded from global memory straight into MFMA
+// operands (no LDS staging and no barrier in the loop); the states of
+// fragment j are loaded once for both blocks.  Work split over the four
+// waves of a workgroup:
+//  * blocks of at most 32 x 32 states (KSPLIT): every wave computes all
+//    tiles of both blocks over every fourth chunk; the four waves' sums are
+//    added in LDS in wave order;
+//  * wider blocks: wave w computes row tile w of both blocks over every
+//    chunk.
+// Every sum is formed in a fixed order: the results do not depend on
+// scheduling.
+struct GroupPos {   // a lane's group inside Omega'
+  int q;            // linear group index (x groups fastest, then y, then z)
+  int xg, y, z;
 };
 
-__device__ __forceinline__ StagePos stage_start(int q, int gx, int oy) {
-  StagePos s;
-  s.xg = q % gx;
+__device__ __forceinline__ void group_init(GroupPos& p, int q, int gx, int oy) {
+  p.q = q;
+  p.xg = q % gx;
   const int row = q / gx;
-  s.yy = row % oy;
-  s.zz = row / oy;
-  return s;
+  p.y = row % oy;
+  p.z = row / oy;
 }
 
-__device__ __forceinline__ void stage_advance(StagePos& s, int by, int gx,
-                                              int oy) {
-  s.xg += by;
-  while (s.xg >= gx) {
-    s.xg -= gx;
-    if (++s.yy == oy) {
-      s.yy = 0;
-      ++s.zz;
+// advance by `step` groups, i.e. drow = step / gx whole rows and
+// dx = step % gx groups
+__device__ __forceinline__ void group_step(GroupPos& p, int step, int dx,
+                                           int drow, int gx, int oy) {
+  p.q += step;
+  p.xg += dx;
+  p.y += drow;
+  if (p.xg >= gx) {
+    p.xg -= gx;
+    ++p.y;
+  }
+  while (p.y >= oy) {
+    p.y -= oy;
+    ++p.z;
+  }
+}
+
+__device__ __forceinline__ long long box_off(const int* org, int nx, int nxy,
+                                             int x, int y, int z) {
+  return (long long)(org[0] + x) + (long long)nx * (org[1] + y) +
+         (long long)nxy * (org[2] + z);
+}
+
+// 16-byte vectors at the element type's own alignment: a whole group of a
+// row is loaded with dwordx4 loads wherever it starts
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
+// o[u] = p[off + u] for lo <= u < hi, 0 elsewhere (u < G); a whole group
+// (lo = 0, hi = G) is read with 16-byte loads, a partial one (row ends, the
+// edge of Omega) element by element, so nothing outside [lo, hi) is read
+template <int G, typename TI, typename TO>
+__device__ __forceinline__ void load_range(const TI* __restrict__ p,
+                                           long long off, int lo, int hi,
+                                           TO* o) {
+  constexpr int VW = 16 / sizeof(TI);   // elements per 16-byte load
+  static_assert(G % VW == 0, "a group is whole 16-byte loads");
+  if (lo == 0 && hi == G) {
+#pragma unroll
+    for (int u = 0; u < G; u += VW) {
+      if constexpr (sizeof(TI) == 8) {
+        const d2u v = *reinterpret_cast<const d2u*>(p + off + u);
+        o[u] = (TO)v[0];
+        o[u + 1] = (TO)v[1];
+      } else {
+        const f4u v = *reinterpret_cast<const f4u*>(p + off + u);
+        o[u] = (TO)v[0];
+        o[u + 1] = (TO)v[1];
+        o[u + 2] = (TO)v[2];
+        o[u + 3] = (TO)v[3];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+      o[u] = (u >= lo && u < hi) ? (TO)p[off + u] : TO(0);
+  }
+}
+
+// where a lane's group meets Omega (the S block's support): [slo, shi)
+__device__ __forceinline__ void s_range(const PairTask& tk, const GroupPos& p,
+                                        int x0, int nv, bool doS, int& slo,
+                                        int& shi) {
+  slo = shi = 0;
+  if (doS && nv > 0 && p.y >= tk.s_lo[1] && p.y < tk.s_hi[1] &&
+      p.z >= tk.s_lo[2] && p.z < tk.s_hi[2]) {
+    slo = max(tk.s_lo[0] - x0, 0);
+    shi = min(tk.s_hi[0] - x0, nv);
+  }
+}
+
+// LDS: the cross-wave sums (KSPLIT) and then both blocks as dense
+// RM x RM matrices (row stride RM + 1), H first
+template <int NTA, int NTB, bool KSPLIT>
+struct PairLds {
+  static constexpr int RM = 16 * NTB, LD = RM + 1;
+  static constexpr int RED = KSPLIT ? 2 * NTA * NTB * 256 : 0;
+  static constexpr int OUT = 2 * RM * LD;
+  static constexpr int SIZE = RED > OUT ? RED : OUT;
+};
+
+// write both blocks from the LDS matrices (diagonal blocks symmetrised);
+// with s_ident the S block is the identity
+template <int RM>
+__device__ __forceinline__ void pair_write(const PairTask& tk,
+                                           const double* sh, bool wH,
+                                           bool wS, bool s_ident,
+                                           double* __restrict__ Hout,
+                                           double* __restrict__ Sout) {
+  constexpr int LD = RM + 1;
+  const int ma = tk.ma, mb = tk.mb;
+  double* CH = Hout + tk.c_off;
+  double* CS = Sout + tk.c_off;
+  const double* sS = sh + RM * LD;
+  for (int e = threadIdx.x; e < ma * mb; e += WG) {
+    const int i = e / mb, m = e % mb;
+    if (wH) {
+      double v = sh[i * LD + m];
+      if (tk.sym) v = 0.5 * (v + sh[m * LD + i]);
+      CH[e] = v;
+    }
+    if (s_ident) {
+      CS[e] = i == m ? 1.0 : 0.0;
+    } else if (wS) {
+      double v = sS[i * LD + m];
+      if (tk.sym) v = 0.5 * (v + sS[m * LD + i]);
+      CS[e] = v;
     }
   }
 }
 
-// box offsets of the thread's point in A's and B's boxes (valid: inside
-// Omega, not padding)
-__device__ __forceinline__ bool stage_point(const PairTask& tk,
-                                            const StagePos& s, int x,
-                                            long long& ia, long long& ib) {
-  if (s.zz >= tk.om[2] || x >= tk.om[0]) return false;
-  ia = (tk.a_org[0] + x) +
-       (long long)tk.a_dims[0] *
-           ((tk.a_org[1] + s.yy) + (long long)tk.a_dims[1] * (tk.a_org[2] + s.zz));
-  ib = (tk.b_org[0] + x) +
-       (long long)tk.b_dims[0] *
-           ((tk.b_org[1] + s.yy) + (long long)tk.b_dims[1] * (tk.b_org[2] + s.zz));
-  return true;
-}
-
-// write the block (symmetrised on diagonal blocks) from LDS
-__device__ __forceinline__ void pair_store(const PairTask& tk,
-                                           const double* blk, int ldb,
-                                           double* C) {
-  for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG) {
-    const int i = e / tk.mb, m = e % tk.mb;
-    double v = blk[i * ldb + m];
-    if (tk.sym) v = 0.5 * (v + blk[m * ldb + i]);
-    C[e] = v;
-  }
-}
-
-// FP64 MFMA 16x16x4; RMAX >= the largest state count, a multiple of 16.
-// TI is the storage type of the operands (FP32 operands are widened to FP64
-// when staged, so the products and sums are FP64 either way).
-// With `only_imported_diag_s`, only the diagonal S blocks of imported
-// states (sym, which == 0, ident == 0) are computed and every other task
-// returns at once.
-template <int RMAX, typename TI>
+// FP64 MFMA 16x16x4, G = 4 points per lane group.  TI is the storage type of
+// the operands (FP32 operands are widened, so products and sums are FP64).
+// With s_only, only the S blocks of diagonal tasks of imported states
+// (sym, ident == 0) are computed and every other task returns at once.
+template <int NTA, int NTB, bool KSPLIT, typename TI, bool PF>
 __global__ __launch_bounds__(WG) void k_pair(
-    const PairTask* __restrict__ tasks, int ntask,
-    const TI* __restrict__ PHI, const TI* __restrict__ HPHI,
-    double* __restrict__ Hout, double* __restrict__ Sout,
-    int only_imported_diag_s) {
-  constexpr int KST = 64, LP = KST + 1;
-  constexpr int UMAX = (RMAX / 16) * (RMAX / 16) > 4
-                           ? ((RMAX / 16) * (RMAX / 16) + 3) / 4 : 1;
+    const PairTask* __restrict__ tasks, int ntask, const TI* __restrict__ X,
+    const TI* __restrict__ HP, double* __restrict__ Hout,
+    double* __restrict__ Sout, int s_only) {
+  constexpr int G = 4;
+  using L = PairLds<NTA, NTB, KSPLIT>;
+  __shared__ double sh[L::SIZE];
   const int ti = blockIdx.x;
   if (ti >= ntask) return;
-  const PairTask tk = tasks[ti];
-  if (only_imported_diag_s && !(tk.sym && tk.which == 0 && !tk.ident)) return;
-  const TI* A = PHI + tk.a_off;
-  const TI* B = (tk.which ? HPHI : PHI) + tk.b_off;
-  double* C = (tk.which ? Hout : Sout) + tk.c_off;
-  const int gx = (tk.om[0] + 3) >> 2;
-  const long long ngrp = (long long)gx * tk.om[1] * tk.om[2];
-  const int nst = (int)((4 * ngrp + KST - 1) / KST);
-  const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
-  const int ntiles = nta * ntb;
-  const int ks = ntiles >= 4 ? 1 : 4 / ntiles;
-  const int kw = KST / ks;
-  __shared__ double As[RMAX * LP];
-  __shared__ double Bs[RMAX * LP];
-  __shared__ double part[4][256];
+  const PairTask& tk = tasks[ti];
+  if (s_only && !(tk.sym && !tk.ident)) return;
+  const bool doH = !s_only;
+  const bool doS = tk.has_s != 0;
+  const int ma = tk.ma, mb = tk.mb;
+  const int ox = tk.om[0], oy = tk.om[1], oz = tk.om[2];
+  const int gx = (ox + G - 1) / G;
+  const int ngrp = gx * oy * oz;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  const int pt = threadIdx.x & (KST - 1), i0 = threadIdx.x / KST;
-  StagePos sp = stage_start(pt >> 2, gx, tk.om[1]);
-  d4 acc[UMAX];
+  const int ta0 = KSPLIT ? 0 : wave;           // first row tile of the wave
+  const bool wave_on = KSPLIT || 16 * wave < ma;
+  const TI* pa[NTA];
+  bool va[NTA];
 #pragma unroll
-  for (int u = 0; u < UMAX; ++u) acc[u] = d4{0, 0, 0, 0};
-  for (int st = 0; st < nst; ++st) {
-    long long ia = 0, ib = 0;
-    const bool valid = stage_point(tk, sp, 4 * sp.xg + (pt & 3), ia, ib);
-#pragma unroll
-    for (int m = 0; m < RMAX / (WG / KST); ++m) {
-      const int i = i0 + (WG / KST) * m;
-      As[i * LP + pt] =
-          (valid && i < tk.ma) ? (double)A[(long long)i * tk.lda + ia] : 0.0;
-      Bs[i * LP + pt] =
-          (valid && i < tk.mb) ? (double)B[(long long)i * tk.ldb + ib] : 0.0;
-    }
-    stage_advance(sp, KST / 4, gx, tk.om[1]);
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < UMAX; ++u) {
-      const int unit = wave + 4 * u;
-      if (unit < ntiles * ks) {   // wave-uniform
-        const int tile = unit / ks, slice = unit % ks;
-        const int ta = tile / ntb, tb = tile % ntb;
-        const double* pa = As + (ta * 16 + r) * LP + slice * kw + 4 * g;
-        const double* pb = Bs + (tb * 16 + r) * LP + slice * kw + 4 * g;
-        for (int kk = 0; kk < kw; kk += 16)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[u] = mfma_f64(pa[kk + v], pb[kk + v], acc[u]);
-      }
-    }
-    __syncthreads();
+  for (int t = 0; t < NTA; ++t) {
+    const int row = 16 * (ta0 + t) + r;
+    va[t] = row < ma;
+    pa[t] = X + tk.a_off + (long long)(va[t] ? row : 0) * tk.lda;
   }
-  double* blk = As;   // the staging area is free now
+  const TI* pb[NTB];
+  const TI* ph[NTB];
+  bool vb[NTB];
 #pragma unroll
-  for (int u = 0; u < UMAX; ++u) {
-    const int unit = wave + 4 * u;
-    if (unit < ntiles * ks) {
-      const int tile = unit / ks;
-      const int ta = tile / ntb, tb = tile % ntb;
+  for (int t = 0; t < NTB; ++t) {
+    const int row = 16 * t + r;
+    vb[t] = row < mb;
+    pb[t] = X + tk.b_off + (long long)(vb[t] ? row : 0) * tk.ldb;
+    ph[t] = HP + tk.h_off + (long long)(vb[t] ? row : 0) * tk.ldh;
+  }
+  d4 accH[NTA][NTB], accS[NTA][NTB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rl = g + 4 * i;
-        if (ks == 1) {
-          const int row = ta * 16 + rl, col = tb * 16 + r;
-          if (row < tk.ma && col < tk.mb) blk[row * LP + col] = acc[u][i];
-        } else {
-          part[unit][rl * 16 + r] = acc[u][i];
+  for (int a = 0; a < NTA; ++a)
+#pragma unroll
+    for (int b = 0; b < NTB; ++b) accH[a][b] = accS[a][b] = d4{0, 0, 0, 0};
+  const int step = KSPLIT ? 16 : 4;   // groups per iteration of one wave
+  const int first = KSPLIT ? 4 * wave : 0;
+  GroupPos pos;
+  group_init(pos, first + g, gx, oy);
+  const int dx = step % gx, drow = step / gx;
+  // the operands of a lane's group (zeros outside Omega' / Omega)
+  auto fetch = [&](const GroupPos& p, double (&A)[NTA][G],
+                   double (&BH)[NTB][G], double (&BS)[NTB][G]) {
+    const int x0 = G * p.xg;
+    const int nv = p.q < ngrp ? min(G, ox - x0) : 0;
+    const long long oa = box_off(tk.a_org, tk.a_nx, tk.a_nxy, x0, p.y, p.z);
+    const long long oh = box_off(tk.h_org, tk.h_nx, tk.h_nxy, x0, p.y, p.z);
+    const long long ob = box_off(tk.b_org, tk.b_nx, tk.b_nxy, x0, p.y, p.z);
+    int slo, shi;
+    s_range(tk, p, x0, nv, doS, slo, shi);
+#pragma unroll
+    for (int t = 0; t < NTA; ++t)
+      load_range<G>(pa[t], oa, 0, va[t] ? nv : 0, A[t]);
+#pragma unroll
+    for (int t = 0; t < NTB; ++t) {
+      load_range<G>(ph[t], oh, 0, (doH && vb[t]) ? nv : 0, BH[t]);
+      load_range<G>(pb[t], ob, slo, vb[t] ? shi : 0, BS[t]);
+    }
+  };
+  double a[NTA][G], bh[NTB][G], bs[NTB][G];
+  if (PF && wave_on && first < ngrp) fetch(pos, a, bh, bs);
+  if (wave_on)
+    for (int c0 = first; c0 < ngrp; c0 += step) {   // wave-uniform
+      // PF (software pipeline): the next chunk's loads are in flight while
+      // this chunk's products run; otherwise a chunk is loaded, then used
+      const bool more = PF && c0 + step < ngrp;      // wave-uniform
+      GroupPos nxt = pos;
+      group_step(nxt, step, dx, drow, gx, oy);
+      double a2[NTA][G], bh2[NTB][G], bs2[NTB][G];
+      if (!PF) fetch(pos, a, bh, bs);
+      if (more) fetch(nxt, a2, bh2, bs2);
+#pragma unroll
+      for (int ta = 0; ta < NTA; ++ta) {
+        if (16 * (ta0 + ta) >= ma) continue;   // wave-uniform
+#pragma unroll
+        for (int tb = 0; tb < NTB; ++tb) {
+          if (16 * tb >= mb) continue;
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            if (doH) accH[ta][tb] = mfma_f64(a[ta][u], bh[tb][u], accH[ta][tb]);
+            if (doS) accS[ta][tb] = mfma_f64(a[ta][u], bs[tb][u], accS[ta][tb]);
+          }
         }
       }
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < NTA; ++t)
+#pragma unroll
+          for (int u = 0; u < G; ++u) a[t][u] = a2[t][u];
+#pragma unroll
+        for (int t = 0; t < NTB; ++t)
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            bh[t][u] = bh2[t][u];
+            bs[t][u] = bs2[t][u];
+          }
+      }
+      pos = nxt;
     }
+  if constexpr (KSPLIT) {
+    // the four waves' sums, in wave order
+    for (int w = 1; w < WG / 64; ++w) {
+      if (wave == w)
+#pragma unroll
+        for (int a = 0; a < NTA; ++a)
+#pragma unroll
+          for (int b = 0; b < NTB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              sh[(((0 * NTA + a) * NTB + b) * 4 + i) * 64 + lane] = accH[a][b][i];
+              sh[(((1 * NTA + a) * NTB + b) * 4 + i) * 64 + lane] = accS[a][b][i];
+            }
+      __syncthreads();
+      if (wave == 0)
+#pragma unroll
+        for (int a = 0; a < NTA; ++a)
+#pragma unroll
+          for (int b = 0; b < NTB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              accH[a][b][i] += sh[(((0 * NTA + a) * NTB + b) * 4 + i) * 64 + lane];
+              accS[a][b][i] += sh[(((1 * NTA + a) * NTB + b) * 4 + i) * 64 + lane];
+            }
+      __syncthreads();
+    }
+  }
+  // accumulator item i of lane (r, g): row g + 4 i, column r of the tile
+  if (KSPLIT ? wave == 0 : wave_on) {
+#pragma unroll
+    for (int a = 0; a < NTA; ++a)
+#pragma unroll
+      for (int b = 0; b < NTB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * (ta0 + a) + g + 4 * i, col = 16 * b + r;
+          if (row < ma && col < mb) {
+            sh[row * L::LD + col] = accH[a][b][i];
+            sh[L::RM * L::LD + row * L::LD + col] = accS[a][b][i];
+          }
+        }
   }
   __syncthreads();
-  if (ks > 1) {
-    for (int e = threadIdx.x; e < ntiles * 256; e += WG) {
-      const int tile = e / 256, rl = (e % 256) / 16, cl = e % 16;
-      double v = 0;
-      for (int sl = 0; sl < ks; ++sl) v += part[tile * ks + sl][rl * 16 + cl];
-      const int row = (tile / ntb) * 16 + rl, col = (tile % ntb) * 16 + cl;
-      if (row < tk.ma && col < tk.mb) blk[row * LP + col] = v;
-    }
-    __syncthreads();
-  }
-  pair_store(tk, blk, LP, C);
+  pair_write<L::RM>(tk, sh, doH, doS, false, Hout, Sout);
 }
 
-// mixed form of the pair contraction: split-BF16 x3 MFMA 16x16x32 on FP32
-// states, FP32 sums of a stage flushed into FP64; the diagonal S block of a
-// fragment whose states the solver orthonormalised in FP64 is the identity
-// (tasks marked `ident`; the dropped a_lo b_lo term would bias its diagonal
-// by ~2^-18), imported states get theirs from k_pair<.., float>
-template <int RMAX>
+// mixed forms: split x3 MFMA 16x16x32 on the FP32 operands (MODE as in
+// Split3), G = 8 points per lane group, the FP32 sums (a_hi b_hi and the
+// cross terms apart) flushed into FP64 every PAIR_FLUSH iterations of a wave
+// (128 points of Omega' per wave at most).  Diagonal S blocks: the identity
+// for the solver's FP64-orthonormalised states (ident); for imported states
+// k_pair<.., float> (s_only) computes them.
+constexpr int PAIR_FLUSH = 4;
+
+template <int NTA, int NTB, bool KSPLIT, int MODE, bool PF>
 __global__ __launch_bounds__(WG) void k_pair_x3(
     const PairTask* __restrict__ tasks, int ntask,
-    const float* __restrict__ PHI, const float* __restrict__ HPHI,
+    const float* __restrict__ X, const float* __restrict__ HP,
     double* __restrict__ Hout, double* __restrict__ Sout) {
-  constexpr int KST = 128, LP = KST + 4;
-  constexpr int UMAX = (RMAX / 16) * (RMAX / 16) > 4
-                           ? ((RMAX / 16) * (RMAX / 16) + 3) / 4 : 1;
+  constexpr int G = 8;
+  using L = PairLds<NTA, NTB, KSPLIT>;
+  __shared__ double sh[L::SIZE];
   const int ti = blockIdx.x;
   if (ti >= ntask) return;
-  const PairTask tk = tasks[ti];
-  double* C = (tk.which ? Hout : Sout) + tk.c_off;
-  if (tk.sym && tk.which == 0) {
-    if (tk.ident)
-      for (int e = threadIdx.x; e < tk.ma * tk.mb; e += WG)
-        C[e] = (e / tk.mb == e % tk.mb) ? 1.0 : 0.0;
-    return;   // imported states: k_pair<.., float> computes this block
-  }
-  const float* A = PHI + tk.a_off;
-  const float* B = (tk.which ? HPHI : PHI) + tk.b_off;
-  const int gx = (tk.om[0] + 3) >> 2;
-  const long long ngrp = (long long)gx * tk.om[1] * tk.om[2];
-  const int nst = (int)((4 * ngrp + KST - 1) / KST);
-  const int nta = (tk.ma + 15) / 16, ntb = (tk.mb + 15) / 16;
-  const int ntiles = nta * ntb;
-  const int ks = ntiles >= 4 ? 1 : 4 / ntiles;
-  const int kw = KST / ks;
-  __shared__ float As[RMAX * LP];
-  __shared__ float Bs[RMAX * LP];
-  __shared__ double part[4][256];
-  __shared__ double blk[RMAX * (RMAX + 1)];
+  const PairTask& tk = tasks[ti];
+  const bool s_ident = tk.sym && tk.ident;
+  const bool doS = tk.has_s && !tk.sym;   // diagonal S: identity or s_only
+  const int ma = tk.ma, mb = tk.mb;
+  const int ox = tk.om[0], oy = tk.om[1], oz = tk.om[2];
+  const int gx = (ox + G - 1) / G;
+  const int ngrp = gx * oy * oz;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  // a thread loads two consecutive groups' worth of points: 2 x 64 = KST
-  const int pt = threadIdx.x & 63, i0 = threadIdx.x >> 6;
-  StagePos sp0 = stage_start(pt >> 2, gx, tk.om[1]);
-  StagePos sp1 = stage_start((pt >> 2) + 16, gx, tk.om[1]);
-  f4v acc[UMAX];
-  double tot[UMAX][4];
+  const int ta0 = KSPLIT ? 0 : wave;
+  const bool wave_on = KSPLIT || 16 * wave < ma;
+  const float* pa[NTA];
+  bool va[NTA];
 #pragma unroll
-  for (int u = 0; u < UMAX; ++u) {
-    acc[u] = f4v{0, 0, 0, 0};
-    tot[u][0] = tot[u][1] = tot[u][2] = tot[u][3] = 0;
+  for (int t = 0; t < NTA; ++t) {
+    const int row = 16 * (ta0 + t) + r;
+    va[t] = row < ma;
+    pa[t] = X + tk.a_off + (long long)(va[t] ? row : 0) * tk.lda;
   }
-  for (int st = 0; st < nst; ++st) {
-    long long ia0 = 0, ib0 = 0, ia1 = 0, ib1 = 0;
-    const bool v0 = stage_point(tk, sp0, 4 * sp0.xg + (pt & 3), ia0, ib0);
-    const bool v1 = stage_point(tk, sp1, 4 * sp1.xg + (pt & 3), ia1, ib1);
+  const float* pb[NTB];
+  const float* ph[NTB];
+  bool vb[NTB];
 #pragma unroll
-    for (int m = 0; m < RMAX / 4; ++m) {
-      const int i = i0 + 4 * m;
-      const bool ra = i < tk.ma, rb = i < tk.mb;
-      As[i * LP + pt] = (v0 && ra) ? A[(long long)i * tk.lda + ia0] : 0.f;
-      As[i * LP + 64 + pt] = (v1 && ra) ? A[(long long)i * tk.lda + ia1] : 0.f;
-      Bs[i * LP + pt] = (v0 && rb) ? B[(long long)i * tk.ldb + ib0] : 0.f;
-      Bs[i * LP + 64 + pt] = (v1 && rb) ? B[(long long)i * tk.ldb + ib1] : 0.f;
+  for (int t = 0; t < NTB; ++t) {
+    const int row = 16 * t + r;
+    vb[t] = row < mb;
+    pb[t] = X + tk.b_off + (long long)(vb[t] ? row : 0) * tk.ldb;
+    ph[t] = HP + tk.h_off + (long long)(vb[t] ? row : 0) * tk.ldh;
+  }
+  using SP = Split3<MODE>;
+  f4v accH[NTA][NTB], accS[NTA][NTB], crH[NTA][NTB], crS[NTA][NTB];
+  double totH[NTA][NTB][4], totS[NTA][NTB][4];
+#pragma unroll
+  for (int a = 0; a < NTA; ++a)
+#pragma unroll
+    for (int b = 0; b < NTB; ++b) {
+      accH[a][b] = accS[a][b] = crH[a][b] = crS[a][b] = f4v{0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) totH[a][b][i] = totS[a][b][i] = 0.0;
     }
-    stage_advance(sp0, KST / 4, gx, tk.om[1]);
-    stage_advance(sp1, KST / 4, gx, tk.om[1]);
-    __syncthreads();
+  auto flush = [&]() {
 #pragma unroll
-    for (int u = 0; u < UMAX; ++u) {
-      const int unit = wave + 4 * u;
-      if (unit < ntiles * ks) {   // wave-uniform
-        const int tile = unit / ks, slice = unit % ks;
-        const int ta = tile / ntb, tb = tile % ntb;
-        const float* pa = As + (ta * 16 + r) * LP + slice * kw + 8 * g;
-        const float* pb = Bs + (tb * 16 + r) * LP + slice * kw + 8 * g;
-        for (int kk = 0; kk < kw; kk += 32) {
-          float a[8], b[8];
+    for (int a = 0; a < NTA; ++a)
 #pragma unroll
-          for (int v = 0; v < 8; ++v) {
-            a[v] = pa[kk + v];
-            b[v] = pb[kk + v];
+      for (int b = 0; b < NTB; ++b) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          totH[a][b][i] += (double)accH[a][b][i] + SP::kCross * (double)crH[a][b][i];
+          totS[a][b][i] += (double)accS[a][b][i] + SP::kCross * (double)crS[a][b][i];
+        }
+        accH[a][b] = accS[a][b] = crH[a][b] = crS[a][b] = f4v{0, 0, 0, 0};
+      }
+  };
+  const int step = KSPLIT ? 16 : 4;
+  const int first = KSPLIT ? 4 * wave : 0;
+  GroupPos pos;
+  group_init(pos, first + g, gx, oy);
+  const int dx = step % gx, drow = step / gx;
+  // the operands of a lane's group (zeros outside Omega' / Omega)
+  auto fetch = [&](const GroupPos& p, float (&A)[NTA][G], float (&BH)[NTB][G],
+                   float (&BS)[NTB][G]) {
+    const int x0 = G * p.xg;
+    const int nv = p.q < ngrp ? min(G, ox - x0) : 0;
+    const long long oa = box_off(tk.a_org, tk.a_nx, tk.a_nxy, x0, p.y, p.z);
+    const long long oh = box_off(tk.h_org, tk.h_nx, tk.h_nxy, x0, p.y, p.z);
+    const long long ob = box_off(tk.b_org, tk.b_nx, tk.b_nxy, x0, p.y, p.z);
+    int slo, shi;
+    s_range(tk, p, x0, nv, doS, slo, shi);
+#pragma unroll
+    for (int t = 0; t < NTA; ++t)
+      load_range<G>(pa[t], oa, 0, va[t] ? nv : 0, A[t]);
+#pragma unroll
+    for (int t = 0; t < NTB; ++t) {
+      load_range<G>(ph[t], oh, 0, vb[t] ? nv : 0, BH[t]);
+      load_range<G>(pb[t], ob, slo, vb[t] ? shi : 0, BS[t]);
+    }
+  };
+  int since = 0;
+  float fa[NTA][G], fh[NTB][G], fs[NTB][G];
+  if (PF && wave_on && first < ngrp) fetch(pos, fa, fh, fs);
+  if (wave_on)
+    for (int c0 = first; c0 < ngrp; c0 += step) {   // wave-uniform
+      // PF (software pipeline): the next chunk's loads are in flight while
+      // this chunk's products run; otherwise a chunk is loaded, then used
+      const bool more = PF && c0 + step < ngrp;      // wave-uniform
+      GroupPos nxt = pos;
+      group_step(nxt, step, dx, drow, gx, oy);
+      float fa2[NTA][G], fh2[NTB][G], fs2[NTB][G];
+      if (!PF) fetch(pos, fa, fh, fs);
+      if (more) fetch(nxt, fa2, fh2, fs2);
+      typename SP::V ah[NTA], al[NTA];
+#pragma unroll
+      for (int t = 0; t < NTA; ++t) SP::split(fa[t], ah[t], al[t]);
+#pragma unroll
+      for (int tb = 0; tb < NTB; ++tb) {
+        if (16 * tb >= mb) continue;   // wave-uniform
+        typename SP::V bh, bl, sh8, sl8;
+        SP::split(fh[tb], bh, bl);
+        if (doS) SP::split(fs[tb], sh8, sl8);
+#pragma unroll
+        for (int ta = 0; ta < NTA; ++ta) {
+          if (16 * (ta0 + ta) >= ma) continue;
+          mma3<MODE>(ah[ta], al[ta], bh, bl, accH[ta][tb], crH[ta][tb]);
+          if (doS)
+            mma3<MODE>(ah[ta], al[ta], sh8, sl8, accS[ta][tb], crS[ta][tb]);
+        }
+      }
+      if (++since == PAIR_FLUSH) {
+        since = 0;
+        flush();
+      }
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < NTA; ++t)
+#pragma unroll
+          for (int u = 0; u < G; ++u) fa[t][u] = fa2[t][u];
+#pragma unroll
+        for (int t = 0; t < NTB; ++t)
+#pragma unroll
+          for (int u = 0; u < G; ++u) {
+            fh[t][u] = fh2[t][u];
+            fs[t][u] = fs2[t][u];
           }
-          acc[u] = mfma_x3(a, b, acc[u]);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) tot[u][i] += (double)acc[u][i];
-        acc[u] = f4v{0, 0, 0, 0};
       }
+      pos = nxt;
     }
-    __syncthreads();
+  flush();
+  if constexpr (KSPLIT) {
+    for (int w = 1; w < WG / 64; ++w) {
+      if (wave == w)
+#pragma unroll
+        for (int a = 0; a < NTA; ++a)
+#pragma unroll
+          for (int b = 0; b < NTB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              sh[(((0 * NTA + a) * NTB + b) * 4 + i) * 64 + lane] = totH[a][b][i];
+              sh[(((1 * NTA + a) * NTB + b) * 4 + i) * 64 + lane] = totS[a][b][i];
+            }
+      __syncthreads();
+      if (wave == 0)
+#pragma unroll
+        for (int a = 0; a < NTA; ++a)
+#pragma unroll
+          for (int b = 0; b < NTB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              totH[a][b][i] += sh[(((0 * NTA + a) * NTB + b) * 4 + i) * 64 + lane];
+              totS[a][b][i] += sh[(((1 * NTA + a) * NTB + b) * 4 + i) * 64 + lane];
+            }
+      __syncthreads();
+    }
   }
+  // accumulator item i of lane (r, g): row 4 g + i, column r of the tile
+  if (KSPLIT ? wave == 0 : wave_on) {
 #pragma unroll
-  for (int u = 0; u < UMAX; ++u) {
-    const int unit = wave + 4 * u;
-    if (unit < ntiles * ks) {
-      const int tile = unit / ks;
-      const int ta = tile / ntb, tb = tile % ntb;
+    for (int a = 0; a < NTA; ++a)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rl = 4 * g + i;
-        if (ks == 1) {
-          const int row = ta * 16 + rl, col = tb * 16 + r;
-          if (row < tk.ma && col < tk.mb) blk[row * (RMAX + 1) + col] = tot[u][i];
-        } else {
-          part[unit][rl * 16 + r] = tot[u][i];
+      for (int b = 0; b < NTB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * (ta0 + a) + 4 * g + i, col = 16 * b + r;
+          if (row < ma && col < mb) {
+            sh[row * L::LD + col] = totH[a][b][i];
+            sh[L::RM * L::LD + row * L::LD + col] = totS[a][b][i];
+          }
         }
-      }
-    }
   }
   __syncthreads();
-  if (ks > 1) {
-    for (int e = threadIdx.x; e < ntiles * 256; e += WG) {
-      const int tile = e / 256, rl = (e % 256) / 16, cl = e % 16;
-      double v = 0;
-      for (int sl = 0; sl < ks; ++sl) v += part[tile * ks + sl][rl * 16 + cl];
-      const int row = (tile / ntb) * 16 + rl, col = (tile % ntb) * 16 + cl;
-      if (row < tk.ma && col < tk.mb) blk[row * (RMAX + 1) + col] = v;
-    }
-    __syncthreads();
-  }
-  pair_store(tk, blk, RMAX + 1, C);
+  pair_write<L::RM>(tk, sh, true, doS, s_ident, Hout, Sout);
 }
 
 template <typename T>
 void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
                    int n_tasks, const T* phi, const T* hphi, double* H,
-                   double* S, double flops, double bytes) {
+                   double* S, double flops, double bytes, int variant) {
+  if (n_tasks <= 0) return;
   Timed tm(c, "elements", bytes, flops);
-  const int rm = f->max_states <= 16 ? 16 : f->max_states <= 32 ? 32
-               : f->max_states <= 48 ? 48 : 64;
-#define PAIR(R)                                                              \
+  const int nt = (f->max_states + 15) / 16;
+  const bool fp16 = c->precision == OFM_MIXED_FP16X3;
+#define PAIR1(A, B, K, PF)                                                   \
   do {                                                                       \
     if constexpr (sizeof(T) == 8)                                            \
-      hipLaunchKernelGGL((k_pair<R, double>), dim3(n_tasks), dim3(WG), 0,    \
-                         c->stream,                                          \
-                         tasks, n_tasks, (const double*)phi,                 \
-                         (const double*)hphi, H, S, 0);                      \
+      hipLaunchKernelGGL((k_pair<A, B, K, double, PF>), dim3(n_tasks),       \
+                         dim3(WG), 0, c->stream, tasks, n_tasks,             \
+                         (const double*)phi, (const double*)hphi, H, S, 0);  \
+    else if (fp16)                                                           \
+      hipLaunchKernelGGL((k_pair_x3<A, B, K, 1, PF>), dim3(n_tasks),         \
+                         dim3(WG), 0, c->stream, tasks, n_tasks,             \
+                         (const float*)phi, (const float*)hphi, H, S);       \
     else                                                                     \
-      hipLaunchKernelGGL(k_pair_x3<R>, dim3(n_tasks), dim3(WG), 0,           \
-                         c->stream, tasks, n_tasks, (const float*)phi,       \
-                         (const float*)hphi, H, S);                          \
+      hipLaunchKernelGGL((k_pair_x3<A, B, K, 0, PF>), dim3(n_tasks),         \
+                         dim3(WG), 0, c->stream, tasks, n_tasks,             \
+                         (const float*)phi, (const float*)hphi, H, S);       \
   } while (0)
-  if (rm == 16) PAIR(16);
-  else if (rm == 32) PAIR(32);
-  else if (rm == 48) PAIR(48);
-  else PAIR(64);
+#define PAIR(A, B, K)                                                        \
+  do {                                                                       \
+    if (variant == 1) PAIR1(A, B, K, true);                                  \
+    else PAIR1(A, B, K, false);                                              \
+  } while (0)
+  if (nt <= 1) PAIR(1, 1, true);
+  else if (nt == 2) PAIR(2, 2, true);
+  else if (nt == 3) PAIR(1, 3, false);
+  else PAIR(1, 4, false);
 #undef PAIR
+#undef PAIR1
   OFM_HIP(hipGetLastError());
 }
+
 void pair_elements_f64_on_f32(ofm_ctx* c, const ofm_frags* f,
                               const PairTask* tasks, int n_tasks,
                               const float* phi, const float* hphi, double* H,
                               double* S) {
   if (n_tasks <= 0) return;
-  const int rm = f->max_states <= 16 ? 16 : f->max_states <= 32 ? 32
-               : f->max_states <= 48 ? 48 : 64;
-#define PAIRF(R)                                                             \
-  hipLaunchKernelGGL((k_pair<R, float>), dim3(n_tasks), dim3(WG), 0,         \
-                     c->stream, tasks, n_tasks, phi, hphi, H, S, 1)
-  if (rm == 16) PAIRF(16);
-  else if (rm == 32) PAIRF(32);
-  else if (rm == 48) PAIRF(48);
-  else PAIRF(64);
+  const int nt = (f->max_states + 15) / 16;
+#define PAIRF(A, B, K)                                                       \
+  hipLaunchKernelGGL((k_pair<A, B, K, float, true>), dim3(n_tasks), dim3(WG), \
+                     0, c->stream, tasks, n_tasks, phi, hphi, H, S, 1)
+  if (nt <= 1) PAIRF(1, 1, true);
+  else if (nt == 2) PAIRF(2, 2, true);
+  else if (nt == 3) PAIRF(1, 3, false);
+  else PAIRF(1, 4, false);
 #undef PAIRF
   OFM_HIP(hipGetLastError());
 }
 template void pair_elements<double>(ofm_ctx*, const ofm_frags*,
                                     const PairTask*, int, const double*,
                                     const double*, double*, double*, double,
-                                    double);
+                                    double, int);
 template void pair_elements<float>(ofm_ctx*, const ofm_frags*, const PairTask*,
                                    int, const float*, const float*, double*,
-                                   double*, double, double);
+                                   double*, double, double, int);
+
 
 __global__ void k_fill_zero(double* __restrict__ p, long long n) {
   for (long long i = blockIdx.x * (long long)WG + threadIdx.x; i < n;

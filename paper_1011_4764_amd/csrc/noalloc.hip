@@ -79,7 +79,8 @@ extern "C" ofm_status ofm_matrix_elements_noalloc(ofm_ctx* c, ofm_frags* f,
                 "the scratch array of this device was not resolved");
     // no timing brackets: their events are not needed here
     c->profiling = false;
-    run_pair_elements(c, f, static_cast<PairTask*>(p), H_dev, S_dev);
+    // no timing runs here: the variant is the pinned, cached or default one
+    run_pair_elements(c, f, static_cast<PairTask*>(p), H_dev, S_dev, false);
     c->profiling = prof;
     return OFM_OK;
   } catch (const Error& e) {

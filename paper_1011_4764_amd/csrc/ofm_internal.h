@@ -50,21 +50,30 @@ struct FragDev {
   double vmax;            // max of V over the box (filter upper bound)
 };
 
-// one task of the grouped pair contraction: C (ma x mb) += A^T B over the
-// cuboid omega, A stored on box a, B on box b (both x-fastest)
+// one task of the grouped pair contraction: both blocks of the pair (j, n),
+// j <= n, over Omega' = box_j ^ dil(box_n), the support of the H block:
+//   H_jn = Phi_j^T (H Phi_n)  over Omega',
+//   S_jn = Phi_j^T Phi_n      over Omega = box_j ^ box_n (inside Omega').
+// Phi_j lives on box_j, Phi_n on box_n, H Phi_n on dil(box_n), x fastest.
 struct PairTask {
-  long long a_off, b_off;   // base offsets of the first vector of A and B
-  long long c_off;          // offset of the ma x mb row-major output block
-  int a_dims[3], b_dims[3]; // dims of the boxes A and B live on
-  int a_org[3], b_org[3];   // omega's corner relative to each box
-  int om[3];                // omega dims
-  int lda, ldb;             // vector strides of A and B
-  int ma, mb;
-  int sym;                  // 1: diagonal block, symmetrise on write
-  int which;                // 0: S block, 1: H block
-  int ident;                // mixed form: write the identity (diagonal S
-                            // block of solver-orthonormalised states)
-  int frag;                 // row fragment j of the block
+  long long a_off;          // Phi_j, first state (state arena)
+  long long b_off;          // Phi_n, first state (state arena)
+  long long h_off;          // H Phi_n, first state (H phi arena)
+  long long c_off;          // offset of both ma x mb row-major blocks
+  int a_org[3];             // Omega' corner in box_j coordinates
+  int b_org[3];             // Omega' corner in box_n coordinates (may be < 0)
+  int h_org[3];             // Omega' corner in dil(box_n) coordinates
+  int om[3];                // Omega' dims
+  int s_lo[3], s_hi[3];     // Omega in Omega' coordinates, [s_lo, s_hi)
+  int a_nx, a_nxy;          // box_j: points per row, per plane
+  int b_nx, b_nxy;          // box_n
+  int h_nx, h_nxy;          // dil(box_n)
+  int lda, ldb, ldh;        // vector strides
+  int ma, mb;               // s_j, s_n
+  int sym;                  // diagonal block: symmetrise on write
+  int has_s;                // Omega is not empty (else S_jn = 0)
+  int ident;                // mixed form: S_jj = I (solver-orthonormalised)
+  int frag;                 // j
 };
 
 // per-fragment Chebyshev filter state (device)
@@ -107,6 +116,8 @@ struct ofm_ctx {
   void* blas = nullptr;    // rocblas_handle, created lazily
   int live = 0;            // fragment / matrix handles made with this context
   std::map<long long, int> tuned;  // stencil variant per (precision, plane class)
+  std::map<int, int> pair_tuned;   // pair-kernel variant per (precision, tile class)
+  int pair_variant = -1;           // pinned pair-kernel variant, -1: autotune
   int n_cu = 256;
 };
 
@@ -144,12 +155,14 @@ struct ofm_frags {
   int2* d_tiles_nr[3] = {nullptr, nullptr, nullptr};
   int n_tiles_nr[3] = {0, 0, 0};
   // multi-step kernel: (fragment, vector) tiles of the boxes it takes, with
-  // the on-chip filter off [0] or on [1] (then it takes none of those), the
-  // largest plane of each set, and the strip tiles of the remaining boxes
-  // per stencil variant
-  int2* d_vt[2] = {nullptr, nullptr};
-  int n_vt[2] = {0, 0};
-  int vt_plane[2] = {0, 0};
+  // the on-chip filter off [0] or on [1] (then it takes none of those), per
+  // class of points per thread (1..4: one launch per class, so a small plane
+  // does not run on a workgroup sized for the largest), and the strip tiles
+  // of the remaining boxes per stencil variant
+  int2* d_vt[2][4] = {{nullptr, nullptr, nullptr, nullptr},
+                      {nullptr, nullptr, nullptr, nullptr}};
+  int n_vt[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  int n_vt_all[2] = {0, 0};
   int2* d_tiles_rest[2][3] = {{nullptr, nullptr, nullptr},
                               {nullptr, nullptr, nullptr}};
   int n_tiles_rest[2][3] = {{0, 0, 0}, {0, 0, 0}};
@@ -291,9 +304,11 @@ void destroy_blas(ofm_ctx* c);
 // the matrix-element stage on a planned task list: sets the tasks' ident
 // flags from the fragments' state origin, uploads the list to d_tasks
 // (device, n_tasks entries), fills H and S (n_values doubles each, device)
-// and launches the contraction kernels on the context stream
+// and launches the contraction kernels on the context stream; with
+// may_tune, a kernel variant not yet chosen for this (precision, tile
+// class) is chosen by timing each variant once (this synchronises)
 void run_pair_elements(ofm_ctx* c, ofm_frags* f, PairTask* d_tasks, double* H,
-                       double* S);
+                       double* S, bool may_tune);
 // per-device scratch of the allocation-free entry point (noalloc.hip):
 // resolved once per device at context creation
 void noalloc_init(int device);
@@ -316,7 +331,8 @@ std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
                                 const std::vector<char>* keep = nullptr);
 // two or three Chebyshev steps per launch for boxes whose plane fits one
 // workgroup
-int multistep_ppt(int elem_bytes, int max_plane);
+// points per thread the multi-step kernel uses for a box (0: not taken)
+int multistep_ppt(int elem_bytes, const FragDev& d);
 bool multistep_eligible(int elem_bytes, const FragDev& d);
 template <typename T>
 void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
@@ -356,16 +372,19 @@ void gauge(hipStream_t s, const ofm_frags* f, T* X);
 template <typename T>
 void whole_h(ofm_ctx* c, const ofm_frags* f, const T* X, T* HPHI,
              int only_frag);
-// every block of the task list (the mixed form leaves the diagonal S
-// blocks of imported states, tasks with sym, which == 0 and ident == 0, to
+// both blocks of every task of the list (the mixed form leaves the diagonal
+// S blocks of imported states, tasks with sym and ident == 0, to
 // pair_elements_f64_on_f32)
+// variant (autotuned, same bits): 0 loads a chunk and then multiplies it,
+// 1 keeps the next chunk's loads in flight during the products
+constexpr int NPAIRVARIANT = 2;
 template <typename T>
 void pair_elements(ofm_ctx* c, const ofm_frags* f, const PairTask* tasks,
                    int n_tasks, const T* phi, const T* hphi, double* H,
-                   double* S, double flops, double bytes);
-// mixed form: the diagonal S blocks of imported states (tasks with sym,
-// which == 0 and ident == 0 of the same list) with FP64 MFMA products on
-// the FP32 operands
+                   double* S, double flops, double bytes, int variant);
+// mixed form: the diagonal S blocks of imported states (tasks with sym and
+// ident == 0 of the same list) with FP64 MFMA products on the FP32
+// operands
 void pair_elements_f64_on_f32(ofm_ctx* c, const ofm_frags* f,
                               const PairTask* tasks, int n_tasks,
                               const float* phi, const float* hphi, double* H,

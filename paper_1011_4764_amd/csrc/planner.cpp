@@ -177,60 +177,43 @@ static bool intersect(const int* alo, const int* ad, const int* blo,
 
 std::vector<PairTask> plan_pair_tasks(const ofm_frags* f) {
   std::vector<PairTask> tasks;
-  tasks.reserve(f->pair_j.size() * 2);
+  tasks.reserve(f->pair_j.size());
   for (size_t p = 0; p < f->pair_j.size(); ++p) {
     const FragDev& a = f->host[f->pair_j[p]];
     const FragDev& b = f->host[f->pair_n[p]];
-    const bool sym = f->pair_j[p] == f->pair_n[p];
-    int lo[3], dm[3];
-    // S block: both states on their own boxes, over box_j ^ box_n
-    if (intersect(a.lo, a.dims, b.lo, b.dims, lo, dm)) {
-      PairTask t{};
-      t.a_off = a.x_off;
-      t.b_off = b.x_off;
-      t.c_off = f->block_off[p];
-      for (int ax = 0; ax < 3; ++ax) {
-        t.a_dims[ax] = a.dims[ax];
-        t.b_dims[ax] = b.dims[ax];
-        t.a_org[ax] = lo[ax] - a.lo[ax];
-        t.b_org[ax] = lo[ax] - b.lo[ax];
-        t.om[ax] = dm[ax];
-      }
-      t.lda = a.ld;
-      t.ldb = b.ld;
-      t.ma = a.n_states;
-      t.mb = b.n_states;
-      t.sym = sym;
-      t.which = 0;
-      t.frag = f->pair_j[p];
-      tasks.push_back(t);
+    int lo[3], dm[3], slo[3], sdm[3];
+    // Omega' = box_j ^ dil(box_n) is never empty for a pair of the list
+    if (!intersect(a.lo, a.dims, b.dlo, b.ddims, lo, dm)) continue;
+    PairTask t{};
+    t.a_off = a.x_off;
+    t.b_off = b.x_off;
+    t.h_off = b.hphi_off;
+    t.c_off = f->block_off[p];
+    t.has_s = intersect(a.lo, a.dims, b.lo, b.dims, slo, sdm) ? 1 : 0;
+    for (int ax = 0; ax < 3; ++ax) {
+      t.a_org[ax] = lo[ax] - a.lo[ax];
+      t.b_org[ax] = lo[ax] - b.lo[ax];
+      t.h_org[ax] = lo[ax] - b.dlo[ax];
+      t.om[ax] = dm[ax];
+      t.s_lo[ax] = t.has_s ? slo[ax] - lo[ax] : 0;
+      t.s_hi[ax] = t.has_s ? slo[ax] + sdm[ax] - lo[ax] : 0;
     }
-    // H block: states of j against H phi of n on n's dilated box
-    if (intersect(a.lo, a.dims, b.dlo, b.ddims, lo, dm)) {
-      PairTask t{};
-      t.a_off = a.x_off;
-      t.b_off = b.hphi_off;
-      t.c_off = f->block_off[p];
-      for (int ax = 0; ax < 3; ++ax) {
-        t.a_dims[ax] = a.dims[ax];
-        t.b_dims[ax] = b.ddims[ax];
-        t.a_org[ax] = lo[ax] - a.lo[ax];
-        t.b_org[ax] = lo[ax] - b.dlo[ax];
-        t.om[ax] = dm[ax];
-      }
-      t.lda = a.ld;
-      t.ldb = b.ldd;
-      t.ma = a.n_states;
-      t.mb = b.n_states;
-      t.sym = sym;
-      t.which = 1;
-      t.frag = f->pair_j[p];
-      tasks.push_back(t);
-    }
+    t.a_nx = a.dims[0];
+    t.a_nxy = a.dims[0] * a.dims[1];
+    t.b_nx = b.dims[0];
+    t.b_nxy = b.dims[0] * b.dims[1];
+    t.h_nx = b.ddims[0];
+    t.h_nxy = b.ddims[0] * b.ddims[1];
+    t.lda = a.ld;
+    t.ldb = b.ld;
+    t.ldh = b.ldd;
+    t.ma = a.n_states;
+    t.mb = b.n_states;
+    t.sym = f->pair_j[p] == f->pair_n[p];
+    t.frag = f->pair_j[p];
+    tasks.push_back(t);
   }
   // longest contraction first: better load balance across workgroups
-  // (grouping the tasks by row fragment for L2 reuse measured no faster:
-  // the gathers, not the HBM misses, bound this kernel)
   std::stable_sort(tasks.begin(), tasks.end(),
                    [](const PairTask& x, const PairTask& y) {
                      const long long kx = (long long)x.om[0] * x.om[1] *

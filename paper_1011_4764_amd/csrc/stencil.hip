@@ -373,19 +373,22 @@ __global__ __launch_bounds__(H2T) void k_apply_hm(
   }
 }
 
-// boxes the multi-step kernel takes: planes that fit at most 2 points per
-// thread in FP64 and 4 in FP32 (beyond that its register windows cost more
-// occupancy than the saved passes are worth, measured)
+// boxes the multi-step kernel takes: planes that fit at most 4 points per
+// thread (a box runs in the launch of its own class of points per thread, so
+// only the large planes pay the larger register windows; on the amorphous
+// workload FP64 planes of 1025..1600 points ran 6% faster overall in the
+// 3- and 4-point classes than in one-step strips)
 bool multistep_eligible(int elem_bytes, const FragDev& d) {
-  return d.dims[0] * d.dims[1] <= (elem_bytes == 8 ? 2 : 4) * H2T;
+  (void)elem_bytes;
+  return d.dims[0] * d.dims[1] <= 4 * H2T;
 }
 
-// points per thread of the multi-step kernel for a largest plane, 0 if none
-// fits
-int multistep_ppt(int elem_bytes, int max_plane) {
-  if (elem_bytes == 8)
-    return max_plane <= H2T ? 1 : max_plane <= 2 * H2T ? 2 : 0;
-  return max_plane <= 2 * H2T ? 2 : max_plane <= 4 * H2T ? 4 : 0;
+// points per thread of the multi-step kernel for one box's plane, the
+// fewest that cover it (0 if the box is not taken); boxes of one class run
+// in one launch
+int multistep_ppt(int elem_bytes, const FragDev& d) {
+  if (!multistep_eligible(elem_bytes, d)) return 0;
+  return (d.dims[0] * d.dims[1] + H2T - 1) / H2T;
 }
 
 template <typename T>
@@ -410,14 +413,11 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
     if (ns == 3) LAUNCHM(PP, 3);                                             \
     else LAUNCHM(PP, 2);                                                     \
   } while (0)
-  // the boxes it takes need at most 2 points per thread in FP64, 4 in FP32
-  if (ppt == 1) {
-    LAUNCHP(1);
-  } else if (ppt == 2) {
-    LAUNCHP(2);
-  } else if (ppt == 4) {
-    if constexpr (sizeof(T) == 4) LAUNCHP(4);
-  }
+  // the boxes it takes need at most 4 points per thread
+  if (ppt == 1) LAUNCHP(1);
+  else if (ppt == 2) LAUNCHP(2);
+  else if (ppt == 3) LAUNCHP(3);
+  else if (ppt == 4) LAUNCHP(4);
 #undef LAUNCHP
 #undef LAUNCHM
   OFM_HIP(hipGetLastError());

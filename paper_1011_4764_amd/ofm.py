@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("OFM_LIB") or os.path.join(_HERE, "libofm.so")
 
 OFM_OK, OFM_E_INVALID, OFM_E_NOMEM, OFM_E_DEVICE = 0, -1, -2, -3
 OFM_E_NOCONV, OFM_E_SINGULAR, OFM_E_STATE = -4, -5, -6
-OFM_FP64, OFM_MIXED_BF16X3 = 0, 1
+OFM_FP64, OFM_MIXED_BF16X3, OFM_MIXED_FP16X3 = 0, 1, 2
 STATUS = {0: "OFM_OK", -1: "OFM_E_INVALID", -2: "OFM_E_NOMEM",
           -3: "OFM_E_DEVICE", -4: "OFM_E_NOCONV", -5: "OFM_E_SINGULAR",
           -6: "OFM_E_STATE"}
@@ -35,6 +35,7 @@ EXPORTS = [
     "ofm_set_stencil_variant", "ofm_set_fragment_wells", "ofm_select_homo",
     "ofm_solve_global_subset", "ofm_homo_energies", "ofm_homo_lumo_gap",
     "ofm_dense_eigh", "ofm_solve_flags", "ofm_matrix_elements_noalloc",
+    "ofm_set_pair_variant", "ofm_select_band", "ofm_solve_global_window",
 ]
 OFM_MAX_APPLY_VECTORS = 32767
 
@@ -113,6 +114,7 @@ def lib():
             "ofm_reset_stats": ([_P], C.c_int),
             "ofm_stage_times": ([_P, _D, _D, _D], C.c_int),
             "ofm_set_stencil_variant": ([_P, C.c_int], C.c_int),
+            "ofm_set_pair_variant": ([_P, C.c_int], C.c_int),
             "ofm_set_fragment_wells": ([_P, C.c_int, _D, _D, C.c_double,
                                         C.c_double, _LL, _I], C.c_int),
             "ofm_select_homo": ([_P, C.c_int, C.c_double, _UB], C.c_int),
@@ -120,6 +122,11 @@ def lib():
                                          C.c_double, _I, _I, _D, _D, _D],
                                         C.c_int),
             "ofm_homo_energies": ([_P, _D], C.c_int),
+            "ofm_select_band": ([_P, C.c_double, C.c_double, _UB], C.c_int),
+            "ofm_solve_global_window": ([_P, _P, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, C.c_double,
+                                         C.c_int, C.c_double, _I, _D, _D,
+                                         _LL, _I], C.c_int),
             "ofm_dense_eigh": ([_P, C.c_int, _D, _D, _D], C.c_int),
             "ofm_homo_lumo_gap": ([_D, C.c_int, C.c_double, C.c_double, _I,
                                    _D, _D], C.c_int),
@@ -152,7 +159,8 @@ class Context:
     def __init__(self, device=0, stream=None, precision=OFM_FP64):
         if isinstance(precision, str):
             precision = {"fp64": OFM_FP64, "mixed": OFM_MIXED_BF16X3,
-                         "bf16x3": OFM_MIXED_BF16X3}[precision]
+                         "bf16x3": OFM_MIXED_BF16X3,
+                         "fp16x3": OFM_MIXED_FP16X3}[precision]
         self.precision = precision
         h = _P()
         st = lib().ofm_create(C.byref(h), int(device),
@@ -363,6 +371,10 @@ def ofm_set_stencil_variant(frags: Fragments, variant: int):
            frags.ctx.handle)
 
 
+def ofm_set_pair_variant(ctx: Context, variant: int):
+    _check(lib().ofm_set_pair_variant(ctx.handle, int(variant)), ctx.handle)
+
+
 def ofm_apply_fragment_h(ctx: Context, frags: Fragments, j, x):
     x = np.ascontiguousarray(x, np.float64)
     x2 = x.reshape(-1, x.shape[-1]) if x.ndim > 1 else x.reshape(1, -1)
@@ -473,6 +485,35 @@ def ofm_solve_global_subset(ctx: Context, m: Mats, keep, s_thresh=1e-6,
     if want_vectors:
         out["C"] = Cm[:nsel * ne.value].reshape(ne.value, nsel).T.copy()
     return out
+
+
+def ofm_select_band(frags: Fragments, e_lo, e_hi):
+    """Keep mask of the basis functions with fragment eigenvalue in
+    [e_lo, e_hi]."""
+    keep = np.zeros(frags.n_basis, np.uint8)
+    _check(lib().ofm_select_band(frags.handle, float(e_lo), float(e_hi),
+                                 keep.ctypes.data_as(_UB)), frags.ctx.handle)
+    return keep.astype(bool)
+
+
+def ofm_solve_global_window(ctx: Context, m: Mats, e_lo, e_hi, s_thresh=1e-6,
+                            margin0=0.1, margin_step=0.1, max_rounds=6,
+                            tol=1e-8, raise_on_noconv=False):
+    """Window eigenvalues on energy-band subsets of the basis with a growing
+    margin.  Returns dict(E, status, margin, n_sel, n_kept)."""
+    nb = m.frags.n_basis
+    E = np.zeros(nb)
+    ne, nk = C.c_int(), C.c_int()
+    mg = C.c_double()
+    ns = C.c_longlong()
+    st = lib().ofm_solve_global_window(
+        ctx.handle, m.handle, float(s_thresh), float(e_lo), float(e_hi),
+        float(margin0), float(margin_step), int(max_rounds), float(tol),
+        C.byref(ne), _dp(E), C.byref(mg), C.byref(ns), C.byref(nk))
+    if st != OFM_E_NOCONV or raise_on_noconv:
+        _check(st, ctx.handle)
+    return {"E": E[:ne.value].copy(), "status": st, "margin": mg.value,
+            "n_sel": ns.value, "n_kept": nk.value}
 
 
 def ofm_homo_energies(m: Mats):

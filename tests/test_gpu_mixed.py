@@ -1,5 +1,6 @@
-"""GPU parity of the mixed form (FP32 vectors and stencil, split-BF16 x3
-MFMA contractions, FP64 Cholesky / small eigensolves / global solve) against
+"""GPU parity of the mixed forms (FP32 vectors and stencil, split-BF16 x3 or
+scaled split-FP16 x3 MFMA contractions, FP64 Cholesky / small eigensolves /
+global solve; every test runs in both forms) against
 the FP64 oracle: eigenvalues within 1e-5 Ha, matrix elements within 1e-6
 relative to max|H|; diagonal S blocks exactly the identity for the solver's
 states, computed from the states for imported ones."""
@@ -25,9 +26,9 @@ def _build(ctx, s, V=None):
         s.frag_dims, s.frag_states, origin=s.grid.origin)
 
 
-@pytest.fixture(scope="module")
-def mctx():
-    c = P.ofm_create(0, None, P.OFM_MIXED_BF16X3)
+@pytest.fixture(scope="module", params=["bf16x3", "fp16x3"])
+def mctx(request):
+    c = P.ofm_create(0, None, request.param)
     yield c
     c.close()
 
@@ -129,6 +130,7 @@ def test_mixed_diag_s_of_non_orthonormal_imports(mctx, tiny0):
         dlo, dd, h_ = O.apply_whole_H(V, 0.5, s.frag_lo[j], s.frag_dims[j],
                                       phi[j])
         hp[j] = (h_, (dlo, dd))
+    hmax = np.abs(H).max()   # the bound is relative to max|H_ij|
     for p in range(len(pj)):
         j, n = int(pj[p]), int(pn[p])
         Sb, Hb, _ = O.pair_blocks(j, n, s.frag_lo, s.frag_dims, phi,
@@ -147,7 +149,8 @@ def test_mixed_diag_s_of_non_orthonormal_imports(mctx, tiny0):
         else:
             es = np.abs(gS - Sb).max() / max(np.abs(Sb).max(), 1e-300)
             assert es < 1e-6
-        eh = np.abs(gH - Hb).max() / np.abs(Hb).max()
+        eh = np.abs(gH - Hb).max() / hmax
+        _say(f"  block ({j},{n}): H {eh:.2e} of max|H|")
         assert eh < 1e-6
     st, eps, it, cv = P.ofm_solve_fragments(mctx, f)
     assert st == 0
@@ -200,6 +203,39 @@ def _wells_system(seed):
     return box_system(shape, h, lo, dims, [6, 4, 5, 2], V=V)
 
 
+def test_multistep_plane_classes_bit_identical(mctx):
+    """FP32 boxes in all four plane classes of the multi-step kernel (1 to 4
+    points per thread of a 512-thread workgroup: planes of 480, 900, 1280
+    and 1920 points), on-chip filter off: two steps per launch, one launch
+    per class, give the same bits as one step per launch, graph on and off,
+    and the eigenvalues match the oracle's."""
+    rng = np.random.default_rng(12)
+    shape = (52, 44, 8)
+    V = -np.abs(rng.standard_normal(shape[::-1])) * 0.3
+    lo = [(0, 0, 0), (10, 8, 1), (4, 6, 2), (2, 2, 3)]
+    dims = [(24, 20, 5), (30, 30, 5), (40, 32, 4), (48, 40, 3)]
+    st = [3, 4, 3, 4]
+    s = box_system(shape, 0.5, lo, dims, st, V=V)
+    out = []
+    for fused, graph in ((0, 0), (-1, 0), (0, -1)):
+        _say("plane classes: fused", fused, "graph", graph)
+        f = _build(mctx, s)
+        status, eps, it, cv = P.ofm_solve_fragments(
+            mctx, f, fused=fused, use_graph=graph, resident=-1)
+        assert status == 0 and cv.all()
+        out.append((eps, it, [P.ofm_get_states(f, j)[1] for j in range(4)]))
+        f.close()
+    for eps, it, phis in out[1:]:
+        assert np.array_equal(eps, out[0][0])
+        assert np.array_equal(it, out[0][1])
+        for a, b in zip(phis, out[0][2]):
+            assert np.array_equal(a, b)
+    r = O.run(V, 0.5, lo, dims, st, solve=False)
+    err = np.abs(out[0][0] - np.concatenate(r.eps)).max()
+    _say(f"  eps vs oracle {err:.2e} Ha")
+    assert err < 1e-5
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_resident_filter_bit_identical(mctx, seed):
     """The on-chip whole-filter kernel and the multi-step kernel (two or
@@ -248,3 +284,32 @@ def test_mixed_homo_basis_subset(mctx, tiny0, tiny0_oracle):
     assert err < 1e-5
     m.close()
     f.close()
+
+def test_pair_variants_bit_identical(mctx):
+    """Both variants of the pair-contraction kernels (a chunk loaded, then
+    multiplied; or the next chunk's loads in flight during the products) give
+    the same blocks bit for bit, on uneven boxes with halo-only pairs and
+    blocks up to 40 states wide (both work splits of the kernels)."""
+    rng = np.random.default_rng(31)
+    shape = (30, 22, 18)
+    V = -np.abs(rng.standard_normal(shape[::-1]))
+    dims = rng.integers(5, 12, size=(7, 3))
+    lo = np.array([[rng.integers(0, shape[a] - dims[f_, a] + 1)
+                    for a in range(3)] for f_ in range(7)])
+    for st in (rng.integers(1, 9, size=7), rng.integers(14, 41, size=7)):
+        s = box_system(shape, 0.5, lo, dims, st, V=V)
+        f = _build(mctx, s)
+        r = O.run(V, 0.5, lo, dims, st, solve=False)
+        for j in range(7):
+            P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+        out = []
+        for v in (0, 1):
+            P.ofm_set_pair_variant(mctx, v)
+            m = P.ofm_matrix_elements(mctx, f)
+            out.append(P.ofm_mats_copy(m))
+            m.close()
+        P.ofm_set_pair_variant(mctx, -1)
+        _say("pair variants, max states", int(st.max()))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert np.array_equal(out[0][1], out[1][1])
+        f.close()

@@ -744,3 +744,74 @@ def test_new_contexts_while_another_thread_captures(tiny0):
     assert len(out) == 4
     for E in out:
         assert np.array_equal(E, ref)
+
+def test_pair_variants_bit_identical(ctx):
+    """Both variants of the pair-contraction kernels (a chunk loaded, then
+    multiplied; or the next chunk's loads in flight during the products) give
+    the same blocks bit for bit, on uneven boxes with halo-only pairs and
+    blocks up to 40 states wide (both work splits of the kernels)."""
+    rng = np.random.default_rng(31)
+    shape = (30, 22, 18)
+    V = -np.abs(rng.standard_normal(shape[::-1]))
+    dims = rng.integers(5, 12, size=(7, 3))
+    lo = np.array([[rng.integers(0, shape[a] - dims[f_, a] + 1)
+                    for a in range(3)] for f_ in range(7)])
+    for st in (rng.integers(1, 9, size=7), rng.integers(14, 41, size=7)):
+        s = box_system(shape, 0.5, lo, dims, st, V=V)
+        f = _build(ctx, s)
+        r = O.run(V, 0.5, lo, dims, st, solve=False)
+        for j in range(7):
+            P.ofm_set_states(f, j, r.phi[j].T, r.eps[j])
+        out = []
+        for v in (0, 1):
+            P.ofm_set_pair_variant(ctx, v)
+            m = P.ofm_matrix_elements(ctx, f)
+            out.append(P.ofm_mats_copy(m))
+            m.close()
+        P.ofm_set_pair_variant(ctx, -1)
+        _say("pair variants, max states", int(st.max()))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert np.array_equal(out[0][1], out[1][1])
+        f.close()
+
+
+def test_band_selection_and_windowed_solve(ctx, tiny0, tiny0_oracle):
+    """The band mask equals the oracle's on the solver's fragment
+    eigenvalues; the windowed solve equals the oracle's windowed solve of
+    the same (GPU) blocks, round by round the same margin, and a band that
+    covers the basis reproduces the full solve."""
+    _say("band selection and windowed solve")
+    s = tiny0
+    f = _build(ctx, s)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0
+    boff = np.concatenate([[0], np.cumsum(s.frag_states)])
+    eps_list = [eps[boff[j]:boff[j + 1]] for j in range(s.n_frag)]
+    for lo, hi in ((-0.3, 0.4), (0.1, 0.6), (5.0, 6.0)):
+        assert np.array_equal(P.ofm_select_band(f, lo, hi),
+                              O.select_band(eps_list, lo, hi))
+    m = P.ofm_matrix_elements(ctx, f)
+    Hb, Sb = P.ofm_mats_copy(m)
+    H, S = P.unpack_blocks(f, Hb, Sb)
+    lo, hi = -0.3, 0.25
+    ref = O.window_by_band(H, S, eps_list, lo, hi, margin0=0.05,
+                           margin_step=0.1, max_rounds=8, tol=1e-9)
+    got = P.ofm_solve_global_window(ctx, m, lo, hi, margin0=0.05,
+                                    margin_step=0.1, max_rounds=8, tol=1e-9)
+    _say(f"  windowed: {len(got['E'])} eigenvalues, margin {got['margin']}, "
+         f"{got['n_sel']} functions; oracle margin {ref[2]}, {ref[3]}")
+    assert got["status"] == (0 if ref[1] else P.OFM_E_NOCONV)
+    assert abs(got["margin"] - ref[2]) < 1e-12 and got["n_sel"] == ref[3]
+    assert len(got["E"]) == len(ref[0])
+    assert np.abs(got["E"] - ref[0]).max() < 1e-8
+    full = P.ofm_solve_global(ctx, m, 1e-6, lo, hi)["E"]
+    wide = P.ofm_solve_global_window(ctx, m, lo, hi, margin0=10.0,
+                                     margin_step=1.0, max_rounds=2)
+    assert wide["status"] == 0 and wide["n_sel"] == s.n_basis
+    assert np.abs(wide["E"] - full).max() < 1e-12
+    with pytest.raises(P.OfmError):
+        P.ofm_solve_global_window(ctx, m, hi, lo)
+    with pytest.raises(P.OfmError):
+        P.ofm_solve_global_window(ctx, m, lo, hi, margin_step=0.0)
+    m.close()
+    f.close()

@@ -410,3 +410,54 @@ def test_homo_energies_and_subset_pencil_brute_force(tiny0, tiny0_oracle):
     assert g["n_kept"] == int(keep.sum())
     ref = sla.eigh(Hs, Ss, eigvals_only=True)
     assert np.abs(g["E"] - ref).max() < 1e-10
+
+
+# ------------------------------------- windowed solve of a large basis (f1)
+
+def test_select_band_worked_example():
+    """Hand-worked band masks: inclusive bounds, fragment by fragment."""
+    eps = [np.array([-1.0, -0.5, 0.2]), np.array([-0.7, 0.0])]
+    assert O.select_band(eps, -0.7, 0.0).tolist() == \
+        [False, True, False, True, True]
+    assert O.select_band(eps, -0.69, -0.01).tolist() == \
+        [False, True, False, False, False]
+    assert not O.select_band(eps, 1.0, 2.0).any()
+
+
+def test_window_by_band_exact_when_band_covers_basis(tiny0, tiny0_oracle):
+    """A margin that takes every fragment state gives the whole pencil, so
+    the windowed solve equals the full thresholded solve exactly."""
+    r = tiny0_oracle
+    e_all = np.concatenate(r.eps)
+    lo, hi = -0.2, 0.3
+    full = O.global_solve(r.H, r.S, 1e-6, lo, hi)["window"]
+    d = float(e_all.max() - e_all.min()) + 1.0
+    E, conv, mg, nsel = O.window_by_band(r.H, r.S, r.eps, lo, hi,
+                                        margin0=d, margin_step=0.5,
+                                        max_rounds=2)
+    assert conv and nsel == len(e_all)
+    assert np.array_equal(E, full)
+
+
+def test_window_by_band_upper_bounds_at_bottom(tiny0, tiny0_oracle):
+    """At the bottom of the spectrum the band pencil is a principal
+    sub-pencil with S positive definite (nothing dropped), so by Cauchy
+    interlacing its k-th eigenvalue is at least the whole pencil's k-th, and
+    the bound tightens as the margin grows; the largest margin reproduces
+    the whole pencil."""
+    r = tiny0_oracle
+    full = O.global_solve(r.H, r.S, 1e-6)
+    assert full["n_kept"] == r.S.shape[0]
+    E_all = full["E"]
+    lo, hi = E_all[0] - 1e-9, E_all[0] + 0.05
+    prev_err = np.inf
+    for d in (0.0, 0.2, 0.5, 1.0, 3.0):
+        keep = O.select_band(r.eps, -np.inf, hi + d)
+        Hs, Ss = O.subset(r.H, r.S, keep)
+        g = O.global_solve(Hs, Ss, 1e-6)
+        k = min(3, len(g["E"]))
+        assert np.all(g["E"][:k] >= E_all[:k] - 1e-12)
+        err = float(np.abs(g["E"][:k] - E_all[:k]).max())
+        assert err <= prev_err + 1e-12
+        prev_err = err
+    assert prev_err < 1e-12

@@ -2,8 +2,8 @@
 through the C ABI: the same blocks bit for bit (same kernels, same task
 list), on two calls in a row with the second on a smaller system (fewer
 tasks than the list the scratch array still holds from the first call), into
-buffers pre-filled with NaN (every element must be written); FP64 and mixed
-forms, imported states included; rejected arguments leave the context
+buffers pre-filled with NaN (every element must be written); FP64 and both
+mixed forms, imported states included; rejected arguments leave the context
 usable."""
 import ctypes as C
 
@@ -37,11 +37,10 @@ def _systems():
     return big, small
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp16x3"])
 def test_noalloc_matches_allocating_entry_point(prec):
     _say("no-alloc elements", prec)
-    ctx = P.ofm_create(0, None, P.OFM_FP64 if prec == "fp64"
-                       else P.OFM_MIXED_BF16X3)
+    ctx = P.ofm_create(0, None, prec)
     big, small = _systems()
     ntasks = []
     for k, s in enumerate((big, small)):
