@@ -37,9 +37,10 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6         # MI355X FP64 matrix, TFLOP/s
 BF16_PEAK_TFS = 2500.0       # MI355X dense BF16 MFMA, TFLOP/s
 FP16_PEAK_TFS = 2500.0       # MI355X dense FP16 MFMA, TFLOP/s
-# LDS read bandwidth per CU and clock, measured on the box with a
-# ds_read_b128 loop (profiles/lds_peak_probe.md); 256 CUs at 2.4 GHz
-LDS_BYTES_PER_CLK_CU = 128.0
+# LDS read bandwidth of a CDNA4 CU: 256 bytes per clock (a loop of
+# conflict-free ds_read_b128 reads, eight in flight per wave, sustains 248);
+# 256 CUs at 2.4 GHz
+LDS_BYTES_PER_CLK_CU = 256.0
 LDS_PEAK_GBS = LDS_BYTES_PER_CLK_CU * 256 * 2.4
 LDS_BYTES_PER_POINT_STEP = 11 * 4   # on-chip filter, FP32
 STENCIL_KERNELS = {
@@ -71,7 +72,7 @@ def parse():
     ap.add_argument("--no-global", action="store_true",
                     help="skip the once-per-form global solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=48,
+    ap.add_argument("--cpu-sample", type=int, default=160,
                     help="fragments in the oracle's timed sample (worker pool)")
     ap.add_argument("--cpu-sample-1core", type=int, default=3,
                     help="fragments timed on one core")

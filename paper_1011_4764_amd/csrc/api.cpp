@@ -331,15 +331,15 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       if (act[j] && fsh[j].lock < f->host[j].bw) {
         const FragDev& d = f->host[j];
         const double u = (double)d.npts * (d.bw - fsh[j].lock);
-        const int ppt = k::multistep_ppt((int)w, d);
+        const int cls = k::multistep_class((int)w, d);
         if (res && k::resident_eligible((int)w, d)) {
           rnb += u;
           rnpt += d.npts;
-        } else if (have_ms && !tuning && ppt > 0) {
+        } else if (have_ms && !tuning && cls > 0) {
           mnb += u;
           mnpt += d.npts;
-          cnb[ppt - 1] += u;
-          cnpt[ppt - 1] += d.npts;
+          cnb[cls - 1] += u;
+          cnpt[cls - 1] += d.npts;
         } else {
           snb += u;
           snpt += d.npts;
@@ -762,9 +762,9 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
         for (int j = 0; j < n_frag; ++j) {
           const FragDev& d = f->host[j];
           if (set == 1 && k::resident_eligible((int)w, d)) continue;
-          const int ppt = k::multistep_ppt((int)w, d);
-          if (ppt == 0) continue;
-          for (int v = 0; v < d.bw; ++v) vt[ppt - 1].push_back(make_int2(j, v));
+          const int cls = k::multistep_class((int)w, d);
+          if (cls == 0) continue;
+          for (int v = 0; v < d.bw; ++v) vt[cls - 1].push_back(make_int2(j, v));
         }
         f->n_vt_all[set] = 0;
         for (int cl = 0; cl < 4; ++cl) {

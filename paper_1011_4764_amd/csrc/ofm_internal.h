@@ -156,9 +156,10 @@ struct ofm_frags {
   int n_tiles_nr[3] = {0, 0, 0};
   // multi-step kernel: (fragment, vector) tiles of the boxes it takes, with
   // the on-chip filter off [0] or on [1] (then it takes none of those), per
-  // class of points per thread (1..4: one launch per class, so a small plane
-  // does not run on a workgroup sized for the largest), and the strip tiles
-  // of the remaining boxes per stencil variant
+  // launch class (points per thread and workgroup size, multistep_class: one
+  // launch per class, so a small plane does not run on a workgroup sized
+  // for the largest), and the strip tiles of the remaining boxes per stencil
+  // variant
   int2* d_vt[2][4] = {{nullptr, nullptr, nullptr, nullptr},
                       {nullptr, nullptr, nullptr, nullptr}};
   int n_vt[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
@@ -331,12 +332,12 @@ std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
                                 const std::vector<char>* keep = nullptr);
 // two or three Chebyshev steps per launch for boxes whose plane fits one
 // workgroup
-// points per thread the multi-step kernel uses for a box (0: not taken)
-int multistep_ppt(int elem_bytes, const FragDev& d);
+// launch class (1..4) of the multi-step kernel for a box (0: not taken)
+int multistep_class(int elem_bytes, const FragDev& d);
 bool multistep_eligible(int elem_bytes, const FragDev& d);
 template <typename T>
 void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
-              int ntiles, int ppt, int ns, const int* active, int step,
+              int ntiles, int cls, int ns, const int* active, int step,
               const FilterState* fs, double alg_bytes, double flops);
 // whole Chebyshev filter with the vector on chip (FP32, boxes <= 32^3)
 bool resident_eligible(int elem_bytes, const FragDev& d);

@@ -245,15 +245,21 @@ __global__ __launch_bounds__(WG) void k_apply_h(
 #define OFM_H2_THREADS 512
 #endif
 constexpr int H2T = OFM_H2_THREADS;   // threads of a multi-step workgroup
+// Planes of 1025..2048 points run with 2 points per thread on 2 * H2T
+// threads in FP64 and with 3..4 points per thread on H2T threads in FP32:
+// on the amorphous workload (boxes of 24..40 points per axis) the FP64
+// fragment stage measured 1386 against 1440 ms with the wide workgroups and
+// the FP32 one 519 against 585 ms with the narrow ones.
+constexpr bool wide_wg(int elem_bytes) { return elem_bytes == 8; }
 
-template <typename T, int PPT, int NS>
-__global__ __launch_bounds__(H2T) void k_apply_hm(
+template <typename T, int PPT, int NS, int NT>
+__global__ __launch_bounds__(NT) void k_apply_hm(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
     int nblk_pad, const T* __restrict__ Vj, T* IN, T* PV,
     const FilterState* __restrict__ fs, const int* __restrict__ active,
     int step, double nh) {
   static_assert(NS >= 2 && NS <= 3, "two or three steps per launch");
-  constexpr int SP = PPT * H2T;
+  constexpr int SP = PPT * NT;
   constexpr int NV = 2 * (NS - 1) + 1;   // V planes t - 2(NS-1) .. t
   const int t0 = xcd_tile(blockIdx.x, nblk_pad);
   if (t0 >= ntiles) return;
@@ -285,7 +291,7 @@ __global__ __launch_bounds__(H2T) void k_apply_hm(
   T q[PPT];          // y_{k-2} at plane t
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int p = tid + k * H2T;
+    const int p = tid + k * NT;
     ok[k] = p < plane;
     pp[k] = ok[k] ? p : 0;
     px[k] = pp[k] % nx;
@@ -383,17 +389,22 @@ bool multistep_eligible(int elem_bytes, const FragDev& d) {
   return d.dims[0] * d.dims[1] <= 4 * H2T;
 }
 
-// points per thread of the multi-step kernel for one box's plane, the
-// fewest that cover it (0 if the box is not taken); boxes of one class run
-// in one launch
-int multistep_ppt(int elem_bytes, const FragDev& d) {
+// launch class of the multi-step kernel for a box (0: not taken); the
+// classes are (points per thread, threads): 1: (1, H2T), 2: (2, H2T), and
+// for planes above 2 H2T points 3: (2, 2 H2T) with wide workgroups, else
+// 3: (3, H2T) and 4: (4, H2T)
+int multistep_class(int elem_bytes, const FragDev& d) {
   if (!multistep_eligible(elem_bytes, d)) return 0;
-  return (d.dims[0] * d.dims[1] + H2T - 1) / H2T;
+  const int plane = d.dims[0] * d.dims[1];
+  if (wide_wg(elem_bytes)) return plane <= H2T ? 1 : plane <= 2 * H2T ? 2 : 3;
+  return (plane + H2T - 1) / H2T;
 }
+
+
 
 template <typename T>
 void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
-              int ntiles, int ppt, int ns, const int* active, int step,
+              int ntiles, int cls, int ns, const int* active, int step,
               const FilterState* fs, double alg_bytes, double flops) {
   const T* Vj;
   if constexpr (sizeof(T) == 8)
@@ -404,20 +415,22 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
   const int nblk = pad8(ntiles);
   Timed tm(c, "multistep", alg_bytes, flops);
   hipStream_t stream = f->ctx->stream;
-#define LAUNCHM(PP, NSS)                                                     \
-  hipLaunchKernelGGL((k_apply_hm<T, PP, NSS>), dim3(nblk), dim3(H2T), 0,     \
+#define LAUNCHM(PP, NSS, NTT)                                                \
+  hipLaunchKernelGGL((k_apply_hm<T, PP, NSS, NTT>), dim3(nblk), dim3(NTT), 0, \
                      stream, f->d_frag, tiles, ntiles, nblk, Vj, IN, PV, fs, \
                      active, step, nh)
-#define LAUNCHP(PP)                                                          \
+#define LAUNCHP(PP, NTT)                                                     \
   do {                                                                       \
-    if (ns == 3) LAUNCHM(PP, 3);                                             \
-    else LAUNCHM(PP, 2);                                                     \
+    if (ns == 3) LAUNCHM(PP, 3, NTT);                                        \
+    else LAUNCHM(PP, 2, NTT);                                                \
   } while (0)
-  // the boxes it takes need at most 4 points per thread
-  if (ppt == 1) LAUNCHP(1);
-  else if (ppt == 2) LAUNCHP(2);
-  else if (ppt == 3) LAUNCHP(3);
-  else if (ppt == 4) LAUNCHP(4);
+  // the classes of multistep_class
+  if (cls == 1) LAUNCHP(1, H2T);
+  else if (cls == 2) LAUNCHP(2, H2T);
+  else if (wide_wg(sizeof(T)) && cls == 3) LAUNCHP(2, 2 * H2T);
+  else if (!wide_wg(sizeof(T)) && cls == 3) LAUNCHP(3, H2T);
+  else if (!wide_wg(sizeof(T)) && cls == 4) LAUNCHP(4, H2T);
+  else OFM_REQUIRE(false, OFM_E_INVALID, "unknown multi-step launch class");
 #undef LAUNCHP
 #undef LAUNCHM
   OFM_HIP(hipGetLastError());

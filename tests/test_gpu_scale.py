@@ -296,6 +296,31 @@ def test_amorphous_fp64_full_size(amorphous_fp64):
     assert checked == expect >= 5
 
 
+@pytest.mark.timeout(600)
+def test_amorphous_windowed_solve(amorphous_fp64):
+    """The windowed solve on energy bands of the basis reproduces the full
+    dense solve's window [E_1, E_1 + 0.3 Ha] of the amorphous system: it
+    stops once two successive bands agree within 1e-7 Ha, and that result
+    is within 1e-6 Ha of the full solve (the band omits functions whose
+    effect on the window is second order in their coupling)."""
+    d = amorphous_fp64
+    f, ctx = d["f"], d["ctx"]
+    m = P.ofm_matrix_elements(ctx, f)
+    lo, hi = d["window"]
+    w = P.ofm_solve_global_window(ctx, m, lo, hi, margin0=0.3,
+                                  margin_step=0.2, max_rounds=4, tol=1e-7)
+    m.close()
+    ref = d["Ew"]
+    err = float(np.abs(w["E"] - ref).max()) if len(w["E"]) == len(ref) \
+        else float("nan")
+    _say(f"  windowed: status {w['status']}, margin {w['margin']:.2f}, "
+         f"{w['n_sel']} of {d['s'].n_basis} functions, kept {w['n_kept']}, "
+         f"{len(w['E'])} eigenvalues, max |E - full| {err:.2e} Ha")
+    assert w["status"] == 0
+    assert len(w["E"]) == len(ref)
+    assert err < 1e-6
+
+
 def _kept_count_bound(ctx64, S64_sparse, dS_sparse, tau):
     """Weyl's inequality: every eigenvalue of S moves by at most ||dS||_2
     under S -> S + dS, so the kept count |{s >= tau}| can change by at most
@@ -428,6 +453,52 @@ def _subset_dense(f, H, S, keep):
         Hd[np.ix_(rn, rj)] = hb.T
         Sd[np.ix_(rn, rj)] = sb.T
     return Hd, Sd
+
+
+@pytest.mark.timeout(900)
+def test_thiophene_windowed_full_basis():
+    """The polythiophene-like system on its whole 98,304-function basis
+    (mixed fragment stage): the 0.2 Ha window below the top fragment HOMO
+    energy, by the windowed solve on energy bands of the basis (the dense
+    pencil of the whole basis would take 77 GB per matrix).  The margin
+    grows in steps of 0.025 Ha while the band stays within 40k functions;
+    the result (converged to the mixed form's 1e-5 Ha between two bands, or
+    the last band's, reported) is non-empty, ascending and inside the
+    window."""
+    s = thiophene_polymer(0)
+    V = s.potential()
+    g = s.grid
+    ctx = P.ofm_create(0, None, P.OFM_MIXED_BF16X3)
+    f = P.ofm_build_fragments(ctx, (g.nx, g.ny, g.nz), g.h, V, s.frag_lo,
+                              s.frag_dims, s.frag_states, origin=g.origin)
+    st, eps, it, cv = P.ofm_solve_fragments(ctx, f)
+    assert st == 0 and cv.all()
+    m = P.ofm_matrix_elements(ctx, f)
+    e = P.ofm_homo_energies(m)
+    lo, hi = float(e.max()) - 0.2, float(e.max())
+    # margins in steps of 0.025 Ha while the band stays within 40k functions
+    # (a dense pencil of 40k is ~13 GB per matrix)
+    step = 0.025
+    counts = [int(P.ofm_select_band(f, lo - step * r, hi + step * r).sum())
+              for r in range(13)]
+    _say("  band sizes per 0.025 Ha of margin:", counts)
+    rounds = max(2, sum(1 for c in counts if c <= 40000))
+    t0 = time.perf_counter()
+    w = P.ofm_solve_global_window(ctx, m, lo, hi, margin0=0.0,
+                                  margin_step=step, max_rounds=rounds,
+                                  tol=1e-5)
+    t1 = time.perf_counter()
+    E = w["E"]
+    _say(f"  window [{lo:.4f}, {hi:.4f}] Ha on {s.n_basis} functions: status "
+         f"{w['status']}, margin {w['margin']:.2f}, {w['n_sel']} functions in "
+         f"the last band, kept {w['n_kept']}, {len(E)} eigenvalues, "
+         f"{t1 - t0:.1f} s")
+    assert w["status"] in (0, P.OFM_E_NOCONV)
+    assert len(E) > 0 and np.all(np.diff(E) >= 0)
+    assert E[0] >= lo and E[-1] <= hi
+    m.close()
+    f.close()
+    ctx.close()
 
 
 @pytest.mark.timeout(900)
