@@ -176,9 +176,12 @@ void free_frags(ofm_frags* f) {
                   f->d_tiles_rest[0][2], f->d_tiles_rest[1][0],
                   f->d_tiles_rest[1][1], f->d_tiles_rest[1][2],
                   f->d_stiles, f->d_rtiles, f->d_G,
+                  f->d_gfl[0], f->d_gfl[1], f->d_gfl[2], f->d_gfl[3],
+                  f->d_rtl[0], f->d_rtl[1], f->d_rtl[2], f->d_rtl[3],
+                  f->d_rtl[4],
                   f->d_Q, f->d_theta, f->d_res, f->d_res_partial, f->d_fs,
                   f->d_active, f->d_iters, f->d_conv, f->d_flags,
-                  f->d_nactive};
+                  f->d_nactive, f->d_coef};
   for (void* p : ptrs) dev_free(p);
 }
 
@@ -222,6 +225,16 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   OFM_HIP(hipGetLastError());
   k::init_random<T>(s, f, X, cfg.seed);
 
+  // Chebyshev step coefficients, refreshed from the filter intervals at the
+  // start of every outer iteration (the captured sweep reads this buffer)
+  const size_t coef_need = (size_t)nf * cfg.degree * k::step_coef_bytes(sizeof(T));
+  if (f->coef_bytes < coef_need) {
+    dev_free(f->d_coef);
+    f->d_coef = nullptr;
+    f->coef_bytes = 0;
+    f->d_coef = dev_alloc<char>(coef_need);
+    f->coef_bytes = coef_need;
+  }
   std::vector<int> act(nf, 1);
   std::vector<FilterState> fsh(nf);
   hipGraphExec_t sweep_exec = nullptr;
@@ -279,8 +292,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
     double nb, npt, nb2;
     sums(nb, npt, nb2);
     k::apply_h<T>(c, f, X, X, HX, f->d_tiles[var], f->n_tiles[var], var,
-                  f->d_active, 0, f->d_fs, 0, -1, (2 * nb + npt) * w,
-                  28.0 * nb);
+                  f->d_active, 0, f->d_fs, nullptr, 0, 0, -1,
+                  (2 * nb + npt) * w, 28.0 * nb);
   };
   int n_active = nf;
   auto rayleigh_ritz = [&]() {
@@ -324,6 +337,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   const int* tune_n = res ? f->n_tiles_nr : f->n_tiles;
   if (tune_n[var] == 0) tuning = false;   // nothing left to tune
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
+    k::step_coefs_table<T>(s, f, cfg.degree, f->d_coef);
     // filter work: unlocked vectors of the active fragments, per class
     double snb = 0, snpt = 0, mnb = 0, mnpt = 0, rnb = 0, rnpt = 0;
     double cnb[4] = {0, 0, 0, 0}, cnpt[4] = {0, 0, 0, 0};
@@ -350,8 +364,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       // (its 24 vector workgroups share it through L2), once per filter
       if constexpr (sizeof(T) == 4)
         k::filter_resident(c, f, X, f->d_ftiles, f->n_ftiles, f->d_active,
-                           f->d_fs, cfg.degree, (2 * rnb + rnpt) * w,
-                           32.0 * rnb * cfg.degree);
+                           f->d_fs, f->d_coef, cfg.degree,
+                           (2 * rnb + rnpt) * w, 32.0 * rnb * cfg.degree);
     }
     const bool use_ms = have_ms && !tuning;
     int ms_classes = 0;
@@ -375,8 +389,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                   (step == 1 ? 3 * cnb[cl] : 4 * cnb[cl]) * w + cnpt[cl] * w;
               k::apply_hm<T>(timed_each ? c : nullptr, f, in, pv,
                              f->d_vt[vset][cl], f->n_vt[vset][cl], cl + 1, ns,
-                             f->d_active, step, f->d_fs, by,
-                             32.0 * cnb[cl] * ns);
+                             f->d_active, step, f->d_fs, f->d_coef,
+                             cfg.degree, by, 32.0 * cnb[cl] * ns);
             }
             if (ns % 2) std::swap(in, pv);
             step += ns;
@@ -397,8 +411,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
           e1 = tev[step - 2][1];
         }
         k::apply_h<T>(timed_each ? c : nullptr, f, in, prev, out, st_tiles[sv],
-                      st_n[sv], sv, f->d_active, step, f->d_fs, 1, -1, by,
-                      32.0 * snb, e0, e1);
+                      st_n[sv], sv, f->d_active, step, f->d_fs, f->d_coef,
+                      cfg.degree, 1, -1, by, 32.0 * snb, e0, e1);
       }
     };
     if (!use_ms && st_n[var] == 0) {
@@ -784,6 +798,25 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
                                  hipMemcpyHostToDevice, s));
         OFM_HIP(hipStreamSynchronize(s));
       }
+      {
+        auto upload_int = [&](const std::vector<int>& v, int*& dst, int& n) {
+          n = (int)v.size();
+          dst = dev_alloc<int>(v.size());
+          if (!v.empty())
+            OFM_HIP(hipMemcpyAsync(dst, v.data(), sizeof(int) * v.size(),
+                                   hipMemcpyHostToDevice, s));
+          OFM_HIP(hipStreamSynchronize(s));
+        };
+        std::vector<int> gl[4], rl[5];
+        for (int j = 0; j < n_frag; ++j) {
+          const FragDev& d = f->host[j];
+          gl[(d.bw + 15) / 16 - 1].push_back(j);
+          for (int ch = 0; ch < d.rt_count; ++ch)
+            rl[k::rotate_class(d.bw)].push_back(d.rt_begin + ch);
+        }
+        for (int cl = 0; cl < 4; ++cl) upload_int(gl[cl], f->d_gfl[cl], f->n_gfl[cl]);
+        for (int cl = 0; cl < 5; ++cl) upload_int(rl[cl], f->d_rtl[cl], f->n_rtl[cl]);
+      }
       f->d_stiles = dev_alloc<int2>(stiles.size());
       f->d_rtiles = dev_alloc<int2>(rtiles.size());
       f->d_v = dev_alloc<double>(f->v_total);
@@ -1056,11 +1089,11 @@ ofm_status ofm_apply_fragment_h(ofm_ctx* c, ofm_frags* f, int j, int nvec,
       if (w == 8)
         k::apply_h<double>(c, f, (const double*)din, (const double*)din,
                            (double*)dout, dt, (int)t.size(), var, nullptr, 0,
-                           nullptr, 0, 0, 0, 0);
+                           nullptr, nullptr, 0, 0, 0, 0, 0);
       else
         k::apply_h<float>(c, f, (const float*)din, (const float*)din,
                           (float*)dout, dt, (int)t.size(), var, nullptr, 0,
-                          nullptr, 0, 0, 0, 0);
+                          nullptr, nullptr, 0, 0, 0, 0, 0);
       OFM_HIP(hipMemcpy2DAsync(buf.data(), d.npts * w, dout, (size_t)d.ld * w,
                                d.npts * w, nvec, hipMemcpyDeviceToHost, c->stream));
       OFM_HIP(hipStreamSynchronize(c->stream));

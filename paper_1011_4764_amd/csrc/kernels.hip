@@ -176,12 +176,13 @@ __device__ __forceinline__ void load4(const T* p, double* o) {
 // loaded once; the four waves' tiles are then summed in LDS in wave order.
 template <typename T, int NT, bool SYM>
 __global__ __launch_bounds__(WG) void k_gram(
-    const FragDev* __restrict__ F, int nf, const T* __restrict__ A,
-    const T* __restrict__ B, double* __restrict__ partial,
-    const int* __restrict__ active) {
+    const FragDev* __restrict__ F, const int* __restrict__ flist, int nf,
+    const T* __restrict__ A, const T* __restrict__ B,
+    double* __restrict__ partial, const int* __restrict__ active) {
   constexpr int NTILE = SYM ? NT * (NT + 1) / 2 : NT * NT;
-  const int j = blockIdx.x / GCH, ch = blockIdx.x % GCH;
-  if (j >= nf) return;
+  const int fi = blockIdx.x / GCH, ch = blockIdx.x % GCH;
+  if (fi >= nf) return;
+  const int j = flist[fi];   // a fragment of this launch's width class
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
   const int bw = fr.bw;
@@ -260,22 +261,27 @@ __global__ __launch_bounds__(WG) void k_gram(
 template <typename T>
 void gram(ofm_ctx* c, const ofm_frags* f, const T* A, const T* B, double* G,
           const int* active, double bytes, double flops) {
-  Timed tm(c, "gram", bytes, flops);
-  const int nt = (f->max_bw + 15) / 16;
+  int nl = 0;
+  for (int cl = 0; cl < 4; ++cl) nl += f->n_gfl[cl] > 0;
+  Timed tm(c, "gram", bytes, flops, nl);
   const bool sym = A == B;
+  // one launch per width class (16-state tiles per block side)
 #define GRAM(NT)                                                             \
   if (sym)                                                                   \
-    hipLaunchKernelGGL((k_gram<T, NT, true>), dim3(f->n_frag * GCH),         \
-                       dim3(WG), 0, c->stream, f->d_frag, f->n_frag, A, B,   \
-                       G, active);                                           \
+    hipLaunchKernelGGL((k_gram<T, NT, true>), dim3(n * GCH), dim3(WG), 0,    \
+                       c->stream, f->d_frag, fl, n, A, B, G, active);        \
   else                                                                       \
-    hipLaunchKernelGGL((k_gram<T, NT, false>), dim3(f->n_frag * GCH),        \
-                       dim3(WG), 0, c->stream, f->d_frag, f->n_frag, A, B,   \
-                       G, active)
-  if (nt <= 1) GRAM(1);
-  else if (nt == 2) GRAM(2);
-  else if (nt == 3) GRAM(3);
-  else GRAM(4);
+    hipLaunchKernelGGL((k_gram<T, NT, false>), dim3(n * GCH), dim3(WG), 0,   \
+                       c->stream, f->d_frag, fl, n, A, B, G, active)
+  for (int cl = 0; cl < 4; ++cl) {
+    const int n = f->n_gfl[cl];
+    const int* fl = f->d_gfl[cl];
+    if (n == 0) continue;
+    if (cl == 0) GRAM(1);
+    else if (cl == 1) GRAM(2);
+    else if (cl == 2) GRAM(3);
+    else GRAM(4);
+  }
 #undef GRAM
   OFM_HIP(hipGetLastError());
 }
@@ -752,13 +758,14 @@ __device__ __forceinline__ float wave_sum(float v) {
 // cached access on the alkane workload).
 template <typename T, int BMAX>
 __global__ __launch_bounds__(RCH) void k_rotate(
-    const FragDev* __restrict__ F, const int2* __restrict__ rt, int nrt,
-    T* __restrict__ X, T* __restrict__ HX, const double* __restrict__ Q,
+    const FragDev* __restrict__ F, const int2* __restrict__ rt,
+    const int* __restrict__ tlist, int nt, T* __restrict__ X,
+    T* __restrict__ HX, const double* __restrict__ Q,
     const double* __restrict__ theta, double* __restrict__ res_partial,
     const int* __restrict__ active, int upper) {
   static_assert(BMAX % 4 == 0, "BMAX must be a multiple of 4");
-  const int t = blockIdx.x;
-  if (t >= nrt) return;
+  if ((int)blockIdx.x >= nt) return;
+  const int t = tlist[blockIdx.x];   // a chunk of this launch's width class
   const int j = rt[t].x;
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
@@ -838,17 +845,23 @@ template <typename T>
 void rotate(ofm_ctx* c, const ofm_frags* f, T* X, T* HX, const double* Q,
             const double* theta, double* res_partial, const int* active,
             int upper, double bytes, double flops) {
-  Timed tm(c, "rotate", bytes, flops);
-  const int b = f->max_bw;
+  int nl = 0;
+  for (int cl = 0; cl < 5; ++cl) nl += f->n_rtl[cl] > 0;
+  Timed tm(c, "rotate", bytes, flops, nl);
+  // one launch per width class (rotate_class)
 #define ROT(BM)                                                              \
-  hipLaunchKernelGGL((k_rotate<T, BM>), dim3(f->n_rtiles), dim3(RCH), 0,     \
-                     c->stream, f->d_frag, f->d_rtiles, f->n_rtiles, X, HX,  \
-                     Q, theta, res_partial, active, upper)
-  if (b <= 16) ROT(16);
-  else if (b <= 24) ROT(24);
-  else if (b <= 32) ROT(32);
-  else if (b <= 48) ROT(48);
-  else ROT(64);
+  hipLaunchKernelGGL((k_rotate<T, BM>), dim3(n), dim3(RCH), 0, c->stream,    \
+                     f->d_frag, f->d_rtiles, f->d_rtl[cl], n, X, HX, Q,      \
+                     theta, res_partial, active, upper)
+  for (int cl = 0; cl < 5; ++cl) {
+    const int n = f->n_rtl[cl];
+    if (n == 0) continue;
+    if (cl == 0) ROT(16);
+    else if (cl == 1) ROT(24);
+    else if (cl == 2) ROT(32);
+    else if (cl == 3) ROT(48);
+    else ROT(64);
+  }
 #undef ROT
   OFM_HIP(hipGetLastError());
 }

@@ -164,6 +164,12 @@ struct ofm_frags {
                       {nullptr, nullptr, nullptr, nullptr}};
   int n_vt[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   int n_vt_all[2] = {0, 0};
+  // width classes of the Gram and rotation kernels: one launch per class,
+  // so a narrow block does not run with the registers of the widest one
+  int* d_gfl[4] = {nullptr, nullptr, nullptr, nullptr};   // fragments with
+  int n_gfl[4] = {0, 0, 0, 0};                            // ceil(bw/16) = 1..4
+  int* d_rtl[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int n_rtl[5] = {0, 0, 0, 0, 0};   // chunk indices, bw <= 16/24/32/48/64
   int2* d_tiles_rest[2][3] = {{nullptr, nullptr, nullptr},
                               {nullptr, nullptr, nullptr}};
   int n_tiles_rest[2][3] = {{0, 0, 0}, {0, 0, 0}};
@@ -185,6 +191,8 @@ struct ofm_frags {
   unsigned char* d_conv = nullptr;
   int* d_flags = nullptr;
   int* d_nactive = nullptr;
+  void* d_coef = nullptr;    // Chebyshev step coefficients (solve_impl)
+  size_t coef_bytes = 0;
   std::vector<double> eps_host;  // sum_j s_j, valid when have_states
   bool have_states = false;
   // per fragment: 1 when its states come from ofm_solve_fragments (FP64
@@ -338,19 +346,28 @@ bool multistep_eligible(int elem_bytes, const FragDev& d);
 template <typename T>
 void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
               int ntiles, int cls, int ns, const int* active, int step,
-              const FilterState* fs, double alg_bytes, double flops);
+              const FilterState* fs, const void* coef, int cdeg,
+              double alg_bytes, double flops);
+// Chebyshev step coefficients of every fragment for steps 1..degree from
+// the filter intervals in f->d_fs: `degree` records of 5 values of T per
+// fragment (step_coef_bytes each), read by the filter kernels (mode 1)
+template <typename T>
+void step_coefs_table(hipStream_t s, const ofm_frags* f, int degree,
+                      void* table);
+inline size_t step_coef_bytes(int elem_bytes) { return 5 * (size_t)elem_bytes; }
 // whole Chebyshev filter with the vector on chip (FP32, boxes <= 32^3)
 bool resident_eligible(int elem_bytes, const FragDev& d);
 void filter_resident(ofm_ctx* c, const ofm_frags* f, float* X,
                      const int2* tiles, int ntiles, const int* active,
-                     const FilterState* fs, int degree, double alg_bytes,
-                     double flops);
+                     const FilterState* fs, const void* coef, int degree,
+                     double alg_bytes, double flops);
 template <typename T>
 void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
              T* out, const int2* tiles, int ntiles, int variant,
-             const int* active, int step, const FilterState* fs, int mode,
-             long long base_override, double alg_bytes, double flops,
-             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+             const int* active, int step, const FilterState* fs,
+             const void* coef, int cdeg, int mode, long long base_override,
+             double alg_bytes, double flops, hipEvent_t ev0 = nullptr,
+             hipEvent_t ev1 = nullptr);
 template <typename T>
 void gram(ofm_ctx* c, const ofm_frags* f, const T* A, const T* B, double* G,
           const int* active, double bytes, double flops);
@@ -398,6 +415,11 @@ template <typename T>
 void convert_back(hipStream_t s, const T* in, double* out, long long n);
 constexpr int GCH = 16;   // split-K chunks per fragment of the Gram kernel
 constexpr int RCH = 256;  // points per rotation chunk
+// width class of the rotation kernel for a block of bw vectors (0..4:
+// registers sized for 16, 24, 32, 48, 64 vectors)
+inline int rotate_class(int bw) {
+  return bw <= 16 ? 0 : bw <= 24 ? 1 : bw <= 32 ? 2 : bw <= 48 ? 3 : 4;
+}
 constexpr int SMAX = 64;  // largest block width
 }  // namespace k
 

@@ -47,37 +47,73 @@ struct StepCoef {
   T a1, a2, alpha, gamma, beta;
 };
 
+// a value every lane of the wave holds alike, moved to scalar registers
+// (the coefficients of a step are the same for the whole workgroup; kept in
+// vector registers they would take 20 of them for two FP64 steps)
+__device__ __forceinline__ float wave_uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double wave_uniform(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 template <typename T>
-__device__ __forceinline__ StepCoef<T> step_coefs(const FilterState* fs,
-                                                  int step, int mode,
-                                                  double nh) {
+__device__ __forceinline__ StepCoef<T> wave_uniform(const StepCoef<T>& k) {
+  return {wave_uniform(k.a1), wave_uniform(k.a2), wave_uniform(k.alpha),
+          wave_uniform(k.gamma), wave_uniform(k.beta)};
+}
+
+// mode 0 (out = H_j y)
+template <typename T>
+__device__ __forceinline__ StepCoef<T> h_coefs(double nh) {
   StepCoef<T> k;
-  if (mode == 0) {
-    k.a1 = (T)(nh * W1); k.a2 = (T)(nh * W2);
-    k.alpha = 1; k.gamma = 0; k.beta = 0;
-    return k;
-  }
-  const FilterState& st = *fs;
+  k.a1 = (T)(nh * W1); k.a2 = (T)(nh * W2);
+  k.alpha = 1; k.gamma = 0; k.beta = 0;
+  return k;
+}
+
+// Chebyshev step coefficients of every fragment for steps 1..degree (mode
+// 1), one row of `degree` records per fragment, from the filter interval the
+// last Rayleigh-Ritz step left in fs.  The recurrence s_k = 1/(2/s1 -
+// s_{k-1}) runs once per fragment here instead of once per thread and step
+// in the filter kernels, which read their step's record with a scalar load.
+template <typename T>
+__global__ __launch_bounds__(64) void k_step_coefs(
+    const FilterState* __restrict__ fs, int nf, int degree, double nh,
+    StepCoef<T>* __restrict__ coef) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= nf) return;
+  const FilterState st = fs[j];
+  StepCoef<T>* out = coef + (long long)j * degree;
   const double e = 0.5 * (st.upper - st.lower);
-  if (!(e > 1e-12 * fabs(st.upper))) {
-    k.a1 = 0; k.a2 = 0; k.alpha = 0; k.gamma = 1; k.beta = 0;
-    return k;
+  if (!(e > 1e-12 * fabs(st.upper))) {   // degenerate interval: identity
+    for (int k = 0; k < degree; ++k) {
+      StepCoef<T> c;
+      c.a1 = 0; c.a2 = 0; c.alpha = 0; c.gamma = 1; c.beta = 0;
+      out[k] = c;
+    }
+    return;
   }
   const double c = 0.5 * (st.upper + st.lower);
   const double s1 = e / (st.scale - c);
-  double sp = s1, sc = s1;
   const double tau = 2.0 / s1;
-  for (int i = 2; i <= step; ++i) {
-    sp = sc;
-    sc = 1.0 / (tau - sp);
+  double sp = s1, sc = s1;
+  for (int step = 1; step <= degree; ++step) {
+    if (step >= 2) {
+      sp = sc;
+      sc = 1.0 / (tau - sp);
+    }
+    const double a = (step == 1 ? sc : 2.0 * sc) / e;
+    StepCoef<T> k;
+    k.a1 = (T)(a * nh * W1);
+    k.a2 = (T)(a * nh * W2);
+    k.alpha = (T)a;
+    k.gamma = (T)(-c * a);
+    k.beta = (T)(step == 1 ? 0.0 : -sp * sc);
+    out[step - 1] = k;
   }
-  const double a = (step == 1 ? sc : 2.0 * sc) / e;
-  k.a1 = (T)(a * nh * W1);
-  k.a2 = (T)(a * nh * W2);
-  k.alpha = (T)a;
-  k.gamma = (T)(-c * a);
-  k.beta = (T)(step == 1 ? 0.0 : -sp * sc);
-  return k;
 }
 
 // diagonal of H_j at a point touching `nfaces` box faces with potential v
@@ -102,6 +138,7 @@ __global__ __launch_bounds__(WG) void k_apply_h(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
     int nblk_pad, const T* __restrict__ Vj, const T* __restrict__ in,
     const T* prev, T* out, const FilterState* __restrict__ fs,
+    const StepCoef<T>* __restrict__ coef, int cdeg,
     const int* __restrict__ active, int step, int mode, double nh,
     long long base_override) {
   constexpr int SP = PPT * WG;
@@ -128,7 +165,9 @@ __global__ __launch_bounds__(WG) void k_apply_h(
   T* dst = out + base;
   const T* __restrict__ vv = Vj + fr.v_off;
 
-  const StepCoef<T> kc = step_coefs<T>(fs + j, step, mode, nh);
+  const StepCoef<T> kc =
+      mode == 0 ? h_coefs<T>(nh)
+                : wave_uniform(coef[(long long)j * cdeg + step - 1]);
   const bool use_prev = (mode == 1 && step > 1);
 
   __shared__ T lds[2][LW];
@@ -256,8 +295,8 @@ template <typename T, int PPT, int NS, int NT>
 __global__ __launch_bounds__(NT) void k_apply_hm(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
     int nblk_pad, const T* __restrict__ Vj, T* IN, T* PV,
-    const FilterState* __restrict__ fs, const int* __restrict__ active,
-    int step, double nh) {
+    const FilterState* __restrict__ fs, const StepCoef<T>* __restrict__ coef,
+    int cdeg, const int* __restrict__ active, int step, double nh) {
   static_assert(NS >= 2 && NS <= 3, "two or three steps per launch");
   constexpr int SP = PPT * NT;
   constexpr int NV = 2 * (NS - 1) + 1;   // V planes t - 2(NS-1) .. t
@@ -276,7 +315,8 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
   const T* __restrict__ vv = Vj + fr.v_off;
   StepCoef<T> kc[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) kc[s] = step_coefs<T>(fs + j, step + s, 1, nh);
+  for (int s = 0; s < NS; ++s)
+    kc[s] = wave_uniform(coef[(long long)j * cdeg + step + s - 1]);
   const bool use_prev = step > 1;
   const T tnh = (T)nh;
   __shared__ T L0[2][SP];          // y_{k-1}, plane t (double-buffered)
@@ -405,7 +445,8 @@ int multistep_class(int elem_bytes, const FragDev& d) {
 template <typename T>
 void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
               int ntiles, int cls, int ns, const int* active, int step,
-              const FilterState* fs, double alg_bytes, double flops) {
+              const FilterState* fs, const void* coef, int cdeg,
+              double alg_bytes, double flops) {
   const T* Vj;
   if constexpr (sizeof(T) == 8)
     Vj = (const T*)f->d_vf;
@@ -418,7 +459,7 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
 #define LAUNCHM(PP, NSS, NTT)                                                \
   hipLaunchKernelGGL((k_apply_hm<T, PP, NSS, NTT>), dim3(nblk), dim3(NTT), 0, \
                      stream, f->d_frag, tiles, ntiles, nblk, Vj, IN, PV, fs, \
-                     active, step, nh)
+                     (const StepCoef<T>*)coef, cdeg, active, step, nh)
 #define LAUNCHP(PP, NTT)                                                     \
   do {                                                                       \
     if (ns == 3) LAUNCHM(PP, 3, NTT);                                        \
@@ -437,10 +478,12 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
 }
 template void apply_hm<double>(ofm_ctx*, const ofm_frags*, double*, double*,
                                const int2*, int, int, int, const int*, int,
-                               const FilterState*, double, double);
+                               const FilterState*, const void*, int, double,
+                               double);
 template void apply_hm<float>(ofm_ctx*, const ofm_frags*, float*, float*,
                               const int2*, int, int, int, const int*, int,
-                              const FilterState*, double, double);
+                              const FilterState*, const void*, int, double,
+                              double);
 
 // ---------------------------------------------------------------------------
 // whole Chebyshev filter with the vector resident on chip (FP32 boxes of at
@@ -512,10 +555,10 @@ template <bool FULLZ>
 __device__ __forceinline__ void resident_filter(float* L, float (&old)[RN],
                                                 const float (&u)[RN], int a0,
                                                 bool own, int nz,
-                                                const FilterState* fs,
-                                                int degree, double nh) {
+                                                const StepCoef<float>* coef,
+                                                int degree) {
   for (int step = 1; step <= degree; ++step) {
-    const StepCoef<float> kc = step_coefs<float>(fs, step, 1, nh);
+    const StepCoef<float> kc = wave_uniform(coef[step - 1]);
     int nzs = nz;
     asm volatile("" : "+s"(nzs));   // keep per-plane tests inside the step
     resident_step<FULLZ>(old, u, L, a0, own, nzs, kc);
@@ -525,7 +568,8 @@ __device__ __forceinline__ void resident_filter(float* L, float (&old)[RN],
 __global__ __launch_bounds__(RN * RN) void k_filter_resident(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
     int nblk_pad, const float* __restrict__ Vj, float* X,
-    const FilterState* __restrict__ fs, const int* __restrict__ active,
+    const FilterState* __restrict__ fs,
+    const StepCoef<float>* __restrict__ coef, const int* __restrict__ active,
     int degree, double nh) {
   const int t = xcd_tile(blockIdx.x, nblk_pad);
   if (t >= ntiles) return;
@@ -559,10 +603,11 @@ __global__ __launch_bounds__(RN * RN) void k_filter_resident(
     }
   }
   __syncthreads();
+  const StepCoef<float>* cj = coef + (long long)j * degree;
   if (nz == RN)
-    resident_filter<true>(L, old, u, a0, own, nz, fs + j, degree, nh);
+    resident_filter<true>(L, old, u, a0, own, nz, cj, degree);
   else
-    resident_filter<false>(L, old, u, a0, own, nz, fs + j, degree, nh);
+    resident_filter<false>(L, old, u, a0, own, nz, cj, degree);
 #pragma unroll
   for (int z = 0; z < RN; ++z)
     if (own && z < nz)
@@ -576,13 +621,14 @@ bool resident_eligible(int elem_bytes, const FragDev& d) {
 
 void filter_resident(ofm_ctx* c, const ofm_frags* f, float* X,
                      const int2* tiles, int ntiles, const int* active,
-                     const FilterState* fs, int degree, double alg_bytes,
-                     double flops) {
+                     const FilterState* fs, const void* coef, int degree,
+                     double alg_bytes, double flops) {
   const int nblk = pad8(ntiles);
   Timed tm(c, "filter", alg_bytes, flops);
   hipLaunchKernelGGL(k_filter_resident, dim3(nblk), dim3(RN * RN), 0,
                      f->ctx->stream, f->d_frag, tiles, ntiles, nblk,
-                     (const float*)f->d_vf32, X, fs, active, degree,
+                     (const float*)f->d_vf32, X, fs,
+                     (const StepCoef<float>*)coef, active, degree,
                      -0.5 / (f->grid.h * f->grid.h));
   OFM_HIP(hipGetLastError());
 }
@@ -616,9 +662,9 @@ std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
 template <typename T>
 void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
              T* out, const int2* tiles, int ntiles, int variant,
-             const int* active, int step, const FilterState* fs, int mode,
-             long long base_override, double alg_bytes, double flops,
-             hipEvent_t ev0, hipEvent_t ev1) {
+             const int* active, int step, const FilterState* fs,
+             const void* coef, int cdeg, int mode, long long base_override,
+             double alg_bytes, double flops, hipEvent_t ev0, hipEvent_t ev1) {
   const T* Vj;   // potential of the fragment Hamiltonians
   if constexpr (sizeof(T) == 8)
     Vj = (const T*)f->d_vf;
@@ -633,7 +679,8 @@ void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
 #define LAUNCH(P)                                                            \
   hipLaunchKernelGGL((k_apply_h<T, P>), dim3(nblk), dim3(WG), 0, stream,     \
                      f->d_frag, tiles, ntiles, nblk, Vj, in, prev, out, fs,  \
-                     active, step, mode, nh, base_override)
+                     (const StepCoef<T>*)coef, cdeg, active, step, mode, nh, \
+                     base_override)
   if (ppt == 1) LAUNCH(1);
   else if (ppt == 2) LAUNCH(2);
   else if (ppt == 4) LAUNCH(4);
@@ -644,14 +691,27 @@ void apply_h(ofm_ctx* c, const ofm_frags* f, const T* in, const T* prev,
 }
 template void apply_h<double>(ofm_ctx*, const ofm_frags*, const double*,
                               const double*, double*, const int2*, int, int,
-                              const int*, int, const FilterState*, int,
-                              long long, double, double, hipEvent_t,
-                              hipEvent_t);
+                              const int*, int, const FilterState*,
+                              const void*, int, int, long long, double,
+                              double, hipEvent_t, hipEvent_t);
 template void apply_h<float>(ofm_ctx*, const ofm_frags*, const float*,
                              const float*, float*, const int2*, int, int,
-                             const int*, int, const FilterState*, int,
-                             long long, double, double, hipEvent_t,
+                             const int*, int, const FilterState*, const void*,
+                             int, int, long long, double, double, hipEvent_t,
                              hipEvent_t);
+
+template <typename T>
+void step_coefs_table(hipStream_t s, const ofm_frags* f, int degree,
+                      void* table) {
+  hipLaunchKernelGGL(k_step_coefs<T>, dim3((f->n_frag + 63) / 64), dim3(64),
+                     0, s, f->d_fs, f->n_frag, degree,
+                     -0.5 / (f->grid.h * f->grid.h), (StepCoef<T>*)table);
+  OFM_HIP(hipGetLastError());
+}
+template void step_coefs_table<double>(hipStream_t, const ofm_frags*, int,
+                                       void*);
+template void step_coefs_table<float>(hipStream_t, const ofm_frags*, int,
+                                      void*);
 
 }  // namespace k
 }  // namespace ofm
