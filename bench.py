@@ -353,6 +353,11 @@ def bench_config(P, torch, config, seed, steps, warmup, args, main):
                                 **_rate(fp["elements"], FP64_PEAK_TFS)),
         "gram_kernel": dict(kernel="k_gram (FP64 MFMA 16x16x4)",
                             **_rate(fp["gram"], FP64_PEAK_TFS)),
+        "rotate_kernel": dict(kernel="k_rotate (block rotations X Q, HX Q)",
+                              **_rate(fp["rotate"])),
+        "stencil_h_kernel": dict(kernel="k_apply_h (H X per iteration and "
+                                        "strips)",
+                                 **_rate(fp["stencil"])),
     }
     if do_global:
         E = fp["E"]
@@ -494,6 +499,8 @@ def main():
         "roofline": main_cfg["stencil_roofline"],
         "contractions": {"elements_fp64": main_cfg["elements_kernel"],
                          "gram_fp64": main_cfg["gram_kernel"]},
+        "other_kernels": {"rotate_fp64": main_cfg["rotate_kernel"],
+                          "stencil_h_fp64": main_cfg["stencil_h_kernel"]},
     }
     if "global" in main_cfg:
         out["global"] = main_cfg["global"]

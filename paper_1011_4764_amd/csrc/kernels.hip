@@ -756,7 +756,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 // (a convergence test needs only a few digits) and per chunk in FP64.  The
 // block is streamed once (non-temporal loads and stores: ~1% faster than
 // cached access on the alkane workload).
-template <typename T, int BMAX>
+template <typename T, int BMAX, bool WITH_HX>
 __global__ __launch_bounds__(RCH) void k_rotate(
     const FragDev* __restrict__ F, const int2* __restrict__ rt,
     const int* __restrict__ tlist, int nt, T* __restrict__ X,
@@ -779,7 +779,7 @@ __global__ __launch_bounds__(RCH) void k_rotate(
     qt[e] = (i < bw && k < bw && (!upper || k <= i)) ? (T)Qj[k * bw + i]
                                                     : T(0);
   }
-  if (HX)
+  if (WITH_HX)
     for (int i = threadIdx.x; i < bw; i += RCH) th[i] = theta[fr.th_off + i];
   __syncthreads();
   const int p = rt[t].y * RCH + threadIdx.x;
@@ -792,7 +792,7 @@ __global__ __launch_bounds__(RCH) void k_rotate(
                           : T(0);
   }
   T* hp = nullptr;
-  if (HX) {
+  if (WITH_HX) {
     hp = HX + fr.x_off + (ok ? p : 0);
 #pragma unroll
     for (int k = 0; k < BMAX; ++k)
@@ -819,19 +819,19 @@ __global__ __launch_bounds__(RCH) void k_rotate(
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           a = fma(x[k + u], q4[u], a);
-          if (HX) h = fma(hx[k + u], q4[u], h);
+          if (WITH_HX) h = fma(hx[k + u], q4[u], h);
         }
       }
     }
     if (ok) __builtin_nontemporal_store(a, &xp[(long long)i * fr.ld]);
-    if (HX) {
+    if (WITH_HX) {
       if (ok) __builtin_nontemporal_store(h, &hp[(long long)i * fr.ld]);
       const double r = ok ? (double)h - th[i] * (double)a : 0.0;
       const float ws = wave_sum((float)(r * r));
       if (lane == 0) red[wave][i] = ws;
     }
   }
-  if (HX) {
+  if (WITH_HX) {
     __syncthreads();
     for (int i = threadIdx.x; i < bw; i += RCH) {
       double s = 0;
@@ -849,10 +849,20 @@ void rotate(ofm_ctx* c, const ofm_frags* f, T* X, T* HX, const double* Q,
   for (int cl = 0; cl < 5; ++cl) nl += f->n_rtl[cl] > 0;
   Timed tm(c, "rotate", bytes, flops, nl);
   // one launch per width class (rotate_class)
+  // the X-only form (CholQR) holds half the registers of the X and HX form
+  // (a split of the Rayleigh-Ritz rotation into an X launch and an HX launch
+  // that reads the rotated X back ran 7% slower than the fused form)
 #define ROT(BM)                                                              \
-  hipLaunchKernelGGL((k_rotate<T, BM>), dim3(n), dim3(RCH), 0, c->stream,    \
-                     f->d_frag, f->d_rtiles, f->d_rtl[cl], n, X, HX, Q,      \
-                     theta, res_partial, active, upper)
+  do {                                                                       \
+    if (HX)                                                                  \
+      hipLaunchKernelGGL((k_rotate<T, BM, true>), dim3(n), dim3(RCH), 0,     \
+                         c->stream, f->d_frag, f->d_rtiles, f->d_rtl[cl], n, \
+                         X, HX, Q, theta, res_partial, active, upper);       \
+    else                                                                     \
+      hipLaunchKernelGGL((k_rotate<T, BM, false>), dim3(n), dim3(RCH), 0,    \
+                         c->stream, f->d_frag, f->d_rtiles, f->d_rtl[cl], n, \
+                         X, HX, Q, theta, res_partial, active, upper);       \
+  } while (0)
   for (int cl = 0; cl < 5; ++cl) {
     const int n = f->n_rtl[cl];
     if (n == 0) continue;

@@ -3,6 +3,8 @@
 // differences), and the scaled three-term Chebyshev step built on it.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 #include <vector>
 
@@ -291,6 +293,56 @@ constexpr int H2T = OFM_H2_THREADS;   // threads of a multi-step workgroup
 // the FP32 one 519 against 585 ms with the narrow ones.
 constexpr bool wide_wg(int elem_bytes) { return elem_bytes == 8; }
 
+// LDS planes of the multi-step kernel: rows of nx + 2 values whose first two
+// are zero, between two zero rows above and two below the box, so every +-1,
+// +-2 neighbour beyond a face reads 0 without a test; hm_cap is the padded
+// plane a launch of SP plane points holds (its eight planes of NS = 3 fit
+// the 160 KB of LDS of a CU)
+constexpr int hm_padded(int nx, int ny) { return (ny + 4) * (nx + 2); }
+// Global accesses of the multi-step kernel go through buffer resources
+// sized to the vector (or to nothing), whose range check makes a load past
+// the end return 0 and drops such a store: planes beyond the box, y_{k-2}
+// on the first step of a filter and lanes past the plane need no branch and
+// no select.  aux 2 marks an access non-temporal.
+typedef unsigned int hm_u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t hm_rsrc(const void* p,
+                                                          unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes,
+                                           0x00020000);
+}
+template <int AUX>
+__device__ __forceinline__ double hm_load(__amdgpu_buffer_rsrc_t r, double,
+                                          unsigned off) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ float hm_load(__amdgpu_buffer_rsrc_t r, float,
+                                         unsigned off) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ void hm_store(double v, __amdgpu_buffer_rsrc_t r,
+                                         unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(hm_u2, v), r, off,
+                                        0, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void hm_store(float v, __amdgpu_buffer_rsrc_t r,
+                                         unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r,
+                                        off, 0, AUX);
+}
+// byte offset that every buffer of the kernel rejects (boxes hold far fewer
+// than 2^30 bytes per vector; plane offsets added to it stay below 2^32)
+constexpr unsigned HM_OOB = 0x40000000u;
+constexpr int hm_cap(int sp, int elem_bytes) {
+  return sp + sp / 4 + 128 < 163840 / (8 * elem_bytes)
+             ? sp + sp / 4 + 128
+             : 163840 / (8 * elem_bytes);
+}
+
 template <typename T, int PPT, int NS, int NT>
 __global__ __launch_bounds__(NT) void k_apply_hm(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
@@ -299,6 +351,7 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
     int cdeg, const int* __restrict__ active, int step, double nh) {
   static_assert(NS >= 2 && NS <= 3, "two or three steps per launch");
   constexpr int SP = PPT * NT;
+  constexpr int CAP = hm_cap(SP, sizeof(T));
   constexpr int NV = 2 * (NS - 1) + 1;   // V planes t - 2(NS-1) .. t
   const int t0 = xcd_tile(blockIdx.x, nblk_pad);
   if (t0 >= ntiles) return;
@@ -308,21 +361,36 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
   const FragDev& fr = F[j];
   const int nx = fr.dims[0], ny = fr.dims[1], nz = fr.dims[2];
   const int plane = nx * ny;
-  if (plane > SP) return;       // the host launches only boxes that fit
+  // the host launches only boxes that fit
+  if (plane > SP || hm_padded(nx, ny) > CAP) return;
+  const int px = nx + 2;   // LDS row pitch
   const long long base = fr.x_off + (long long)v * fr.ld;
   T* in = IN + base;
   T* pv = PV + base;
   const T* __restrict__ vv = Vj + fr.v_off;
+  const unsigned vbytes = (unsigned)fr.npts * sizeof(T);
+  const unsigned pbytes = (unsigned)plane * sizeof(T);
+  const __amdgpu_buffer_rsrc_t r_in = hm_rsrc(in, vbytes);
+  const __amdgpu_buffer_rsrc_t r_pv = hm_rsrc(pv, vbytes);
+  const __amdgpu_buffer_rsrc_t r_v = hm_rsrc(vv, vbytes);
   StepCoef<T> kc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s)
     kc[s] = wave_uniform(coef[(long long)j * cdeg + step + s - 1]);
   const bool use_prev = step > 1;
+  // y_{k-2} does not exist on the first step of a filter: every load of it
+  // is out of range and returns 0
+  const __amdgpu_buffer_rsrc_t r_q = hm_rsrc(pv, use_prev ? vbytes : 0u);
   const T tnh = (T)nh;
-  __shared__ T L0[2][SP];          // y_{k-1}, plane t (double-buffered)
-  __shared__ T R[NS - 1][3][SP];   // stage outputs, last three planes
+  __shared__ T L0[2][CAP];          // y_{k-1}, plane t (double-buffered)
+  __shared__ T R[NS - 1][3][CAP];   // stage outputs, last three planes
   const int tid = threadIdx.x;
-  int pp[PPT], px[PPT], py[PPT];
+  for (int i = tid; i < 2 * CAP; i += NT) (&L0[0][0])[i] = T(0);
+  for (int i = tid; i < (NS - 1) * 3 * CAP; i += NT) (&R[0][0][0])[i] = T(0);
+  __syncthreads();   // the zeros land before any interior write
+  int pp[PPT], li[PPT], wi[PPT], nfxy[PPT];
+  unsigned po[PPT];   // byte offset of the point in a plane (HM_OOB: none)
+  bool wl[PPT];       // the wave holds a point of the plane in slot k
   bool ok[PPT];
   T W[NS][4][PPT];   // stage s outputs at planes n_s-4..n_s-1, n_s = t-2(s-1)
                      // (stage 0: the input y_{k-1} at planes t-2..t+1)
@@ -333,36 +401,45 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
   for (int k = 0; k < PPT; ++k) {
     const int p = tid + k * NT;
     ok[k] = p < plane;
-    pp[k] = ok[k] ? p : 0;
-    px[k] = pp[k] % nx;
-    py[k] = pp[k] / nx;
+    pp[k] = ok[k] ? p : 0;   // lanes past the plane work on point 0 and
+                             // store nothing
+    const int x = pp[k] % nx, y = pp[k] / nx;
+    li[k] = (y + 2) * px + x + 2;
+    // LDS writes of lanes past the plane go to element 0, a pad that no
+    // point reads (the first two elements of the top zero row), so every
+    // lane computes and writes and no branch hides a store
+    wi[k] = ok[k] ? li[k] : 0;
+    po[k] = ok[k] ? (unsigned)pp[k] * sizeof(T) : HM_OOB;
+    wl[k] = __builtin_amdgcn_readfirstlane((tid & ~63) + k * NT < plane);
+    nfxy[k] = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1);
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i) W[s][i][k] = 0;
-    W[0][2][k] = ok[k] ? in[pp[k]] : T(0);
-    W[0][3][k] = (ok[k] && nz > 1) ? in[plane + pp[k]] : T(0);
-    nw0[k] = (ok[k] && nz > 2) ? in[2 * plane + pp[k]] : T(0);
+    W[0][2][k] = hm_load<0>(r_in, T(), po[k]);
+    W[0][3][k] = hm_load<0>(r_in, T(), po[k] + pbytes);
+    nw0[k] = hm_load<0>(r_in, T(), po[k] + 2 * pbytes);
 #pragma unroll
     for (int i = 0; i < NV - 1; ++i) vq[i][k] = 0;
-    vq[NV - 1][k] = ok[k] ? vv[pp[k]] : T(0);
-    q[k] = (ok[k] && use_prev) ? pv[pp[k]] : T(0);
+    vq[NV - 1][k] = hm_load<0>(r_v, T(), po[k]);
+    q[k] = hm_load<0>(r_q, T(), po[k]);
   }
-  for (int t = 0; t < nz + 2 * (NS - 1); ++t) {
-    const int zoff = t * plane;
+  // One z plane.  Loads are issued for every lane at clamped addresses and
+  // the unwanted values replaced by 0, and in the steady state (every stage
+  // on a plane of the box) no branch depends on the plane, so the wait for
+  // a plane's loads does not also wait for the stores issued after them.
+  auto iter = [&](int t, auto steady_c) {
+    constexpr bool STEADY = decltype(steady_c)::value;
     T an[PPT], vn[PPT], qn[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       // the input and y_{k-2} streams are read once (non-temporal, leaving
-      // L2 to V_j, which the box's other vectors read again)
-      an[k] = (ok[k] && t + 3 < nz)
-                  ? __builtin_nontemporal_load(&in[zoff + 3 * plane + pp[k]])
-                  : T(0);
-      vn[k] = (ok[k] && t + 1 < nz) ? vv[zoff + plane + pp[k]] : T(0);
-      qn[k] = (ok[k] && use_prev && t + 1 < nz)
-                  ? __builtin_nontemporal_load(&pv[zoff + plane + pp[k]])
-                  : T(0);
-      if (t < nz && ok[k]) L0[t & 1][pp[k]] = W[0][2][k];
+      // L2 to V_j, which the box's other vectors read again); planes past
+      // the box read 0
+      an[k] = hm_load<2>(r_in, T(), po[k] + (unsigned)(t + 3) * pbytes);
+      vn[k] = hm_load<0>(r_v, T(), po[k] + (unsigned)(t + 1) * pbytes);
+      qn[k] = hm_load<2>(r_q, T(), po[k] + (unsigned)(t + 1) * pbytes);
+      if (STEADY || t < nz) L0[t & 1][wi[k]] = W[0][2][k];
     }
     __syncthreads();
     T nw[NS + 1][PPT];   // nw[s]: stage s output at plane n_s
@@ -371,33 +448,39 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
 #pragma unroll
     for (int s = 1; s <= NS; ++s) {
       const int z = t - 2 * (s - 1);
-      const bool live = z >= 0 && z < nz;
+      const bool live = STEADY || (z >= 0 && z < nz);
       const T* L = s == 1 ? L0[t & 1] : R[s - 2][live ? z % 3 : 0];
+      const int nfz = (z == 0) + (z == nz - 1);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         nw[s][k] = 0;
-        if (!live || !ok[k]) continue;
-        const int li = pp[k], x = px[k], y = py[k];
-        const T xm1 = x >= 1 ? L[li - 1] : T(0);
-        const T xm2 = x >= 2 ? L[li - 2] : T(0);
-        const T xp1 = x + 1 < nx ? L[li + 1] : T(0);
-        const T xp2 = x + 2 < nx ? L[li + 2] : T(0);
-        const T ym1 = y >= 1 ? L[li - nx] : T(0);
-        const T ym2 = y >= 2 ? L[li - 2 * nx] : T(0);
-        const T yp1 = y + 1 < ny ? L[li + nx] : T(0);
-        const T yp2 = y + 2 < ny ? L[li + 2 * nx] : T(0);
-        const int nfaces = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) +
-                           (z == 0) + (z == nz - 1);
-        const T s1 = (xm1 + xp1) + (ym1 + yp1) + (W[s - 1][1][k] + W[s - 1][3][k]);
-        const T s2 = (xm2 + xp2) + (ym2 + yp2) + (W[s - 1][0][k] + nw[s - 1][k]);
-        const T pn = s == 1 ? q[k] : W[s >= 2 ? s - 2 : 0][0][k];
-        const T o = stencil_point<T>(
-            W[s - 1][2][k], s1, s2,
-            point_diag<T>(tnh, nfaces, vq[NV - 1 - 2 * (s - 1)][k]), pn,
-            kc[s - 1]);
+        if (!live) continue;
+        // waves with no point of the plane in this slot skip the arithmetic
+        // (a scalar branch); their stores below go out of range and their
+        // LDS writes to the dead pad element.  Their value is a sum of this
+        // plane's inputs, so that no load is needed only inside the branch
+        // (a load sunk into it would make the wait counts path-dependent,
+        // and every plane would then wait for the stores issued after its
+        // loads).
+        T o = W[s - 1][2][k] + (vq[NV - 1 - 2 * (s - 1)][k] + q[k]);
+        if (wl[k]) {
+          const int c0 = li[k];
+          const T xm1 = L[c0 - 1], xm2 = L[c0 - 2];
+          const T xp1 = L[c0 + 1], xp2 = L[c0 + 2];
+          const T ym1 = L[c0 - px], ym2 = L[c0 - 2 * px];
+          const T yp1 = L[c0 + px], yp2 = L[c0 + 2 * px];
+          const T s1 = (xm1 + xp1) + (ym1 + yp1) + (W[s - 1][1][k] + W[s - 1][3][k]);
+          const T s2 = (xm2 + xp2) + (ym2 + yp2) + (W[s - 1][0][k] + nw[s - 1][k]);
+          const T pn = s == 1 ? q[k] : W[s >= 2 ? s - 2 : 0][0][k];
+          o = stencil_point<T>(
+              W[s - 1][2][k], s1, s2,
+              point_diag<T>(tnh, nfxy[k] + nfz, vq[NV - 1 - 2 * (s - 1)][k]), pn,
+              kc[s - 1]);
+        }
         if (s >= NS - 1)   // the last two iterates go to HBM
-          __builtin_nontemporal_store(o, &((s % 2 == 0) ? in : pv)[z * plane + li]);
-        if (s <= NS - 1) R[s - 1][z % 3][li] = o;
+          hm_store<2>(o, (s % 2 == 0) ? r_in : r_pv,
+                      po[k] + (unsigned)z * pbytes);
+        if (s <= NS - 1) R[s - 1][z % 3][wi[k]] = o;
         nw[s][k] = o;
       }
     }
@@ -416,7 +499,15 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
       vq[NV - 1][k] = vn[k];
       q[k] = qn[k];
     }
-  }
+  };
+  // planes [s_lo, s_hi) are steady: every stage lies inside the box; the
+  // three loops keep the steady one free of the edge tests
+  const int t_end = nz + 2 * (NS - 1);
+  const int s_lo = min(2 * (NS - 1), nz), s_hi = nz;
+  int t = 0;
+  for (; t < s_lo; ++t) iter(t, std::integral_constant<bool, false>{});
+  for (; t < s_hi; ++t) iter(t, std::integral_constant<bool, true>{});
+  for (; t < t_end; ++t) iter(t, std::integral_constant<bool, false>{});
 }
 
 // boxes the multi-step kernel takes: planes that fit at most 4 points per
@@ -425,19 +516,22 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
 // workload FP64 planes of 1025..1600 points ran 6% faster overall in the
 // 3- and 4-point classes than in one-step strips)
 bool multistep_eligible(int elem_bytes, const FragDev& d) {
-  (void)elem_bytes;
-  return d.dims[0] * d.dims[1] <= 4 * H2T;
+  return multistep_class(elem_bytes, d) > 0;
 }
 
-// launch class of the multi-step kernel for a box (0: not taken); the
+// launch class of the multi-step kernel for a box (0: not taken): the first
+// whose plane (SP points) and padded LDS plane (hm_cap) hold the box's.  The
 // classes are (points per thread, threads): 1: (1, H2T), 2: (2, H2T), and
-// for planes above 2 H2T points 3: (2, 2 H2T) with wide workgroups, else
-// 3: (3, H2T) and 4: (4, H2T)
+// 3: (2, 2 H2T) with wide workgroups, else 3: (3, H2T) and 4: (4, H2T)
 int multistep_class(int elem_bytes, const FragDev& d) {
-  if (!multistep_eligible(elem_bytes, d)) return 0;
   const int plane = d.dims[0] * d.dims[1];
-  if (wide_wg(elem_bytes)) return plane <= H2T ? 1 : plane <= 2 * H2T ? 2 : 3;
-  return (plane + H2T - 1) / H2T;
+  const int padded = hm_padded(d.dims[0], d.dims[1]);
+  const int ncls = wide_wg(elem_bytes) ? 3 : 4;
+  for (int cl = 1; cl <= ncls; ++cl) {
+    const int sp = (wide_wg(elem_bytes) && cl == 3) ? 4 * H2T : cl * H2T;
+    if (plane <= sp && padded <= hm_cap(sp, elem_bytes)) return cl;
+  }
+  return 0;
 }
 
 
