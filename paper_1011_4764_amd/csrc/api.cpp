@@ -189,9 +189,11 @@ void free_frags(ofm_frags* f) {
 // the batched eigensolver
 // ---------------------------------------------------------------------------
 // Steps per launch of the multi-step filter kernel for an even degree:
-// (3, n3) then (2, n2) with n3 even, so the filtered block ends in X.  Two
-// steps per launch is the default: three hold more registers and measured
-// slower on the 32^3 FP64 boxes (lower occupancy outweighs the bytes).
+// (3, n3) then (2, n2) with n3 even, so the filtered block ends in X.  The
+// default is two steps per launch in FP64 and three in the mixed form: on
+// the amorphous workload three steps took the FP32 fragment stage from 435
+// to 391 ms and left the FP64 one where it was (1265 against 1271 ms; its
+// three-step launches hold all 160 KB of LDS, one workgroup per CU).
 static std::vector<std::pair<int, int>> multistep_plan(int degree,
                                                        int max_steps) {
   const int n3 = max_steps >= 3 ? 2 * (degree / 6) : 0;
@@ -951,7 +953,7 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.autotune = !opts || opts->autotune >= 0;
     cfg.use_graph = !opts || opts->use_graph >= 0;
     cfg.resident = !opts || opts->resident >= 0;
-    cfg.fused = !opts || opts->fused == 0 ? 2
+    cfg.fused = !opts || opts->fused == 0 ? (fp64 ? 2 : 3)
                 : opts->fused < 0 ? 0 : std::min(opts->fused, 3);
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,

@@ -471,31 +471,33 @@ __device__ void load_sym(const FragDev& fr, const double* __restrict__ partial,
 // ---------------------------------------------------------------------------
 // CholQR factor: G = R^T R (after unit-diagonal scaling), Q = R^-1
 // ---------------------------------------------------------------------------
-constexpr int SLD = SMAX + 1;
 
 __global__ __launch_bounds__(WG) void k_cholinv(
     const FragDev* __restrict__ F, int nf, const double* __restrict__ partial,
     double* __restrict__ Q, const int* __restrict__ active,
-    int* __restrict__ flags) {
+    int* __restrict__ flags, int ld) {
   const int j = blockIdx.x;
   if (j >= nf) return;
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
   const int bw = fr.bw;
-  __shared__ double M[SMAX * SLD];
-  __shared__ double R[SMAX * SLD];
+  // two n x n matrices of row pitch ld = (largest block width) + 1, sized at
+  // launch
+  extern __shared__ double ch_lds[];
+  double* M = ch_lds;
+  double* R = M + (ld - 1) * ld;
   __shared__ double dsc[SMAX];
   __shared__ int fail;
-  load_sym(fr, partial, M, SLD, 1);
+  load_sym(fr, partial, M, ld, 1);
   // unit-diagonal scaling (column norms of X)
   for (int i = threadIdx.x; i < bw; i += WG) {
-    const double d = M[i * SLD + i];
+    const double d = M[i * ld + i];
     dsc[i] = d > 0 ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < bw * bw; e += WG) {
     const int i = e / bw, jj = e % bw;
-    R[i * SLD + jj] = M[i * SLD + jj] * dsc[i] * dsc[jj];
+    R[i * ld + jj] = M[i * ld + jj] * dsc[i] * dsc[jj];
   }
   if (threadIdx.x == 0) fail = 0;
   __syncthreads();
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(WG) void k_cholinv(
       // shifted Cholesky: G + 1e-12 * bw * I (scaled matrix has unit diagonal)
       for (int e = threadIdx.x; e < bw * bw; e += WG) {
         const int i = e / bw, jj = e % bw;
-        R[i * SLD + jj] = M[i * SLD + jj] * dsc[i] * dsc[jj] +
+        R[i * ld + jj] = M[i * ld + jj] * dsc[i] * dsc[jj] +
                           (i == jj ? 1e-12 * bw : 0.0);
       }
       if (threadIdx.x == 0) fail = 0;
@@ -512,19 +514,19 @@ __global__ __launch_bounds__(WG) void k_cholinv(
     }
     for (int k = 0; k < bw; ++k) {
       if (threadIdx.x == 0) {
-        const double d = R[k * SLD + k];
+        const double d = R[k * ld + k];
         if (!(d > 1e-300)) fail = 1;
-        R[k * SLD + k] = sqrt(d > 1e-300 ? d : 1e-300);
+        R[k * ld + k] = sqrt(d > 1e-300 ? d : 1e-300);
       }
       __syncthreads();
-      const double piv = R[k * SLD + k];
+      const double piv = R[k * ld + k];
       for (int jj = k + 1 + threadIdx.x; jj < bw; jj += WG)
-        R[k * SLD + jj] /= piv;
+        R[k * ld + jj] /= piv;
       __syncthreads();
       const int m = bw - k - 1;
       for (int e = threadIdx.x; e < m * m; e += WG) {
         const int a = k + 1 + e / m, b = k + 1 + e % m;
-        if (b >= a) R[a * SLD + b] -= R[k * SLD + a] * R[k * SLD + b];
+        if (b >= a) R[a * ld + b] -= R[k * ld + a] * R[k * ld + b];
       }
       __syncthreads();
     }
@@ -544,8 +546,8 @@ __global__ __launch_bounds__(WG) void k_cholinv(
     double x[SMAX];
     for (int row = col; row >= 0; --row) {
       double s = (row == col) ? 1.0 : 0.0;
-      for (int kk = row + 1; kk <= col; ++kk) s -= R[row * SLD + kk] * x[kk];
-      x[row] = s / R[row * SLD + row];
+      for (int kk = row + 1; kk <= col; ++kk) s -= R[row * ld + kk] * x[kk];
+      x[row] = s / R[row * ld + row];
     }
     for (int row = 0; row < bw; ++row)
       Qj[row * bw + col] = row <= col ? x[row] * dsc[row] : 0.0;
@@ -554,8 +556,10 @@ __global__ __launch_bounds__(WG) void k_cholinv(
 
 void cholinv(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
              const int* active, int* flags) {
-  hipLaunchKernelGGL(k_cholinv, dim3(f->n_frag), dim3(WG), 0, s, f->d_frag,
-                     f->n_frag, G, Q, active, flags);
+  const int ld = f->max_bw + 1;
+  hipLaunchKernelGGL(k_cholinv, dim3(f->n_frag), dim3(WG),
+                     2 * (size_t)f->max_bw * ld * sizeof(double), s,
+                     f->d_frag, f->n_frag, G, Q, active, flags, ld);
   OFM_HIP(hipGetLastError());
 }
 
@@ -570,52 +574,57 @@ constexpr int RRW = WG;   // threads per fragment
 __global__ __launch_bounds__(RRW) void k_rr_eig(
     const FragDev* __restrict__ F, int nf, const double* __restrict__ partial,
     double* __restrict__ Q, double* __restrict__ theta,
-    const int* __restrict__ active, int pre) {
+    const int* __restrict__ active, int pre, int ld) {
   const int j = blockIdx.x;
   if (j >= nf) return;
   if (active && !active[j]) return;
   const FragDev& fr = F[j];
   const int n = fr.bw;
-  __shared__ double A[SMAX * SLD];
-  __shared__ double U[SMAX * SLD];
-  __shared__ double Pm[SMAX * SLD];
+  // three n x n matrices of row pitch ld = (largest block width) + 1, sized
+  // at launch so that a 40-wide block does not reserve room for 64 (four
+  // fragments per CU instead of one)
+  extern __shared__ double rr_lds[];
+  const int nmax = ld - 1;
+  double* A = rr_lds;
+  double* U = A + nmax * ld;
+  double* Pm = U + nmax * ld;
   __shared__ double cs[SMAX / 2], sn[SMAX / 2];
   __shared__ int pp[SMAX / 2], qq[SMAX / 2];
   __shared__ double red[RRW / 64];
   __shared__ double offn, totn;
-  load_sym(fr, partial, A, SLD, 0);
+  load_sym(fr, partial, A, ld, 0);
   if (pre) {
     const double* Qj0 = Q + fr.small_off;
     for (int e = threadIdx.x; e < n * n; e += RRW)
-      Pm[(e / n) * SLD + e % n] = Qj0[e];
+      Pm[(e / n) * ld + e % n] = Qj0[e];
     __syncthreads();
     // U = A P, then A = P^T U (symmetrised)
     for (int e = threadIdx.x; e < n * n; e += RRW) {
       const int r = e / n, c = e % n;
       double acc = 0;
-      for (int k = 0; k < n; ++k) acc += A[r * SLD + k] * Pm[k * SLD + c];
-      U[r * SLD + c] = acc;
+      for (int k = 0; k < n; ++k) acc += A[r * ld + k] * Pm[k * ld + c];
+      U[r * ld + c] = acc;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n * n; e += RRW) {
       const int r = e / n, c = e % n;
       double acc = 0;
-      for (int k = 0; k < n; ++k) acc += Pm[k * SLD + r] * U[k * SLD + c];
-      A[r * SLD + c] = acc;
+      for (int k = 0; k < n; ++k) acc += Pm[k * ld + r] * U[k * ld + c];
+      A[r * ld + c] = acc;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n * n; e += RRW) {
       const int r = e / n, c = e % n;
       if (c > r) {
-        const double m = 0.5 * (A[r * SLD + c] + A[c * SLD + r]);
-        A[r * SLD + c] = m;
-        A[c * SLD + r] = m;
+        const double m = 0.5 * (A[r * ld + c] + A[c * ld + r]);
+        A[r * ld + c] = m;
+        A[c * ld + r] = m;
       }
     }
     __syncthreads();
   }
   for (int e = threadIdx.x; e < n * n; e += RRW)
-    U[(e / n) * SLD + e % n] = (e / n == e % n) ? 1.0 : 0.0;
+    U[(e / n) * ld + e % n] = (e / n == e % n) ? 1.0 : 0.0;
   const int n2 = n + (n & 1);       // round-robin over an even count
   const int npair = n2 / 2;
   __syncthreads();
@@ -623,7 +632,7 @@ __global__ __launch_bounds__(RRW) void k_rr_eig(
     // off-diagonal and total Frobenius norms
     double so = 0, st = 0;
     for (int e = threadIdx.x; e < n * n; e += RRW) {
-      const double a = A[(e / n) * SLD + e % n];
+      const double a = A[(e / n) * ld + e % n];
       st += a * a;
       if (e / n != e % n) so += a * a;
     }
@@ -656,9 +665,9 @@ __global__ __launch_bounds__(RRW) void k_rr_eig(
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1, s = 0;
         if (q < n) {
-          const double apq = A[p * SLD + q];
+          const double apq = A[p * ld + q];
           if (apq != 0.0) {
-            const double app = A[p * SLD + p], aqq = A[q * SLD + q];
+            const double app = A[p * ld + p], aqq = A[q * ld + q];
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0 ? 1.0 : -1.0) /
                              (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -675,9 +684,9 @@ __global__ __launch_bounds__(RRW) void k_rr_eig(
         const int p = pp[i], q = qq[i];
         if (q >= n || sn[i] == 0.0) continue;
         const double c = cs[i], s = sn[i];
-        const double ap = A[p * SLD + m], aq = A[q * SLD + m];
-        A[p * SLD + m] = c * ap - s * aq;
-        A[q * SLD + m] = s * ap + c * aq;
+        const double ap = A[p * ld + m], aq = A[q * ld + m];
+        A[p * ld + m] = c * ap - s * aq;
+        A[q * ld + m] = s * ap + c * aq;
       }
       __syncthreads();
       // columns: A <- A J, U <- U J
@@ -686,12 +695,12 @@ __global__ __launch_bounds__(RRW) void k_rr_eig(
         const int p = pp[i], q = qq[i];
         if (q >= n || sn[i] == 0.0) continue;
         const double c = cs[i], s = sn[i];
-        const double ap = A[m * SLD + p], aq = A[m * SLD + q];
-        A[m * SLD + p] = c * ap - s * aq;
-        A[m * SLD + q] = s * ap + c * aq;
-        const double up = U[m * SLD + p], uq = U[m * SLD + q];
-        U[m * SLD + p] = c * up - s * uq;
-        U[m * SLD + q] = s * up + c * uq;
+        const double ap = A[m * ld + p], aq = A[m * ld + q];
+        A[m * ld + p] = c * ap - s * aq;
+        A[m * ld + q] = s * ap + c * aq;
+        const double up = U[m * ld + p], uq = U[m * ld + q];
+        U[m * ld + p] = c * up - s * uq;
+        U[m * ld + q] = s * up + c * uq;
       }
       __syncthreads();
     }
@@ -699,29 +708,31 @@ __global__ __launch_bounds__(RRW) void k_rr_eig(
   // ascending order (stable by index), Q[k][rank] = U[k][i]
   double* Qj = Q + fr.small_off;
   for (int i = threadIdx.x; i < n; i += RRW) {
-    const double d = A[i * SLD + i];
+    const double d = A[i * ld + i];
     int rank = 0;
     for (int m = 0; m < n; ++m) {
-      const double dm = A[m * SLD + m];
+      const double dm = A[m * ld + m];
       rank += (dm < d) || (dm == d && m < i);
     }
     theta[fr.th_off + rank] = d;
     if (pre) {
       for (int k2 = 0; k2 < n; ++k2) {
         double acc = 0;
-        for (int mm = 0; mm < n; ++mm) acc += Pm[k2 * SLD + mm] * U[mm * SLD + i];
+        for (int mm = 0; mm < n; ++mm) acc += Pm[k2 * ld + mm] * U[mm * ld + i];
         Qj[k2 * n + rank] = acc;
       }
     } else {
-      for (int k2 = 0; k2 < n; ++k2) Qj[k2 * n + rank] = U[k2 * SLD + i];
+      for (int k2 = 0; k2 < n; ++k2) Qj[k2 * n + rank] = U[k2 * ld + i];
     }
   }
 }
 
 void rr_eig(hipStream_t s, const ofm_frags* f, const double* G, double* Q,
             double* theta, const int* active, int pre) {
-  hipLaunchKernelGGL(k_rr_eig, dim3(f->n_frag), dim3(RRW), 0, s, f->d_frag,
-                     f->n_frag, G, Q, theta, active, pre);
+  const int ld = f->max_bw + 1;
+  hipLaunchKernelGGL(k_rr_eig, dim3(f->n_frag), dim3(RRW),
+                     3 * (size_t)f->max_bw * ld * sizeof(double), s, f->d_frag,
+                     f->n_frag, G, Q, theta, active, pre, ld);
   OFM_HIP(hipGetLastError());
 }
 
