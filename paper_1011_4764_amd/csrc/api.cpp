@@ -189,15 +189,26 @@ void free_frags(ofm_frags* f) {
 // the batched eigensolver
 // ---------------------------------------------------------------------------
 // Steps per launch of the multi-step filter kernel for an even degree:
-// (3, n3) then (2, n2) with n3 even, so the filtered block ends in X.  The
-// default is two steps per launch in FP64 and three in the mixed form: on
-// the amorphous workload three steps took the FP32 fragment stage from 435
-// to 391 ms and left the FP64 one where it was (1265 against 1271 ms; its
-// three-step launches hold all 160 KB of LDS, one workgroup per CU).
+// (3, n3) then (2, n2) with n3 even, so the filtered block ends in X.
 static std::vector<std::pair<int, int>> multistep_plan(int degree,
                                                        int max_steps) {
   const int n3 = max_steps >= 3 ? 2 * (degree / 6) : 0;
   return {{3, n3}, {2, (degree - 3 * n3) / 2}};
+}
+
+// fused: 2 or 3 steps per launch as asked, or FUSED_AUTO
+constexpr int FUSED_AUTO = 4;
+
+// Most steps per launch for a launch class of the multi-step kernel: three,
+// except for FP64 planes of 1025..2048 points (the class of 1024-thread
+// workgroups).  Measured on the amorphous workload (fragment stage): FP32,
+// three steps everywhere 363 ms against 403 with two; FP64, two steps
+// everywhere 1229 ms, three everywhere 1232, three only in the 1024-thread
+// class 1281 (that class is slower with three steps, the 512-thread ones
+// faster).
+static int class_steps(bool fp64, int cls, int fused) {
+  if (fused == 2 || fused == 3) return fused;
+  return (fp64 && cls == 3) ? 2 : 3;
 }
 
 struct SolveCfg {
@@ -207,7 +218,8 @@ struct SolveCfg {
   bool autotune;
   bool use_graph;
   bool resident;
-  int fused;   // 0: one step per launch, else the most steps per launch
+  int fused;   // 0 or 1: one step per launch; 2, 3: the most steps per
+               // launch; FUSED_AUTO: per launch class (class_steps)
 };
 
 template <typename T>
@@ -370,8 +382,6 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                            (2 * rnb + rnpt) * w, 32.0 * rnb * cfg.degree);
     }
     const bool use_ms = have_ms && !tuning;
-    int ms_classes = 0;
-    for (int cl = 0; cl < 4; ++cl) ms_classes += f->n_vt[vset][cl] > 0;
     int2* const* st_tiles = tuning ? tune_tiles : strip_tiles;
     const int* st_n = tuning ? tune_n : strip_n;
     auto sweep = [&](bool timed_each) {
@@ -380,23 +390,26 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         // two iterates written, V_j once per box; a three-step launch leaves
         // its last iterate in the other buffer, so they come in pairs and
         // the filtered block ends in X
-        T* in = X;
-        T* pv = P;
-        int step = 1;
-        for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused))
-          for (int i = 0; i < count; ++i) {
-            for (int cl = 0; cl < 4; ++cl) {
-              if (f->n_vt[vset][cl] == 0) continue;
+        // each class follows its own plan (the classes hold different
+        // fragments, so their launches are independent)
+        for (int cl = 0; cl < 4; ++cl) {
+          if (f->n_vt[vset][cl] == 0) continue;
+          T* in = X;
+          T* pv = P;
+          int step = 1;
+          const int ms = class_steps(sizeof(T) == 8, cl + 1, cfg.fused);
+          for (const auto& [ns, count] : multistep_plan(cfg.degree, ms))
+            for (int i = 0; i < count; ++i) {
               const double by =
                   (step == 1 ? 3 * cnb[cl] : 4 * cnb[cl]) * w + cnpt[cl] * w;
               k::apply_hm<T>(timed_each ? c : nullptr, f, in, pv,
                              f->d_vt[vset][cl], f->n_vt[vset][cl], cl + 1, ns,
                              f->d_active, step, f->d_fs, f->d_coef,
                              cfg.degree, by, 32.0 * cnb[cl] * ns);
+              if (ns % 2) std::swap(in, pv);
+              step += ns;
             }
-            if (ns % 2) std::swap(in, pv);
-            step += ns;
-          }
+        }
       }
       if (st_n[var] == 0) return;
       for (int step = 1; step <= cfg.degree; ++step) {
@@ -446,13 +459,18 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       double by = 0;
       int launches = 0;
       if (use_ms) {
-        int steps_l = 0;
-        for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused)) {
-          (void)ns;
-          steps_l += count;
+        for (int cl = 0; cl < 4; ++cl) {
+          if (f->n_vt[vset][cl] == 0) continue;
+          int steps_l = 0;
+          const int ms = class_steps(sizeof(T) == 8, cl + 1, cfg.fused);
+          for (const auto& [ns, count] : multistep_plan(cfg.degree, ms)) {
+            (void)ns;
+            steps_l += count;
+          }
+          launches += steps_l;
+          by += (3 * cnb[cl] + cnpt[cl]) * w +
+                (steps_l - 1) * (4 * cnb[cl] + cnpt[cl]) * w;
         }
-        launches += steps_l * ms_classes;
-        by += (3 * mnb + mnpt) * w + (steps_l - 1) * (4 * mnb + mnpt) * w;
       }
       if (st_n[var] > 0) {
         launches += cfg.degree;
@@ -953,7 +971,7 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.autotune = !opts || opts->autotune >= 0;
     cfg.use_graph = !opts || opts->use_graph >= 0;
     cfg.resident = !opts || opts->resident >= 0;
-    cfg.fused = !opts || opts->fused == 0 ? (fp64 ? 2 : 3)
+    cfg.fused = !opts || opts->fused == 0 ? FUSED_AUTO
                 : opts->fused < 0 ? 0 : std::min(opts->fused, 3);
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,
