@@ -45,7 +45,8 @@ LDS_PEAK_GBS = LDS_BYTES_PER_CLK_CU * 256 * 2.4
 LDS_BYTES_PER_POINT_STEP = 11 * 4   # on-chip filter, FP32
 STENCIL_KERNELS = {
     "stencil": "k_apply_h (one Chebyshev filter step of H_j per launch)",
-    "multistep": "k_apply_hm (two Chebyshev filter steps of H_j per launch)",
+    "multistep": "k_apply_hm (three Chebyshev filter steps of H_j per "
+                 "launch: 4 HBM passes per 3 steps)",
     "sweep": "filter sweep replayed as one graph: k_apply_hm on the boxes "
              "whose plane fits it, k_apply_h on the others",
 }

@@ -116,10 +116,9 @@ typedef struct {
                             launches for every box                         */
   int fused;             /* filter steps per launch for the boxes whose xy
                             plane holds at most 2048 points (larger planes
-                            run one step per launch): 0: the default,
-                            three, but two for FP64 planes of more than 1024
-                            points; 2: two; 3: three; -1 (or 1): one.  Same
-                            bits in every case.                            */
+                            run one step per launch): 0 or 3: three
+                            [default]; 2: two; -1 (or 1): one.  Same bits in
+                            every case.                                    */
 } ofm_solve_opts;
 
 typedef struct ofm_ctx ofm_ctx;

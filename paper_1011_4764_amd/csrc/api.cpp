@@ -196,20 +196,11 @@ static std::vector<std::pair<int, int>> multistep_plan(int degree,
   return {{3, n3}, {2, (degree - 3 * n3) / 2}};
 }
 
-// fused: 2 or 3 steps per launch as asked, or FUSED_AUTO
-constexpr int FUSED_AUTO = 4;
-
-// Most steps per launch for a launch class of the multi-step kernel: three,
-// except for FP64 planes of 1025..2048 points (the class of 1024-thread
-// workgroups).  Measured on the amorphous workload (fragment stage): FP32,
-// three steps everywhere 363 ms against 403 with two; FP64, two steps
-// everywhere 1229 ms, three everywhere 1232, three only in the 1024-thread
-// class 1281 (that class is slower with three steps, the 512-thread ones
-// faster).
-static int class_steps(bool fp64, int cls, int fused) {
-  if (fused == 2 || fused == 3) return fused;
-  return (fp64 && cls == 3) ? 2 : 3;
-}
+// Three steps per launch is the default in both forms.  Measured on the
+// amorphous workload (fragment stage): FP32 363 ms against 403 with two (and
+// 382 with four, a form since dropped); FP64 1136 against 1217 with two,
+// once the three-step form of the 1024-thread class stopped spilling
+// registers (V read again from L2 instead of a five-plane register window).
 
 struct SolveCfg {
   double tol;
@@ -218,8 +209,7 @@ struct SolveCfg {
   bool autotune;
   bool use_graph;
   bool resident;
-  int fused;   // 0 or 1: one step per launch; 2, 3: the most steps per
-               // launch; FUSED_AUTO: per launch class (class_steps)
+  int fused;   // 0 or 1: one step per launch, else the most steps per launch
 };
 
 template <typename T>
@@ -397,8 +387,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
           T* in = X;
           T* pv = P;
           int step = 1;
-          const int ms = class_steps(sizeof(T) == 8, cl + 1, cfg.fused);
-          for (const auto& [ns, count] : multistep_plan(cfg.degree, ms))
+          for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused))
             for (int i = 0; i < count; ++i) {
               const double by =
                   (step == 1 ? 3 * cnb[cl] : 4 * cnb[cl]) * w + cnpt[cl] * w;
@@ -462,8 +451,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         for (int cl = 0; cl < 4; ++cl) {
           if (f->n_vt[vset][cl] == 0) continue;
           int steps_l = 0;
-          const int ms = class_steps(sizeof(T) == 8, cl + 1, cfg.fused);
-          for (const auto& [ns, count] : multistep_plan(cfg.degree, ms)) {
+          for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused)) {
             (void)ns;
             steps_l += count;
           }
@@ -971,7 +959,7 @@ ofm_status ofm_solve_fragments(ofm_ctx* c, ofm_frags* f,
     cfg.autotune = !opts || opts->autotune >= 0;
     cfg.use_graph = !opts || opts->use_graph >= 0;
     cfg.resident = !opts || opts->resident >= 0;
-    cfg.fused = !opts || opts->fused == 0 ? FUSED_AUTO
+    cfg.fused = !opts || opts->fused == 0 ? 3
                 : opts->fused < 0 ? 0 : std::min(opts->fused, 3);
     OFM_REQUIRE(!opts || opts->guard == 0 || opts->guard == f->guard,
                 OFM_E_INVALID,

@@ -352,7 +352,12 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
   static_assert(NS >= 2 && NS <= 3, "two or three steps per launch");
   constexpr int SP = PPT * NT;
   constexpr int CAP = hm_cap(SP, sizeof(T));
-  constexpr int NV = 2 * (NS - 1) + 1;   // V planes t - 2(NS-1) .. t
+  // V at the planes of the NS stages: a register window of planes
+  // t - 2(NS-1) .. t, or (FP64, three steps, 1024 threads, where the window
+  // would spill registers) V(t) alone with the other stages' planes read
+  // again from L2 at every plane (on 512 threads the window measured faster)
+  constexpr bool VRELOAD = NS == 3 && sizeof(T) == 8 && NT > 512;
+  constexpr int NV = VRELOAD ? 1 : 2 * (NS - 1) + 1;
   const int t0 = xcd_tile(blockIdx.x, nblk_pad);
   if (t0 >= ntiles) return;
   const int j = tiles[t0].x, v = tiles[t0].y;
@@ -388,14 +393,15 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
   for (int i = tid; i < 2 * CAP; i += NT) (&L0[0][0])[i] = T(0);
   for (int i = tid; i < (NS - 1) * 3 * CAP; i += NT) (&R[0][0][0])[i] = T(0);
   __syncthreads();   // the zeros land before any interior write
-  int pp[PPT], li[PPT], wi[PPT], nfxy[PPT];
+  int pp[PPT];
+  int lf[PPT];   // LDS index of the point | (box faces it touches in x, y) << 20
   unsigned po[PPT];   // byte offset of the point in a plane (HM_OOB: none)
   bool wl[PPT];       // the wave holds a point of the plane in slot k
   bool ok[PPT];
   T W[NS][4][PPT];   // stage s outputs at planes n_s-4..n_s-1, n_s = t-2(s-1)
                      // (stage 0: the input y_{k-1} at planes t-2..t+1)
   T nw0[PPT];        // input plane t+2
-  T vq[NV][PPT];     // V at planes t-2(NS-1) .. t
+  T vq[NV][PPT];     // V at planes t-2(NS-1) .. t (t alone with VRELOAD)
   T q[PPT];          // y_{k-2} at plane t
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -404,14 +410,10 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
     pp[k] = ok[k] ? p : 0;   // lanes past the plane work on point 0 and
                              // store nothing
     const int x = pp[k] % nx, y = pp[k] / nx;
-    li[k] = (y + 2) * px + x + 2;
-    // LDS writes of lanes past the plane go to element 0, a pad that no
-    // point reads (the first two elements of the top zero row), so every
-    // lane computes and writes and no branch hides a store
-    wi[k] = ok[k] ? li[k] : 0;
+    lf[k] = ((y + 2) * px + x + 2) |
+            (((x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1)) << 20);
     po[k] = ok[k] ? (unsigned)pp[k] * sizeof(T) : HM_OOB;
     wl[k] = __builtin_amdgcn_readfirstlane((tid & ~63) + k * NT < plane);
-    nfxy[k] = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1);
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -424,6 +426,11 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
     vq[NV - 1][k] = hm_load<0>(r_v, T(), po[k]);
     q[k] = hm_load<0>(r_q, T(), po[k]);
   }
+  // the point's LDS index; LDS writes of lanes past the plane go to element
+  // 0, a pad that no point reads (the first two elements of the top zero
+  // row), so every lane computes and writes and no branch hides a store
+  auto li_of = [&](int k) { return lf[k] & 0xfffff; };
+  auto wi_of = [&](int k) { return ok[k] ? (lf[k] & 0xfffff) : 0; };
   // One z plane.  Loads are issued for every lane at clamped addresses and
   // the unwanted values replaced by 0, and in the steady state (every stage
   // on a plane of the box) no branch depends on the plane, so the wait for
@@ -431,15 +438,21 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
   auto iter = [&](int t, auto steady_c) {
     constexpr bool STEADY = decltype(steady_c)::value;
     T an[PPT], vn[PPT], qn[PPT];
+    T vs[NS][PPT];   // VRELOAD: V at stage s's plane t - 2(s-1), s >= 2
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       // the input and y_{k-2} streams are read once (non-temporal, leaving
       // L2 to V_j, which the box's other vectors read again); planes past
-      // the box read 0
+      // the box (and before it) read 0
+      if (VRELOAD)
+#pragma unroll
+        for (int s = 2; s <= NS; ++s)
+          vs[s - 1][k] =
+              hm_load<0>(r_v, T(), po[k] + (unsigned)(t - 2 * (s - 1)) * pbytes);
       an[k] = hm_load<2>(r_in, T(), po[k] + (unsigned)(t + 3) * pbytes);
       vn[k] = hm_load<0>(r_v, T(), po[k] + (unsigned)(t + 1) * pbytes);
       qn[k] = hm_load<2>(r_q, T(), po[k] + (unsigned)(t + 1) * pbytes);
-      if (STEADY || t < nz) L0[t & 1][wi[k]] = W[0][2][k];
+      if (STEADY || t < nz) L0[t & 1][wi_of(k)] = W[0][2][k];
     }
     __syncthreads();
     T nw[NS + 1][PPT];   // nw[s]: stage s output at plane n_s
@@ -462,9 +475,11 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
         // (a load sunk into it would make the wait counts path-dependent,
         // and every plane would then wait for the stores issued after its
         // loads).
-        T o = W[s - 1][2][k] + (vq[NV - 1 - 2 * (s - 1)][k] + q[k]);
+        const T vz = (VRELOAD && s >= 2) ? vs[s - 1][k]
+                                         : vq[VRELOAD ? 0 : NV - 1 - 2 * (s - 1)][k];
+        T o = W[s - 1][2][k] + (vz + q[k]);
         if (wl[k]) {
-          const int c0 = li[k];
+          const int c0 = li_of(k);
           const T xm1 = L[c0 - 1], xm2 = L[c0 - 2];
           const T xp1 = L[c0 + 1], xp2 = L[c0 + 2];
           const T ym1 = L[c0 - px], ym2 = L[c0 - 2 * px];
@@ -474,13 +489,13 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
           const T pn = s == 1 ? q[k] : W[s >= 2 ? s - 2 : 0][0][k];
           o = stencil_point<T>(
               W[s - 1][2][k], s1, s2,
-              point_diag<T>(tnh, nfxy[k] + nfz, vq[NV - 1 - 2 * (s - 1)][k]), pn,
+              point_diag<T>(tnh, (lf[k] >> 20) + nfz, vz), pn,
               kc[s - 1]);
         }
         if (s >= NS - 1)   // the last two iterates go to HBM
           hm_store<2>(o, (s % 2 == 0) ? r_in : r_pv,
                       po[k] + (unsigned)z * pbytes);
-        if (s <= NS - 1) R[s - 1][z % 3][wi[k]] = o;
+        if (s <= NS - 1) R[s - 1][z % 3][wi_of(k)] = o;
         nw[s][k] = o;
       }
     }

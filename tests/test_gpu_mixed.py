@@ -207,7 +207,7 @@ def test_multistep_plane_classes_bit_identical(mctx):
     """FP32 boxes in all four plane classes of the multi-step kernel (1 to 4
     points per thread of a 512-thread workgroup: planes of 480, 900, 1280
     and 1920 points), on-chip filter off: three steps per launch (the
-    mixed default) and two, one launch per class, give the same bits as
+    default) and two, one launch per class, give the same bits as
     one step per launch, graph on and off, and the eigenvalues match the
     oracle's."""
     rng = np.random.default_rng(12)
@@ -218,7 +218,7 @@ def test_multistep_plane_classes_bit_identical(mctx):
     st = [3, 4, 3, 4]
     s = box_system(shape, 0.5, lo, dims, st, V=V)
     out = []
-    for fused, graph in ((0, 0), (-1, 0), (0, -1), (2, 0)):
+    for fused, graph in ((0, 0), (-1, 0), (0, -1), (2, 0), (2, -1)):
         _say("plane classes: fused", fused, "graph", graph)
         f = _build(mctx, s)
         status, eps, it, cv = P.ofm_solve_fragments(
