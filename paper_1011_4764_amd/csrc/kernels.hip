@@ -530,7 +530,7 @@ __global__ __launch_bounds__(WG) void k_cholinv(
       }
       __syncthreads();
     }
-    // every thread takes the verdict into a register, and all of them have
+    // every thread takes the outcome into a register, and all of them have
     // taken it before thread 0 may reset `fail` for the shifted attempt
     const int failed = fail;
     __syncthreads();

@@ -296,8 +296,8 @@ constexpr bool wide_wg(int elem_bytes) { return elem_bytes == 8; }
 // LDS planes of the multi-step kernel: rows of nx + 2 values whose first two
 // are zero, between two zero rows above and two below the box, so every +-1,
 // +-2 neighbour beyond a face reads 0 without a test; hm_cap is the padded
-// plane a launch of SP plane points holds (its eight planes of NS = 3 fit
-// the 160 KB of LDS of a CU)
+// plane a launch of SP plane points holds (5/4 of SP: a 32 x 32 plane pads
+// to 1224 of 1280; eight planes of NS = 3 fit the 160 KB of LDS of a CU)
 constexpr int hm_padded(int nx, int ny) { return (ny + 4) * (nx + 2); }
 // Global accesses of the multi-step kernel go through buffer resources
 // sized to the vector (or to nothing), whose range check makes a load past
@@ -338,13 +338,22 @@ __device__ __forceinline__ void hm_store(float v, __amdgpu_buffer_rsrc_t r,
 // than 2^30 bytes per vector; plane offsets added to it stay below 2^32)
 constexpr unsigned HM_OOB = 0x40000000u;
 constexpr int hm_cap(int sp, int elem_bytes) {
-  return sp + sp / 4 + 128 < 163840 / (8 * elem_bytes)
-             ? sp + sp / 4 + 128
+  return sp + sp / 4 < 163840 / (8 * elem_bytes)
+             ? sp + sp / 4
              : 163840 / (8 * elem_bytes);
+}
+// waves per SIMD the compiler must leave room for: the FP64 three-step
+// form on 512 threads with 2 points each is held to 128 registers so that
+// two of its workgroups share a CU (their LDS planes fit 160 KB together):
+// 2.4% off the amorphous FP64 fragment stage
+template <typename T, int PPT, int NS, int NT>
+constexpr int hm_waves_per_eu() {
+  return (sizeof(T) == 8 && NS == 3 && PPT == 2 && NT == 512) ? 4 : 1;
 }
 
 template <typename T, int PPT, int NS, int NT>
-__global__ __launch_bounds__(NT) void k_apply_hm(
+__global__ __launch_bounds__(NT) __attribute__((
+    amdgpu_waves_per_eu(hm_waves_per_eu<T, PPT, NS, NT>()))) void k_apply_hm(
     const FragDev* __restrict__ F, const int2* __restrict__ tiles, int ntiles,
     int nblk_pad, const T* __restrict__ Vj, T* IN, T* PV,
     const FilterState* __restrict__ fs, const StepCoef<T>* __restrict__ coef,
@@ -353,10 +362,10 @@ __global__ __launch_bounds__(NT) void k_apply_hm(
   constexpr int SP = PPT * NT;
   constexpr int CAP = hm_cap(SP, sizeof(T));
   // V at the planes of the NS stages: a register window of planes
-  // t - 2(NS-1) .. t, or (FP64, three steps, 1024 threads, where the window
-  // would spill registers) V(t) alone with the other stages' planes read
-  // again from L2 at every plane (on 512 threads the window measured faster)
-  constexpr bool VRELOAD = NS == 3 && sizeof(T) == 8 && NT > 512;
+  // t - 2(NS-1) .. t, or (FP64, three steps, where the window would not fit
+  // the 128 registers of the occupancy these launches keep) V(t) alone with
+  // the other stages' planes read again from L2 at every plane
+  constexpr bool VRELOAD = NS == 3 && sizeof(T) == 8;
   constexpr int NV = VRELOAD ? 1 : 2 * (NS - 1) + 1;
   const int t0 = xcd_tile(blockIdx.x, nblk_pad);
   if (t0 >= ntiles) return;
