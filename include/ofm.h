@@ -99,8 +99,9 @@ typedef struct {
   double tol;            /* residual bound ||H_j phi - eps phi||_2 per wanted
                             state [1e-10 FP64, 2e-5 mixed]                   */
   int max_iter;          /* outer (filter + Rayleigh-Ritz) iterations [60]   */
-  int guard;             /* extra block vectors beyond s_j [8]               */
-  int degree;            /* Chebyshev filter degree per iteration [32]       */
+  int guard;             /* extra block vectors beyond s_j [6]               */
+  int degree;            /* Chebyshev filter degree per iteration, rounded
+                            up to even [42 FP64, 36 mixed]                   */
   unsigned long long seed; /* start-vector seed [0]                          */
   int use_graph;         /* >= 0: the Chebyshev filter sweep is captured once
                             as a HIP graph and replayed every iteration [on];

@@ -14,9 +14,11 @@
 
 #include "ofm.h"
 
-// extra block vectors beyond s_j in the fragment eigensolver
+// extra block vectors beyond s_j in the fragment eigensolver (6 with the
+// default filter degrees below measured best of 4..16 on the amorphous
+// workload in both forms)
 #ifndef OFM_GUARD_VECTORS
-#define OFM_GUARD_VECTORS 8
+#define OFM_GUARD_VECTORS 6
 #endif
 
 namespace ofm {

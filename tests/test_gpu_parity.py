@@ -539,7 +539,7 @@ def test_homo_subset_errors(ctx, tiny0):
 
 
 def test_widest_block_end_to_end(ctx):
-    """The widest supported block (56 states + 8 guard vectors = 64: 4x4
+    """The widest supported block (58 states + 6 guard vectors = 64: 4x4
     Gram tiles, 64-wide rotations, 64x64 Jacobi, 4x4 pair tiles) on two
     overlapping ragged boxes: eigenvalues within 1e-8 Ha and the window of
     the global solve within 1e-8 Ha of the oracle."""
@@ -548,7 +548,7 @@ def test_widest_block_end_to_end(ctx):
     V = -np.abs(rng.standard_normal(shape[::-1])) * 0.5
     lo = [(0, 0, 0), (6, 1, 1)]
     dims = [(11, 10, 11), (11, 10, 10)]
-    states = [56, 56]
+    states = [58, 58]
     s = box_system(shape, 0.5, lo, dims, states, V=V)
     r = O.run(V, 0.5, lo, dims, states)
     f = _build(ctx, s)
