@@ -44,7 +44,9 @@ LDS_BYTES_PER_CLK_CU = 256.0
 LDS_PEAK_GBS = LDS_BYTES_PER_CLK_CU * 256 * 2.4
 LDS_BYTES_PER_POINT_STEP = 11 * 4   # on-chip filter, FP32
 STENCIL_KERNELS = {
-    "stencil": "k_apply_h (one Chebyshev filter step of H_j per launch)",
+    "stencil": "k_apply_h (one application of H_j per launch: H X, and "
+               "filter steps in strips; FP32 H X also as one-stage "
+               "k_apply_hm)",
     "multistep": "k_apply_hm (three Chebyshev filter steps of H_j per "
                  "launch: 4 HBM passes per 3 steps)",
     "sweep": "filter sweep replayed as one graph: k_apply_hm on the boxes "
@@ -399,7 +401,8 @@ def bench_config(P, torch, config, seed, steps, warmup, args, main):
         mixed["elements_kernel"]["frac_bf16_peak_3_products"] = \
             3 * mixed["elements_kernel"]["TFLOPs"] / BF16_PEAK_TFS
         for fam, name in (("multistep", "k_apply_hm<float>"),
-                          ("stencil", "k_apply_h<float>"),
+                          ("stencil", "k_apply_h<float> and one-stage "
+                                      "k_apply_hm<float> (H X)"),
                           ("sweep", "k_apply_hm<float> + k_apply_h<float> "
                                     "(graph)")):
             s_ = mx[fam]

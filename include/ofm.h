@@ -106,10 +106,12 @@ typedef struct {
   int use_graph;         /* >= 0: the Chebyshev filter sweep is captured once
                             as a HIP graph and replayed every iteration [on];
                             -1: launch its kernels one by one               */
-  int autotune;          /* >= 0: time the stencil variants on the first
-                            filter sweep, once per (precision, largest box
-                            plane) and context, and keep the fastest [on];
-                            -1: use the fixed default variant              */
+  int autotune;          /* >= 0: time the variants of the strip stencil
+                            (boxes outside the multi-step classes, and H X
+                            in FP64) on the first filter sweep, once per
+                            (precision, largest box plane) and context, and
+                            keep the fastest [on]; -1: use the fixed
+                            default variant                                */
   int resident;          /* >= 0: in the mixed form, boxes of at most 32
                             points per axis run the whole filter in one
                             launch with the vector held on chip (same bits

@@ -248,9 +248,10 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       if (*e) (void)hipGraphExecDestroy(*e);
     }
   } graph_guard{&sweep_exec};
-  // stencil variant: cached per (precision, largest plane), else timed on
-  // the first filter sweep (steps 2..7 cycle through the variants; every
-  // variant computes identical values, so tuning never changes results)
+  // stencil variant of the strip launches: cached per (precision, largest
+  // plane), else timed on the strips of the first filter sweep (steps 2..7
+  // cycle through the variants; every variant computes identical values, so
+  // tuning never changes results)
   const long long key = (long long)sizeof(T) * 1000000000LL + f->max_plane;
   int var = f->variant;
   bool tuning = false;
@@ -292,12 +293,33 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
     k::gram<T>(c, f, X, X, f->d_G, f->d_active, nb * w, nb2 * 2.0 * 0.5);
     k::cholinv(s, f, f->d_G, f->d_Q, f->d_active, f->d_flags);
   };
+  // H X over every vector of the active fragments.  FP32: boxes of the
+  // multi-step classes march along z one plane per workgroup (one stage),
+  // the others run in strips; both evaluate a point with the same
+  // arithmetic, so the split does not change a bit (amorphous workload:
+  // 1.27 against ~2.2 ms per H X; in FP64 the strips were faster, 2.56
+  // against 3.03 ms, the 2048-point planes holding one workgroup per CU)
+  const bool hx_ms = sizeof(T) == 4 && cfg.fused >= 2 && f->n_vt_all[0] > 0;
   auto apply_plain = [&]() {
-    double nb, npt, nb2;
-    sums(nb, npt, nb2);
-    k::apply_h<T>(c, f, X, X, HX, f->d_tiles[var], f->n_tiles[var], var,
-                  f->d_active, 0, f->d_fs, nullptr, 0, 0, -1,
-                  (2 * nb + npt) * w, 28.0 * nb);
+    double cb[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0}, rb = 0, rp = 0;
+    for (int j = 0; j < nf; ++j)
+      if (act[j]) {
+        const FragDev& d = f->host[j];
+        const int cls = hx_ms ? k::multistep_class((int)w, d) : 0;
+        (cls > 0 ? cb[cls - 1] : rb) += (double)d.npts * d.bw;
+        (cls > 0 ? cp[cls - 1] : rp) += d.npts;
+      }
+    if (hx_ms)
+      for (int cl = 0; cl < 4; ++cl)
+        if (f->n_vt[0][cl] > 0)
+          k::apply_hm<T>(c, f, X, HX, f->d_vt[0][cl], f->n_vt[0][cl], cl + 1,
+                         1, f->d_active, 1, nullptr, nullptr, 0,
+                         (2 * cb[cl] + cp[cl]) * w, 28.0 * cb[cl]);
+    int2* const* tl = hx_ms ? f->d_tiles_rest[0] : f->d_tiles;
+    const int* tn = hx_ms ? f->n_tiles_rest[0] : f->n_tiles;
+    if (tn[var] > 0)
+      k::apply_h<T>(c, f, X, X, HX, tl[var], tn[var], var, f->d_active, 0,
+                    f->d_fs, nullptr, 0, 0, -1, (2 * rb + rp) * w, 28.0 * rb);
   };
   int n_active = nf;
   auto rayleigh_ritz = [&]() {
@@ -336,10 +358,9 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                              : res ? f->d_tiles_nr : f->d_tiles;
   const int* strip_n = have_ms ? f->n_tiles_rest[vset]
                        : res ? f->n_tiles_nr : f->n_tiles;
-  // the autotuning sweep runs every non-resident box in strips
-  int2* const* tune_tiles = res ? f->d_tiles_nr : f->d_tiles;
-  const int* tune_n = res ? f->n_tiles_nr : f->n_tiles;
-  if (tune_n[var] == 0) tuning = false;   // nothing left to tune
+  // the variant only changes the strip launches, so the autotuning sweep
+  // times those (boxes of the multi-step classes keep their launches)
+  if (strip_n[var] == 0) tuning = false;   // nothing to tune
   for (int it = 1; it < cfg.max_iter && n_active > 0; ++it) {
     k::step_coefs_table<T>(s, f, cfg.degree, f->d_coef);
     // filter work: unlocked vectors of the active fragments, per class
@@ -353,7 +374,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         if (res && k::resident_eligible((int)w, d)) {
           rnb += u;
           rnpt += d.npts;
-        } else if (have_ms && !tuning && cls > 0) {
+        } else if (have_ms && cls > 0) {
           mnb += u;
           mnpt += d.npts;
           cnb[cls - 1] += u;
@@ -371,11 +392,8 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                            f->d_fs, f->d_coef, cfg.degree,
                            (2 * rnb + rnpt) * w, 32.0 * rnb * cfg.degree);
     }
-    const bool use_ms = have_ms && !tuning;
-    int2* const* st_tiles = tuning ? tune_tiles : strip_tiles;
-    const int* st_n = tuning ? tune_n : strip_n;
     auto sweep = [&](bool timed_each) {
-      if (use_ms) {
+      if (have_ms) {
         // y_{k-1}, y_{k-2} read (no y_{k-2} on the first launch), the last
         // two iterates written, V_j once per box; a three-step launch leaves
         // its last iterate in the other buffer, so they come in pairs and
@@ -400,7 +418,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
             }
         }
       }
-      if (st_n[var] == 0) return;
+      if (strip_n[var] == 0) return;
       for (int step = 1; step <= cfg.degree; ++step) {
         const bool odd = step & 1;
         const T* in = odd ? X : P;
@@ -414,12 +432,13 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
           e0 = tev[step - 2][0];
           e1 = tev[step - 2][1];
         }
-        k::apply_h<T>(timed_each ? c : nullptr, f, in, prev, out, st_tiles[sv],
-                      st_n[sv], sv, f->d_active, step, f->d_fs, f->d_coef,
-                      cfg.degree, 1, -1, by, 32.0 * snb, e0, e1);
+        k::apply_h<T>(timed_each ? c : nullptr, f, in, prev, out,
+                      strip_tiles[sv], strip_n[sv], sv, f->d_active, step,
+                      f->d_fs, f->d_coef, cfg.degree, 1, -1, by, 32.0 * snb,
+                      e0, e1);
       }
     };
-    if (!use_ms && st_n[var] == 0) {
+    if (!have_ms && strip_n[var] == 0) {
       // every box took the on-chip filter
     } else if (tuning || !cfg.use_graph) {
       sweep(true);
@@ -447,7 +466,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       // kernel family that carries its work (a mix of both, "sweep")
       double by = 0;
       int launches = 0;
-      if (use_ms) {
+      if (have_ms) {
         for (int cl = 0; cl < 4; ++cl) {
           if (f->n_vt[vset][cl] == 0) continue;
           int steps_l = 0;
@@ -460,13 +479,13 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
                 (steps_l - 1) * (4 * cnb[cl] + cnpt[cl]) * w;
         }
       }
-      if (st_n[var] > 0) {
+      if (strip_n[var] > 0) {
         launches += cfg.degree;
         for (int step = 1; step <= cfg.degree; ++step)
           by += (step == 1 ? 2 * snb : 3 * snb) * w + snpt * w;
       }
-      const char* fam = !use_ms ? "stencil"
-                        : st_n[var] == 0 ? "multistep" : "sweep";
+      const char* fam = !have_ms ? "stencil"
+                        : strip_n[var] == 0 ? "multistep" : "sweep";
       Timed tm(c, fam, by, 32.0 * (mnb + snb) * cfg.degree, launches);
       OFM_HIP(hipGraphLaunch(sweep_exec, s));
     }

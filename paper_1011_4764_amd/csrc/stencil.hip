@@ -281,7 +281,9 @@ __global__ __launch_bounds__(WG) void k_apply_h(
 // iterate goes to the buffer of its parity (IN holds y_{k-1}, PV y_{k-2}),
 // after each point's last read there, exactly as single-step launches leave
 // it.  Points are evaluated by stencil_point in the same order as k_apply_h,
-// so the results are bit-identical to NS single-step launches.
+// so the results are bit-identical to NS single-step launches.  NS = 1
+// (FP32) is the Rayleigh-Ritz product PV <- H_j IN over every vector
+// (locked ones included), bit-identical to k_apply_h in mode 0.
 #ifndef OFM_H2_THREADS
 #define OFM_H2_THREADS 512
 #endif
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(NT) __attribute__((
     int nblk_pad, const T* __restrict__ Vj, T* IN, T* PV,
     const FilterState* __restrict__ fs, const StepCoef<T>* __restrict__ coef,
     int cdeg, const int* __restrict__ active, int step, double nh) {
-  static_assert(NS >= 2 && NS <= 3, "two or three steps per launch");
+  static_assert(NS >= 1 && NS <= 3, "H y, or two or three steps per launch");
   constexpr int SP = PPT * NT;
   constexpr int CAP = hm_cap(SP, sizeof(T));
   // V at the planes of the NS stages: a register window of planes
@@ -371,7 +373,8 @@ __global__ __launch_bounds__(NT) __attribute__((
   if (t0 >= ntiles) return;
   const int j = tiles[t0].x, v = tiles[t0].y;
   if (active && !active[j]) return;
-  if (v < fs[j].lock) return;   // locked Ritz vectors are left as they are
+  // the filter leaves locked Ritz vectors as they are
+  if (NS > 1 && v < fs[j].lock) return;
   const FragDev& fr = F[j];
   const int nx = fr.dims[0], ny = fr.dims[1], nz = fr.dims[2];
   const int plane = nx * ny;
@@ -388,16 +391,22 @@ __global__ __launch_bounds__(NT) __attribute__((
   const __amdgpu_buffer_rsrc_t r_pv = hm_rsrc(pv, vbytes);
   const __amdgpu_buffer_rsrc_t r_v = hm_rsrc(vv, vbytes);
   StepCoef<T> kc[NS];
+  if constexpr (NS == 1) {
+    kc[0] = h_coefs<T>(nh);
+  } else {
 #pragma unroll
-  for (int s = 0; s < NS; ++s)
-    kc[s] = wave_uniform(coef[(long long)j * cdeg + step + s - 1]);
-  const bool use_prev = step > 1;
+    for (int s = 0; s < NS; ++s)
+      kc[s] = wave_uniform(coef[(long long)j * cdeg + step + s - 1]);
+  }
+  const bool use_prev = NS > 1 && step > 1;
   // y_{k-2} does not exist on the first step of a filter: every load of it
   // is out of range and returns 0
   const __amdgpu_buffer_rsrc_t r_q = hm_rsrc(pv, use_prev ? vbytes : 0u);
   const T tnh = (T)nh;
-  __shared__ T L0[2][CAP];          // y_{k-1}, plane t (double-buffered)
-  __shared__ T R[NS - 1][3][CAP];   // stage outputs, last three planes
+  // y_{k-1}, plane t (double-buffered); stage outputs, last three planes
+  // (no stage output is read back when NS = 1)
+  __shared__ T L0[2][CAP];
+  __shared__ T R[NS > 1 ? NS - 1 : 1][NS > 1 ? 3 : 1][NS > 1 ? CAP : 1];
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * CAP; i += NT) (&L0[0][0])[i] = T(0);
   for (int i = tid; i < (NS - 1) * 3 * CAP; i += NT) (&R[0][0][0])[i] = T(0);
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(NT) __attribute__((
     for (int s = 1; s <= NS; ++s) {
       const int z = t - 2 * (s - 1);
       const bool live = STEADY || (z >= 0 && z < nz);
-      const T* L = s == 1 ? L0[t & 1] : R[s - 2][live ? z % 3 : 0];
+      const T* L = s == 1 ? L0[t & 1] : R[s >= 2 ? s - 2 : 0][live ? z % 3 : 0];
       const int nfz = (z == 0) + (z == nz - 1);
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
@@ -504,7 +513,7 @@ __global__ __launch_bounds__(NT) __attribute__((
         if (s >= NS - 1)   // the last two iterates go to HBM
           hm_store<2>(o, (s % 2 == 0) ? r_in : r_pv,
                       po[k] + (unsigned)z * pbytes);
-        if (s <= NS - 1) R[s - 1][z % 3][wi_of(k)] = o;
+        if (NS > 1 && s <= NS - 1) R[s - 1][z % 3][wi_of(k)] = o;
         nw[s][k] = o;
       }
     }
@@ -572,7 +581,8 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
     Vj = (const T*)f->d_vf32;
   const double nh = -0.5 / (f->grid.h * f->grid.h);
   const int nblk = pad8(ntiles);
-  Timed tm(c, "multistep", alg_bytes, flops);
+  // the H X launches (ns = 1) are booked with the other H X launches
+  Timed tm(c, ns == 1 ? "stencil" : "multistep", alg_bytes, flops);
   hipStream_t stream = f->ctx->stream;
 #define LAUNCHM(PP, NSS, NTT)                                                \
   hipLaunchKernelGGL((k_apply_hm<T, PP, NSS, NTT>), dim3(nblk), dim3(NTT), 0, \
@@ -581,7 +591,9 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
 #define LAUNCHP(PP, NTT)                                                     \
   do {                                                                       \
     if (ns == 3) LAUNCHM(PP, 3, NTT);                                        \
-    else LAUNCHM(PP, 2, NTT);                                                \
+    else if (ns == 2) LAUNCHM(PP, 2, NTT);                                   \
+    else if constexpr (sizeof(T) == 4) LAUNCHM(PP, 1, NTT);                  \
+    else OFM_REQUIRE(false, OFM_E_INVALID, "H X form is FP32 only");         \
   } while (0)
   // the classes of multistep_class
   if (cls == 1) LAUNCHP(1, H2T);
