@@ -288,11 +288,12 @@ __global__ __launch_bounds__(WG) void k_apply_h(
 #define OFM_H2_THREADS 512
 #endif
 constexpr int H2T = OFM_H2_THREADS;   // threads of a multi-step workgroup
-// Planes of 1025..2048 points run with 2 points per thread on 2 * H2T
-// threads in FP64 and with 3..4 points per thread on H2T threads in FP32:
-// on the amorphous workload (boxes of 24..40 points per axis) the FP64
-// fragment stage measured 1386 against 1440 ms with the wide workgroups and
-// the FP32 one 519 against 585 ms with the narrow ones.
+// Planes of 1025..2048 points run with 2 points per thread on 3 H2T / 2
+// (up to 1536 points) or 2 H2T threads in FP64 and with 3..4 points per
+// thread on H2T threads in FP32: on the amorphous workload (boxes of 24..40
+// points per axis) the FP64 fragment stage measured 1386 against 1440 ms
+// with the wide workgroups and the FP32 one 519 against 585 ms with the
+// narrow ones; the 3 H2T / 2 class then took it from 1035 to 938 ms.
 constexpr bool wide_wg(int elem_bytes) { return elem_bytes == 8; }
 
 // LDS planes of the multi-step kernel: rows of nx + 2 values whose first two
@@ -364,10 +365,13 @@ __global__ __launch_bounds__(NT) __attribute__((
   constexpr int SP = PPT * NT;
   constexpr int CAP = hm_cap(SP, sizeof(T));
   // V at the planes of the NS stages: a register window of planes
-  // t - 2(NS-1) .. t, or (FP64, three steps, where the window would not fit
-  // the 128 registers of the occupancy these launches keep) V(t) alone with
-  // the other stages' planes read again from L2 at every plane
-  constexpr bool VRELOAD = NS == 3 && sizeof(T) == 8;
+  // t - 2(NS-1) .. t, or (FP64, three steps, 512 or 1024 threads, where the
+  // window would not fit the 128 registers of the occupancy these launches
+  // keep) V(t) alone with the other stages' planes read again from L2 at
+  // every plane.  At 768 threads (three waves per SIMD, up to 168
+  // registers) the window fits, and that class ran 1.2x faster per point
+  // than the 1024-thread one with the reloads.
+  constexpr bool VRELOAD = NS == 3 && sizeof(T) == 8 && NT % 512 == 0;
   constexpr int NV = VRELOAD ? 1 : 2 * (NS - 1) + 1;
   const int t0 = xcd_tile(blockIdx.x, nblk_pad);
   if (t0 >= ntiles) return;
@@ -554,14 +558,14 @@ bool multistep_eligible(int elem_bytes, const FragDev& d) {
 
 // launch class of the multi-step kernel for a box (0: not taken): the first
 // whose plane (SP points) and padded LDS plane (hm_cap) hold the box's.  The
-// classes are (points per thread, threads): 1: (1, H2T), 2: (2, H2T), and
-// 3: (2, 2 H2T) with wide workgroups, else 3: (3, H2T) and 4: (4, H2T)
+// classes hold planes of up to cl H2T points, cl = 1..4, as (points per
+// thread, threads) 1: (1, H2T), 2: (2, H2T), and with wide workgroups
+// 3: (2, 3 H2T / 2) and 4: (2, 2 H2T), else 3: (3, H2T) and 4: (4, H2T)
 int multistep_class(int elem_bytes, const FragDev& d) {
   const int plane = d.dims[0] * d.dims[1];
   const int padded = hm_padded(d.dims[0], d.dims[1]);
-  const int ncls = wide_wg(elem_bytes) ? 3 : 4;
-  for (int cl = 1; cl <= ncls; ++cl) {
-    const int sp = (wide_wg(elem_bytes) && cl == 3) ? 4 * H2T : cl * H2T;
+  for (int cl = 1; cl <= 4; ++cl) {
+    const int sp = cl * H2T;
     if (plane <= sp && padded <= hm_cap(sp, elem_bytes)) return cl;
   }
   return 0;
@@ -598,7 +602,8 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
   // the classes of multistep_class
   if (cls == 1) LAUNCHP(1, H2T);
   else if (cls == 2) LAUNCHP(2, H2T);
-  else if (wide_wg(sizeof(T)) && cls == 3) LAUNCHP(2, 2 * H2T);
+  else if (wide_wg(sizeof(T)) && cls == 3) LAUNCHP(2, 3 * H2T / 2);
+  else if (wide_wg(sizeof(T)) && cls == 4) LAUNCHP(2, 2 * H2T);
   else if (!wide_wg(sizeof(T)) && cls == 3) LAUNCHP(3, H2T);
   else if (!wide_wg(sizeof(T)) && cls == 4) LAUNCHP(4, H2T);
   else OFM_REQUIRE(false, OFM_E_INVALID, "unknown multi-step launch class");

@@ -571,8 +571,8 @@ def test_multistep_bit_identical(ctx, tiny0, case):
     """Three (the default) or two filter steps per launch give the same bits
     as one step per launch (eigenvalues, iteration counts, states), graph on
     and off; planes of 144 to 2208 points: every FP64 launch class of the
-    multi-step kernel (144, 900 and 1200 points) beside a plane over its
-    limit of 2048 points (strips) in one sweep."""
+    multi-step kernel (144, 900, 1200 and 1800 points) beside a plane over
+    its limit of 2048 points (strips) in one sweep."""
     if case == "tiny":
         s = tiny0
     elif case == "split":
@@ -580,9 +580,11 @@ def test_multistep_bit_identical(ctx, tiny0, case):
         shape = (60, 52, 12)
         V = -np.abs(rng.standard_normal(shape[::-1])) * 0.3
         s = box_system(shape, 0.5,
-                       [(0, 0, 0), (30, 20, 0), (10, 8, 4), (20, 20, 7)],
-                       [(48, 46, 3), (12, 12, 12), (40, 30, 4), (30, 30, 4)],
-                       [4, 5, 4, 3], V=V)
+                       [(0, 0, 0), (30, 20, 0), (10, 8, 4), (20, 20, 7),
+                        (0, 4, 8)],
+                       [(48, 46, 3), (12, 12, 12), (40, 30, 4), (30, 30, 4),
+                        (45, 40, 4)],
+                       [4, 5, 4, 3, 4], V=V)
     else:
         rng = np.random.default_rng(7)
         shape = (40, 34, 14)
