@@ -550,8 +550,8 @@ __global__ __launch_bounds__(NT) __attribute__((
 // boxes the multi-step kernel takes: planes that fit at most 4 points per
 // thread (a box runs in the launch of its own class of points per thread, so
 // only the large planes pay the larger register windows; on the amorphous
-// workload FP64 planes of 1025..1600 points ran 6% faster overall in the
-// 3- and 4-point classes than in one-step strips)
+// workload FP64 planes of 1025..1600 points ran 6% faster overall in
+// multi-step classes than in one-step strips)
 bool multistep_eligible(int elem_bytes, const FragDev& d) {
   return multistep_class(elem_bytes, d) > 0;
 }
@@ -600,13 +600,19 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
     else OFM_REQUIRE(false, OFM_E_INVALID, "H X form is FP32 only");         \
   } while (0)
   // the classes of multistep_class
-  if (cls == 1) LAUNCHP(1, H2T);
-  else if (cls == 2) LAUNCHP(2, H2T);
-  else if (wide_wg(sizeof(T)) && cls == 3) LAUNCHP(2, 3 * H2T / 2);
-  else if (wide_wg(sizeof(T)) && cls == 4) LAUNCHP(2, 2 * H2T);
-  else if (!wide_wg(sizeof(T)) && cls == 3) LAUNCHP(3, H2T);
-  else if (!wide_wg(sizeof(T)) && cls == 4) LAUNCHP(4, H2T);
-  else OFM_REQUIRE(false, OFM_E_INVALID, "unknown multi-step launch class");
+  OFM_REQUIRE(cls >= 1 && cls <= 4, OFM_E_INVALID,
+              "unknown multi-step launch class");
+  if (cls == 1) {
+    LAUNCHP(1, H2T);
+  } else if (cls == 2) {
+    LAUNCHP(2, H2T);
+  } else if constexpr (wide_wg(sizeof(T))) {
+    if (cls == 3) LAUNCHP(2, 3 * H2T / 2);
+    else LAUNCHP(2, 2 * H2T);
+  } else {
+    if (cls == 3) LAUNCHP(3, H2T);
+    else LAUNCHP(4, H2T);
+  }
 #undef LAUNCHP
 #undef LAUNCHM
   OFM_HIP(hipGetLastError());
