@@ -170,8 +170,8 @@ void free_frags(ofm_frags* f) {
                   f->d_hphi, f->d_tiles[0], f->d_tiles[1], f->d_tiles[2],
                   f->d_ftiles, f->d_tiles_nr[0], f->d_tiles_nr[1],
                   f->d_tiles_nr[2], f->d_vt[0][0], f->d_vt[0][1],
-                  f->d_vt[0][2], f->d_vt[0][3], f->d_vt[1][0], f->d_vt[1][1],
-                  f->d_vt[1][2], f->d_vt[1][3],
+                  f->d_vt[0][2], f->d_vt[0][3], f->d_vt[0][4], f->d_vt[1][0],
+                  f->d_vt[1][1], f->d_vt[1][2], f->d_vt[1][3], f->d_vt[1][4],
                   f->d_tiles_rest[0][0], f->d_tiles_rest[0][1],
                   f->d_tiles_rest[0][2], f->d_tiles_rest[1][0],
                   f->d_tiles_rest[1][1], f->d_tiles_rest[1][2],
@@ -301,7 +301,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
   // against 3.03 ms, the 2048-point planes holding one workgroup per CU)
   const bool hx_ms = sizeof(T) == 4 && cfg.fused >= 2 && f->n_vt_all[0] > 0;
   auto apply_plain = [&]() {
-    double cb[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0}, rb = 0, rp = 0;
+    double cb[k::NMSCLS] = {}, cp[k::NMSCLS] = {}, rb = 0, rp = 0;
     for (int j = 0; j < nf; ++j)
       if (act[j]) {
         const FragDev& d = f->host[j];
@@ -310,7 +310,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         (cls > 0 ? cp[cls - 1] : rp) += d.npts;
       }
     if (hx_ms)
-      for (int cl = 0; cl < 4; ++cl)
+      for (int cl = 0; cl < k::NMSCLS; ++cl)
         if (f->n_vt[0][cl] > 0)
           k::apply_hm<T>(c, f, X, HX, f->d_vt[0][cl], f->n_vt[0][cl], cl + 1,
                          1, f->d_active, 1, nullptr, nullptr, 0,
@@ -365,7 +365,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
     k::step_coefs_table<T>(s, f, cfg.degree, f->d_coef);
     // filter work: unlocked vectors of the active fragments, per class
     double snb = 0, snpt = 0, mnb = 0, mnpt = 0, rnb = 0, rnpt = 0;
-    double cnb[4] = {0, 0, 0, 0}, cnpt[4] = {0, 0, 0, 0};
+    double cnb[k::NMSCLS] = {}, cnpt[k::NMSCLS] = {};
     for (int j = 0; j < nf; ++j)
       if (act[j] && fsh[j].lock < f->host[j].bw) {
         const FragDev& d = f->host[j];
@@ -400,7 +400,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
         // the filtered block ends in X
         // each class follows its own plan (the classes hold different
         // fragments, so their launches are independent)
-        for (int cl = 0; cl < 4; ++cl) {
+        for (int cl = 0; cl < k::NMSCLS; ++cl) {
           if (f->n_vt[vset][cl] == 0) continue;
           T* in = X;
           T* pv = P;
@@ -467,7 +467,7 @@ ofm_status solve_impl(ofm_ctx* c, ofm_frags* f, const SolveCfg& cfg,
       double by = 0;
       int launches = 0;
       if (have_ms) {
-        for (int cl = 0; cl < 4; ++cl) {
+        for (int cl = 0; cl < k::NMSCLS; ++cl) {
           if (f->n_vt[vset][cl] == 0) continue;
           int steps_l = 0;
           for (const auto& [ns, count] : multistep_plan(cfg.degree, cfg.fused)) {
@@ -799,7 +799,7 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
                f->d_tiles_rest[1][v], f->n_tiles_rest[1][v]);
       }
       for (int set = 0; set < 2; ++set) {
-        std::vector<int2> vt[4];
+        std::vector<int2> vt[k::NMSCLS];
         for (int j = 0; j < n_frag; ++j) {
           const FragDev& d = f->host[j];
           if (set == 1 && k::resident_eligible((int)w, d)) continue;
@@ -808,7 +808,7 @@ ofm_status ofm_build_fragments(ofm_ctx* c, const ofm_grid* grid,
           for (int v = 0; v < d.bw; ++v) vt[cls - 1].push_back(make_int2(j, v));
         }
         f->n_vt_all[set] = 0;
-        for (int cl = 0; cl < 4; ++cl) {
+        for (int cl = 0; cl < k::NMSCLS; ++cl) {
           upload(vt[cl], f->d_vt[set][cl], f->n_vt[set][cl]);
           f->n_vt_all[set] += f->n_vt[set][cl];
         }

@@ -162,9 +162,9 @@ struct ofm_frags {
   // launch per class, so a small plane does not run on a workgroup sized
   // for the largest), and the strip tiles of the remaining boxes per stencil
   // variant
-  int2* d_vt[2][4] = {{nullptr, nullptr, nullptr, nullptr},
-                      {nullptr, nullptr, nullptr, nullptr}};
-  int n_vt[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  int2* d_vt[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr},
+                      {nullptr, nullptr, nullptr, nullptr, nullptr}};
+  int n_vt[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
   int n_vt_all[2] = {0, 0};
   // width classes of the Gram and rotation kernels: one launch per class,
   // so a narrow block does not run with the registers of the widest one
@@ -342,7 +342,10 @@ std::vector<int2> stencil_tiles(const ofm_frags* f, int elem_bytes,
                                 const std::vector<char>* keep = nullptr);
 // two or three Chebyshev steps per launch for boxes whose plane fits one
 // workgroup
-// launch class (1..4) of the multi-step kernel for a box (0: not taken)
+// launch classes of the multi-step kernel (ofm_frags::d_vt holds one tile
+// list per class)
+constexpr int NMSCLS = 5;
+// launch class (1..NMSCLS) of the multi-step kernel for a box (0: not taken)
 int multistep_class(int elem_bytes, const FragDev& d);
 bool multistep_eligible(int elem_bytes, const FragDev& d);
 template <typename T>

@@ -547,8 +547,8 @@ __global__ __launch_bounds__(NT) __attribute__((
   for (; t < t_end; ++t) iter(t, std::integral_constant<bool, false>{});
 }
 
-// boxes the multi-step kernel takes: planes that fit at most 4 points per
-// thread (a box runs in the launch of its own class of points per thread, so
+// boxes the multi-step kernel takes: planes that fit one of its launch
+// classes (a box runs in the launch of its own class of points per thread, so
 // only the large planes pay the larger register windows; on the amorphous
 // workload FP64 planes of 1025..1600 points ran 6% faster overall in
 // multi-step classes than in one-step strips)
@@ -560,12 +560,14 @@ bool multistep_eligible(int elem_bytes, const FragDev& d) {
 // whose plane (SP points) and padded LDS plane (hm_cap) hold the box's.  The
 // classes hold planes of up to cl H2T points, cl = 1..4, as (points per
 // thread, threads) 1: (1, H2T), 2: (2, H2T), and with wide workgroups
-// 3: (2, 3 H2T / 2) and 4: (2, 2 H2T), else 3: (3, H2T) and 4: (4, H2T)
+// 3: (2, 3 H2T / 2) and 4: (2, 2 H2T), else 3: (3, H2T) and 4: (4, H2T);
+// FP32 adds class 5, planes of up to 6 H2T points as (3, 2 H2T)
 int multistep_class(int elem_bytes, const FragDev& d) {
   const int plane = d.dims[0] * d.dims[1];
   const int padded = hm_padded(d.dims[0], d.dims[1]);
-  for (int cl = 1; cl <= 4; ++cl) {
-    const int sp = cl * H2T;
+  const int ncls = wide_wg(elem_bytes) ? 4 : 5;
+  for (int cl = 1; cl <= ncls; ++cl) {
+    const int sp = cl == 5 ? 6 * H2T : cl * H2T;
     if (plane <= sp && padded <= hm_cap(sp, elem_bytes)) return cl;
   }
   return 0;
@@ -600,7 +602,7 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
     else OFM_REQUIRE(false, OFM_E_INVALID, "H X form is FP32 only");         \
   } while (0)
   // the classes of multistep_class
-  OFM_REQUIRE(cls >= 1 && cls <= 4, OFM_E_INVALID,
+  OFM_REQUIRE(cls >= 1 && cls <= (wide_wg(sizeof(T)) ? 4 : 5), OFM_E_INVALID,
               "unknown multi-step launch class");
   if (cls == 1) {
     LAUNCHP(1, H2T);
@@ -611,7 +613,8 @@ void apply_hm(ofm_ctx* c, const ofm_frags* f, T* IN, T* PV, const int2* tiles,
     else LAUNCHP(2, 2 * H2T);
   } else {
     if (cls == 3) LAUNCHP(3, H2T);
-    else LAUNCHP(4, H2T);
+    else if (cls == 4) LAUNCHP(4, H2T);
+    else LAUNCHP(3, 2 * H2T);
   }
 #undef LAUNCHP
 #undef LAUNCHM

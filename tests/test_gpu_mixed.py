@@ -204,18 +204,19 @@ def _wells_system(seed):
 
 
 def test_multistep_plane_classes_bit_identical(mctx):
-    """FP32 boxes in all four plane classes of the multi-step kernel (1 to 4
+    """FP32 boxes in all five plane classes of the multi-step kernel (1 to 4
     points per thread of a 512-thread workgroup: planes of 480, 900, 1280
-    and 1920 points), on-chip filter off: three steps per launch (the
+    and 1920 points; 3 points per thread of a 1024-thread workgroup: 2100
+    points), on-chip filter off: three steps per launch (the
     default) and two, one launch per class, give the same bits as
     one step per launch, graph on and off, and the eigenvalues match the
     oracle's."""
     rng = np.random.default_rng(12)
     shape = (52, 44, 8)
     V = -np.abs(rng.standard_normal(shape[::-1])) * 0.3
-    lo = [(0, 0, 0), (10, 8, 1), (4, 6, 2), (2, 2, 3)]
-    dims = [(24, 20, 5), (30, 30, 5), (40, 32, 4), (48, 40, 3)]
-    st = [3, 4, 3, 4]
+    lo = [(0, 0, 0), (10, 8, 1), (4, 6, 2), (2, 2, 3), (1, 1, 4)]
+    dims = [(24, 20, 5), (30, 30, 5), (40, 32, 4), (48, 40, 3), (50, 42, 3)]
+    st = [3, 4, 3, 4, 3]
     s = box_system(shape, 0.5, lo, dims, st, V=V)
     out = []
     for fused, graph in ((0, 0), (-1, 0), (0, -1), (2, 0), (2, -1)):
@@ -224,7 +225,7 @@ def test_multistep_plane_classes_bit_identical(mctx):
         status, eps, it, cv = P.ofm_solve_fragments(
             mctx, f, fused=fused, use_graph=graph, resident=-1)
         assert status == 0 and cv.all()
-        out.append((eps, it, [P.ofm_get_states(f, j)[1] for j in range(4)]))
+        out.append((eps, it, [P.ofm_get_states(f, j)[1] for j in range(5)]))
         f.close()
     for eps, it, phis in out[1:]:
         assert np.array_equal(eps, out[0][0])
