@@ -118,8 +118,9 @@ typedef struct {
                             as the per-step launches) [on]; -1: per-step
                             launches for every box                         */
   int fused;             /* filter steps per launch for the boxes whose xy
-                            plane holds at most 2048 points (larger planes
-                            run one step per launch): 0 or 3: three
+                            plane holds at most 2048 points in FP64, 3072
+                            in the mixed forms (larger planes run one step
+                            per launch): 0 or 3: three
                             [default]; 2: two; -1 (or 1): one.  Same bits in
                             every case.                                    */
 } ofm_solve_opts;
