@@ -290,7 +290,8 @@ __global__ __launch_bounds__(WG) void k_apply_h(
 constexpr int H2T = OFM_H2_THREADS;   // threads of a multi-step workgroup
 // Planes of 1025..2048 points run with 2 points per thread on 3 H2T / 2
 // (up to 1536 points) or 2 H2T threads in FP64 and with 3..4 points per
-// thread on H2T threads in FP32: on the amorphous workload (boxes of 24..40
+// thread on H2T threads in FP32 (which also takes planes of 2049..3072
+// points, 3 per thread on 2 H2T threads): on the amorphous workload (boxes of 24..40
 // points per axis) the FP64 fragment stage measured 1386 against 1440 ms
 // with the wide workgroups and the FP32 one 519 against 585 ms with the
 // narrow ones; the 3 H2T / 2 class then took it from 1035 to 938 ms.
