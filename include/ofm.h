@@ -107,10 +107,11 @@ typedef struct {
                             as a HIP graph and replayed every iteration [on];
                             -1: launch its kernels one by one               */
   int autotune;          /* >= 0: time the variants of the strip stencil
-                            (boxes outside the multi-step classes, and H X
-                            in FP64) on the first filter sweep, once per
-                            (precision, largest box plane) and context, and
-                            keep the fastest [on]; -1: use the fixed
+                            on the strips of the first filter sweep (boxes
+                            outside the multi-step classes; none: nothing
+                            is timed), once per (precision, largest box
+                            plane) and context, and keep the fastest, which
+                            also runs H X in FP64 [on]; -1: use the fixed
                             default variant                                */
   int resident;          /* >= 0: in the mixed form, boxes of at most 32
                             points per axis run the whole filter in one
